@@ -1,0 +1,158 @@
+"""Python access to the plain FP64 CPU oracle (oracle/sccs_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg may import this package; the product path
+(``paper_1208_0945_amd``) never does.  It shares no code with the HIP
+library; only the seeded input generator feeds both.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsccs_oracle.so")
+SRC_PATH = os.path.join(HERE, "sccs_oracle.c")
+
+PRIOR_NONE, PRIOR_NORMAL, PRIOR_LAPLACE = 0, 1, 2
+CRIT_FIXED, CRIT_REL_LOGPOST, CRIT_ABS_DXBETA = 0, 1, 2
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, no fast-math)."""
+    if force or not os.path.exists(LIB_PATH):
+        cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall", "-Wextra",
+               "-o", LIB_PATH, SRC_PATH, "-lm"]
+        subprocess.run(cmd, check=True)
+    return LIB_PATH
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("n_patients", ctypes.c_int32), ("n_rows", ctypes.c_int64),
+                ("n_cols", ctypes.c_int32), ("patient_ptr", ctypes.c_void_p),
+                ("offset", ctypes.c_void_p), ("count", ctypes.c_void_p),
+                ("col_ptr", ctypes.c_void_p), ("row_idx", ctypes.c_void_p),
+                ("weight", ctypes.c_void_p)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("loglik", ctypes.c_double), ("logpost", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build(force=True)
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER(_Problem)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.ora_loglik.argtypes = [P, ctypes.c_void_p, dp]
+        L.ora_loglik.restype = ctypes.c_int
+        L.ora_log_prior.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_void_p]
+        L.ora_log_prior.restype = ctypes.c_double
+        L.ora_grad_hess.argtypes = [P, ctypes.c_void_p, ctypes.c_int32, dp, dp]
+        L.ora_grad_hess.restype = ctypes.c_int
+        L.ora_newton_step.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double]
+        L.ora_newton_step.restype = ctypes.c_double
+        L.ora_trust_clamp.argtypes = [ctypes.c_double, dp]
+        L.ora_trust_clamp.restype = ctypes.c_double
+        L.ora_ccd.argtypes = [P, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                              ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                              ctypes.POINTER(_Result), ctypes.c_void_p, ctypes.c_void_p]
+        L.ora_ccd.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+class OracleProblem:
+    """Keeps contiguous copies of the arrays alive for the C structure."""
+
+    def __init__(self, prob, weight: Optional[np.ndarray] = None):
+        self.patient_ptr = _c(prob.patient_ptr, np.int64)
+        self.offset = _c(prob.offset, np.int32)
+        self.count = _c(prob.count, np.int32)
+        self.col_ptr = _c(prob.col_ptr, np.int64)
+        self.row_idx = _c(prob.row_idx, np.int32)
+        self.weight = None if weight is None else _c(weight, np.int32)
+        self.J = int(prob.n_cols)
+        self.s = _Problem(int(prob.n_patients), int(self.patient_ptr[-1]), self.J,
+                          self.patient_ptr.ctypes.data, self.offset.ctypes.data,
+                          self.count.ctypes.data, self.col_ptr.ctypes.data,
+                          self.row_idx.ctypes.data,
+                          None if self.weight is None else self.weight.ctypes.data)
+
+
+def _prob(prob, weight=None) -> OracleProblem:
+    return prob if isinstance(prob, OracleProblem) else OracleProblem(prob, weight)
+
+
+def loglik(prob, beta, weight=None) -> float:
+    P = _prob(prob, weight)
+    b = _c(beta, np.float64)
+    out = ctypes.c_double()
+    rc = lib().ora_loglik(ctypes.byref(P.s), b.ctypes.data, ctypes.byref(out))
+    if rc:
+        raise ValueError(f"ora_loglik failed ({rc})")
+    return out.value
+
+
+def log_prior(kind: int, var: float, beta) -> float:
+    b = _c(beta, np.float64)
+    return lib().ora_log_prior(kind, var, len(b), b.ctypes.data)
+
+
+def grad_hess(prob, beta, j: int, weight=None) -> Tuple[float, float]:
+    P = _prob(prob, weight)
+    b = _c(beta, np.float64)
+    g, h = ctypes.c_double(), ctypes.c_double()
+    rc = lib().ora_grad_hess(ctypes.byref(P.s), b.ctypes.data, int(j), ctypes.byref(g), ctypes.byref(h))
+    if rc:
+        raise ValueError(f"ora_grad_hess failed ({rc})")
+    return g.value, h.value
+
+
+def newton_step(kind: int, var: float, beta_j: float, g: float, h: float) -> float:
+    return lib().ora_newton_step(kind, var, beta_j, g, h)
+
+
+def trust_clamp(dv: float, trust: float) -> Tuple[float, float]:
+    t = ctypes.c_double(trust)
+    d = lib().ora_trust_clamp(dv, ctypes.byref(t))
+    return d, t.value
+
+
+def ccd(prob, prior_kind: int, var: float, max_sweeps: int, criterion: int = CRIT_FIXED,
+        tol: float = 0.0, beta0=None, trust0=None, weight=None, want_trace: bool = False):
+    """Run Algorithm 1.  Returns dict(beta, trust, sweeps, converged, loglik,
+    logpost, trace[sweeps, J, 3] or None, logpost_trace[sweeps])."""
+    P = _prob(prob, weight)
+    J = P.J
+    beta = np.zeros(J) if beta0 is None else _c(beta0, np.float64).copy()
+    trust = np.ones(J) if trust0 is None else _c(trust0, np.float64).copy()
+    res = _Result()
+    trace = np.zeros((max(max_sweeps, 1), J, 3)) if want_trace else None
+    lpt = np.zeros(max(max_sweeps, 1))
+    rc = lib().ora_ccd(ctypes.byref(P.s), int(prior_kind), float(var), beta.ctypes.data,
+                       trust.ctypes.data, int(max_sweeps), int(criterion), float(tol),
+                       ctypes.byref(res), None if trace is None else trace.ctypes.data,
+                       lpt.ctypes.data)
+    if rc:
+        raise ValueError(f"ora_ccd failed ({rc})")
+    n = res.sweeps
+    return {"beta": beta, "trust": trust, "sweeps": n, "converged": bool(res.converged),
+            "loglik": res.loglik, "logpost": res.logpost,
+            "trace": None if trace is None else trace[:n], "logpost_trace": lpt[:n]}

@@ -1,0 +1,250 @@
+"""Seeded synthetic era data for the self-controlled case series (SCCS) model.
+
+This module only draws data.  It holds none of the fitting arithmetic (no
+likelihood, gradient, Newton step or derived per-patient/per-column totals):
+both the CPU oracle and the GPU path compute everything they need from the
+raw arrays returned here.
+
+Data model (Section 2.1 of the paper): patient i has K_i exposure eras; era k
+has a length l_ik in days, a binary drug-exposure vector x_ik over J drugs and
+an adverse-event count y_ik ~ Poisson(l_ik * exp(x_ik' beta) * rate).  The
+cases-only design keeps only patients with n_i = sum_k y_ik >= 1; a patient
+whose draw gives n_i = 0 has its count vector redrawn (eras, lengths and
+exposures kept) until n_i >= 1.
+
+The paper's claims data are proprietary; these generators stand in for them
+with the shapes of the workloads the method is measured on:
+
+* eras per patient  K_i = 1 + Poisson(mu)            (mu = 4 tiny, 9 otherwise)
+* era length        l_ik ~ UniformInt[1, 365]
+* exposure          x_ikj ~ Bernoulli(p_j), independent per era and drug;
+                    p_j = p0 * rank_j^(-1.1) (Zipf popularity) with the ranks
+                    given by a seeded permutation of the drug ids
+* true effects      a few nonzero beta_j ~ Normal(0, var)
+* counts            rate 1e-3 per day
+
+Layout of a ``Problem`` (all numpy, C-contiguous):
+
+* ``patient_ptr`` int64 [N+1]: eras of patient i are rows
+  patient_ptr[i] .. patient_ptr[i+1]-1 (rows grouped by patient).
+* ``offset`` int32 [K]: l_ik; ``count`` int32 [K]: y_ik.
+* ``col_ptr`` int64 [J+1], ``row_idx`` int32 [nnz]: X in compressed column
+  storage; rows strictly ascending inside each column; values are all one.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+ROOT_SEED = 12080945
+RATE_PER_DAY = 1e-3
+
+
+@dataclasses.dataclass
+class Problem:
+    name: str
+    n_patients: int
+    patient_ptr: np.ndarray
+    offset: np.ndarray
+    count: np.ndarray
+    n_cols: int
+    col_ptr: np.ndarray
+    row_idx: np.ndarray
+    beta_true: np.ndarray
+    seed_info: str = ""
+
+    @property
+    def n_rows(self) -> int:
+        return int(self.patient_ptr[-1])
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col_ptr[-1])
+
+    def column(self, j: int) -> np.ndarray:
+        return self.row_idx[self.col_ptr[j]:self.col_ptr[j + 1]]
+
+    def summary(self) -> dict:
+        c = np.diff(self.col_ptr)
+        return {"name": self.name, "N": self.n_patients, "K": self.n_rows,
+                "J": self.n_cols, "nnz": self.nnz,
+                "col_nnz_min": int(c.min()) if len(c) else 0,
+                "col_nnz_median": float(np.median(c)) if len(c) else 0.0,
+                "col_nnz_max": int(c.max()) if len(c) else 0}
+
+
+def _rng(*path: int) -> np.random.Generator:
+    """Child generator addressed by a path of integers under the root seed."""
+    ss = np.random.SeedSequence(ROOT_SEED, spawn_key=tuple(int(p) for p in path))
+    return np.random.Generator(np.random.PCG64(ss))
+
+
+def _bernoulli_rows(rng: np.random.Generator, n_rows: int, p: float) -> np.ndarray:
+    """Sorted row indices of an independent Bernoulli(p) column of length n_rows.
+
+    Drawn as a geometric-gap process, which gives exactly the distribution of
+    n_rows independent Bernoulli draws while costing O(nnz) draws.
+    """
+    if p <= 0.0 or n_rows == 0:
+        return np.zeros(0, dtype=np.int32)
+    if p >= 1.0:
+        return np.arange(n_rows, dtype=np.int32)
+    chunks = []
+    pos = -1
+    expect = n_rows * p
+    batch = int(expect + 6.0 * math.sqrt(expect + 1.0) + 64)
+    while True:
+        gaps = rng.geometric(p, size=batch).astype(np.int64)
+        rows = pos + np.cumsum(gaps)
+        if rows[-1] >= n_rows:
+            chunks.append(rows[rows < n_rows])
+            break
+        chunks.append(rows)
+        pos = int(rows[-1])
+        batch = max(64, int((n_rows - pos) * p * 1.2) + 64)
+    return np.concatenate(chunks).astype(np.int32)
+
+
+def make_problem(name: str, n_patients: int, n_cols: int, era_mean: float,
+                 incl_prob: Sequence[float], beta_true: np.ndarray,
+                 seed_path: Sequence[int], rate: float = RATE_PER_DAY,
+                 max_len: int = 365) -> Problem:
+    """Draw one cases-only SCCS problem.
+
+    incl_prob[j] is the per-era exposure probability of drug j; beta_true[j]
+    its true log relative incidence.
+    """
+    incl_prob = np.asarray(incl_prob, dtype=np.float64)
+    beta_true = np.asarray(beta_true, dtype=np.float64)
+    assert incl_prob.shape == (n_cols,) and beta_true.shape == (n_cols,)
+    rng_eras = _rng(*seed_path, 0)
+    k_i = 1 + rng_eras.poisson(era_mean, size=n_patients).astype(np.int64)
+    patient_ptr = np.zeros(n_patients + 1, dtype=np.int64)
+    np.cumsum(k_i, out=patient_ptr[1:])
+    n_rows = int(patient_ptr[-1])
+    offset = rng_eras.integers(1, max_len + 1, size=n_rows, dtype=np.int32)
+
+    cols: List[np.ndarray] = []
+    for j in range(n_cols):
+        cols.append(_bernoulli_rows(_rng(*seed_path, 1, j), n_rows, float(incl_prob[j])))
+    col_ptr = np.zeros(n_cols + 1, dtype=np.int64)
+    np.cumsum([len(c) for c in cols], out=col_ptr[1:])
+    row_idx = np.concatenate(cols).astype(np.int32) if cols else np.zeros(0, np.int32)
+
+    # true linear predictor per era (data model only)
+    eta_true = np.zeros(n_rows, dtype=np.float64)
+    for j in np.flatnonzero(beta_true):
+        eta_true[cols[j]] += beta_true[j]
+    mean = offset.astype(np.float64) * np.exp(eta_true) * rate
+
+    rng_y = _rng(*seed_path, 2)
+    count = rng_y.poisson(mean).astype(np.int32)
+    pid = np.repeat(np.arange(n_patients, dtype=np.int64), k_i)
+    # redraw the count vector of every patient without an event
+    todo = np.flatnonzero(np.bincount(pid, weights=count, minlength=n_patients) == 0)
+    rounds = 0
+    while todo.size:
+        rows = _rows_of(patient_ptr, todo)
+        count[rows] = rng_y.poisson(mean[rows]).astype(np.int32)
+        tot = np.bincount(np.searchsorted(patient_ptr, rows, side="right") - 1,
+                          weights=count[rows], minlength=n_patients)[todo]
+        todo = todo[tot == 0]
+        rounds += 1
+        if rounds > 1_000_000:
+            raise RuntimeError("count redraw did not terminate")
+    return Problem(name=name, n_patients=n_patients, patient_ptr=patient_ptr,
+                   offset=offset, count=count, n_cols=n_cols, col_ptr=col_ptr,
+                   row_idx=row_idx, beta_true=beta_true,
+                   seed_info=f"root={ROOT_SEED} path={tuple(seed_path)}")
+
+
+def _rows_of(patient_ptr: np.ndarray, pats: np.ndarray) -> np.ndarray:
+    lo = patient_ptr[pats]
+    hi = patient_ptr[pats + 1]
+    lens = hi - lo
+    starts = np.repeat(lo - np.concatenate([[0], np.cumsum(lens)[:-1]]), lens)
+    return starts + np.arange(int(lens.sum()))
+
+
+def zipf_probs(n_cols: int, p0: float, exponent: float, rng: np.random.Generator) -> np.ndarray:
+    """Per-drug exposure probability p0 * rank^-exponent with permuted ranks."""
+    ranks = rng.permutation(n_cols) + 1
+    return p0 * ranks.astype(np.float64) ** (-exponent)
+
+
+def sparse_beta(n_cols: int, n_nonzero: int, var: float, rng: np.random.Generator) -> np.ndarray:
+    beta = np.zeros(n_cols, dtype=np.float64)
+    idx = rng.choice(n_cols, size=min(n_nonzero, n_cols), replace=False)
+    beta[idx] = rng.normal(0.0, math.sqrt(var), size=len(idx))
+    return beta
+
+
+# ---------------------------------------------------------------- workloads
+
+def tiny(n_patients: int = 1000, n_cols: int = 20, seed: int = 0) -> Problem:
+    """1,000 patients, 1+Poisson(4) eras, J=20 drugs at p=0.05, 5 true effects
+    ~N(0, 0.5) (variance)."""
+    rng = _rng(1, seed, 9)
+    beta = sparse_beta(n_cols, 5, 0.5, rng)
+    return make_problem("tiny", n_patients, n_cols, 4.0, np.full(n_cols, 0.05), beta,
+                        seed_path=(1, seed))
+
+
+def zipf_problem(name: str, n_patients: int, n_cols: int, p0: float, seed_path: Sequence[int],
+                 era_mean: float = 9.0, n_effects: int = 50, effect_var: float = 0.7,
+                 exponent: float = 1.1) -> Problem:
+    rng = _rng(*seed_path, 9)
+    probs = zipf_probs(n_cols, p0, exponent, rng)
+    beta = sparse_beta(n_cols, n_effects, effect_var, rng)
+    return make_problem(name, n_patients, n_cols, era_mean, probs, beta, seed_path=seed_path)
+
+
+def mid(n_patients: int = 2_000_000, n_cols: int = 2000, seed: int = 0) -> Problem:
+    """2M patients, ~20M eras (1+Poisson(9)), J=2000 Zipf(1.1) drugs with
+    p_j = 0.1 rank^-1.1, 50 true effects ~N(0, 0.7)."""
+    return zipf_problem("mid", n_patients, n_cols, 0.1, seed_path=(2, seed))
+
+
+def full(n_patients: int = 10_000_000, n_cols: int = 4000, seed: int = 0) -> Problem:
+    """10M patients, ~100M eras, J=4000 Zipf drugs with p_j = 0.482 rank^-1.1."""
+    return zipf_problem("full", n_patients, n_cols, 0.482, seed_path=(3, seed))
+
+
+def outcome_sizes(n_fits: int = 64, lo: float = 1e4, hi: float = 2e6, seed: int = 0) -> np.ndarray:
+    rng = _rng(4, seed, 99)
+    return np.round(np.exp(rng.uniform(math.log(lo), math.log(hi), size=n_fits))).astype(np.int64)
+
+
+def batched_outcomes(n_fits: int = 64, n_cols: int = 1000, seed: int = 0,
+                     sizes: Optional[Sequence[int]] = None) -> List[Problem]:
+    """Independent outcomes over one shared J-drug vocabulary (shared Zipf
+    popularity), patient counts log-uniform 10k..2M."""
+    if sizes is None:
+        sizes = outcome_sizes(n_fits, seed=seed)
+    rng = _rng(4, seed, 9)
+    probs = zipf_probs(n_cols, 0.1, 1.1, rng)
+    out = []
+    for f, n in enumerate(sizes):
+        beta = sparse_beta(n_cols, 50, 0.7, _rng(4, seed, 10, f))
+        out.append(make_problem(f"outcome{f}", int(n), n_cols, 9.0, probs, beta,
+                                seed_path=(4, seed, f)))
+    return out
+
+
+def cv_folds(n_patients: int, n_folds: int = 10, seed: int = 0) -> np.ndarray:
+    """Patient-level fold id (0..n_folds-1), a seeded balanced assignment."""
+    rng = _rng(5, seed)
+    return (rng.permutation(n_patients) % n_folds).astype(np.int32)
+
+
+def prior_grid(n: int = 16, lo: float = 1e-3, hi: float = 10.0) -> np.ndarray:
+    """Prior variances log-spaced from lo to hi, ascending."""
+    return np.logspace(math.log10(lo), math.log10(hi), n)
+
+
+def random_beta(n_cols: int, scale: float, seed: int) -> np.ndarray:
+    """A seeded coefficient vector for evaluating derivatives away from zero."""
+    return _rng(7, seed).normal(0.0, scale, size=n_cols)
