@@ -1,0 +1,167 @@
+"""Benchmark: CCD sweeps/s of the BSCCS MAP fit on one MI355X.
+
+Workload (the configuration the headline metric is quoted on): 2M patients,
+~20M eras (1 + Poisson(9) per patient), J = 2000 binary drugs with Zipf(1.1)
+popularity, Laplace prior lambda = 1 (variance 2), FP64.  One step = one full
+cyclic sweep over all 2000 coordinates (gather + segmented sums, device-wide
+reduction, Newton/trust-region step, sparse update), one persistent launch.
+
+Prints one JSON line.  Besides the required fields it carries:
+  roofline      algorithmic HBM bytes of the sweep kernel / its mean launch
+                time (HIP events on the launch stream) against 8 TB/s;
+  cpu_baseline  the FP64 C oracle timed on the host on a bounded sample;
+  mixed         the mixed-precision form on the same workload: sweeps/s and
+                its relative beta error against the FP64 GPU path.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "CCD sweeps/sec + HBM GB/s at 20M eras, J=2000; mixed vs FP64 at 1e-6 rel"
+HBM_PEAK_GBS = 8000.0
+
+
+def column_stats(prob):
+    """Nonzeros c_j and distinct patients p_j of every column."""
+    c = np.diff(prob.col_ptr)
+    era_pid = np.repeat(np.arange(prob.n_patients, dtype=np.int64), np.diff(prob.patient_ptr))
+    pid = era_pid[prob.row_idx]
+    col = np.repeat(np.arange(prob.n_cols), c)
+    new = np.ones(len(pid), dtype=bool)
+    new[1:] = (pid[1:] != pid[:-1]) | (col[1:] != col[:-1])
+    p = np.bincount(col[new], minlength=prob.n_cols)
+    return c.astype(np.int64), p.astype(np.int64)
+
+
+def bytes_per_sweep(c, p, active, precision):
+    """Algorithmic bytes of one sweep.  Phase A, every coordinate: per nonzero
+    the (row, patient) index pair (8 B) and the gathered weight (8 B FP64,
+    4 B mixed); per patient segment den_i and omega_i n_i (16 B).  Phase B,
+    coordinates with a nonzero step: the new weight per nonzero (8 / 4 B)
+    and the new den_i per segment (8 B)."""
+    wb = 8 if precision == 0 else 4
+    a = (8 + wb) * c.sum() + 16 * p.sum()
+    b = wb * c[active].sum() + 8 * p[active].sum()
+    return float(a + b)
+
+
+def run_form(sccs, prob, precision, steps, warmup, c, p):
+    import torch
+    h = sccs.Handle(prob, precision=precision)
+    h.set_prior(sccs.PRIOR_LAPLACE, 2.0)
+    beta_prev, _ = h.get_beta()
+    for _ in range(warmup):
+        h.sweep(1)
+    beta_prev, _ = h.get_beta()
+    torch.cuda.synchronize()
+    kernel_ms = []
+    algo_bytes = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        h.sweep(1)
+        kernel_ms.append(h.last_kernel_ms())
+        beta, _ = h.get_beta()
+        algo_bytes.append(bytes_per_sweep(c, p, beta != beta_prev, precision))
+        beta_prev = beta
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    beta, _ = h.get_beta()
+    h.close()
+    return {"wall_s": wall, "kernel_ms": kernel_ms, "bytes": algo_bytes, "beta": beta}
+
+
+def cpu_baseline(prob, sweeps):
+    import oracle
+    oracle.build(force=False)
+    P = oracle.OracleProblem(prob)
+    t0 = time.perf_counter()
+    oracle.ccd(P, oracle.PRIOR_LAPLACE, 2.0, 0)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.ccd(P, oracle.PRIOR_LAPLACE, 2.0, sweeps)
+    t = time.perf_counter() - t0
+    per = max(t - t_setup, 1e-9) / sweeps
+    return {"value": 1.0 / per, "unit": "sweeps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sweeps} CCD sweeps of the same workload by the single-threaded FP64 C oracle "
+                      f"(-O2), one-time setup ({t_setup:.2f} s) subtracted; {t:.1f} s total"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--patients", type=int, default=2_000_000)
+    ap.add_argument("--cols", type=int, default=2000)
+    ap.add_argument("--cpu-sweeps", type=int, default=4)
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(patient sharding is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    from paper_1208_0945_amd import sccs, synth
+
+    t0 = time.perf_counter()
+    prob = synth.mid(n_patients=args.patients, n_cols=args.cols)
+    print(f"[bench] generated {prob.summary()} in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    c, p = column_stats(prob)
+
+    fp = run_form(sccs, prob, 0, args.steps, args.warmup, c, p)
+    print(f"[bench] fp64 done: {args.steps / fp['wall_s']:.1f} sweeps/s", file=sys.stderr, flush=True)
+    ms = float(np.mean(fp["kernel_ms"]))
+    achieved = float(np.mean(fp["bytes"])) / (ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": args.steps / fp["wall_s"],
+        "unit": "sweeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": fp["wall_s"] * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"mid SCCS: {prob.n_patients} patients, {prob.n_rows} eras, J={prob.n_cols} "
+                               f"Zipf(1.1) drugs, {prob.nnz} nonzeros, Laplace lambda=1, FP64, one sweep per step",
+                   "n_patients": prob.n_patients, "n_eras": prob.n_rows, "n_cols": prob.n_cols,
+                   "nnz": prob.nnz, "prior": "laplace", "variance": 2.0, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_ccd<double>", "kernel_ms_mean": ms,
+                     "algo_bytes_per_launch": float(np.mean(fp["bytes"]))},
+    }
+    if not args.no_mixed:
+        mx = run_form(sccs, prob, 1, args.steps, args.warmup, c, p)
+        err = float(np.max(np.abs(mx["beta"] - fp["beta"])) / max(np.max(np.abs(fp["beta"])), 1e-300))
+        mms = float(np.mean(mx["kernel_ms"]))
+        out["mixed"] = {"value": args.steps / mx["wall_s"], "unit": "sweeps/s",
+                        "kernel_ms_mean": mms,
+                        "achieved_GBs": float(np.mean(mx["bytes"])) / (mms * 1e-3) / 1e9,
+                        "rel_err_vs_fp64_gpu": err,
+                        "sweeps_compared": args.steps + args.warmup}
+        print(f"[bench] mixed done: {out['mixed']['value']:.1f} sweeps/s, rel err {err:.2e}",
+              file=sys.stderr, flush=True)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_sweeps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

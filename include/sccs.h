@@ -1,0 +1,182 @@
+/*
+ * libsccs -- cyclic coordinate descent (CCD) for the MAP fit of the Bayesian
+ * self-controlled case series (BSCCS) model on one AMD Instinct MI355X
+ * (gfx950), after Suchard, Simpson, Zorych, Ryan and Madigan, "Massive
+ * parallelization of serial inference algorithms for a complex generalized
+ * linear model".
+ *
+ * Model (Section 2.1).  Patient i = 0..N-1 has eras k (rows of X, grouped by
+ * patient) with length l_k >= 0 days, event count y_k >= 0 and a binary
+ * exposure row x_k over J drugs.  With n_i = sum_k y_ik the conditional
+ * log-likelihood is Eq. 2,
+ *     L(beta) = sum_i omega_i [ sum_k y_ik x_ik'beta - n_i log sum_k l_ik exp(x_ik'beta) ],
+ * where omega_i >= 0 is an optional integer patient weight (1 by default;
+ * cross-validation folds use 0/1, the bootstrap uses resample counts).
+ * The prior (Eq. 3) is Normal(0, var) or Laplace(0, var) on every beta_j,
+ * var being the variance (Laplace rate lambda = sqrt(2/var)).  The library
+ * maximises P(beta) = L(beta) + log p(beta) by Algorithm 1: coordinates
+ * j = 0..J-1 are visited in order each sweep; each visit computes the
+ * one-dimensional gradient and Hessian g_j, h_j (Eqs. 7-9), takes one
+ * prior-regularised Newton step (Eq. 4) bounded by an adaptable trust region
+ * (after Genkin et al. 2007: step clipped to +-trust_j, then
+ * trust_j <- max(2|step|, trust_j/2), trust_j = 1 at the start of a fit), and
+ * if the step is nonzero updates exp(X beta) on the column's rows and the
+ * per-patient sums M[L x exp(X beta)] (Section 2.4, Steps 1-4).
+ *
+ * Laplace step rules at a kink (the paper leaves them open): beta_j > 0 uses
+ * the branch with -lambda and stops at zero if the step would cross it;
+ * beta_j < 0 symmetrically; beta_j = 0 moves only if |g_j| > lambda
+ * (strict).  Without curvature (h_j = 0) no step is taken.
+ *
+ * Conventions.
+ *  - Status: 0 = SCCS_OK; positive = informational; negative = error.  No
+ *    C++ exception crosses this interface.  On error, sccs_last_error()
+ *    describes it.  Validation finishes before any state changes.
+ *  - Host pointers unless stated.  Input arrays are borrowed for the duration
+ *    of the call only; the library copies what it needs.
+ *  - A handle is not thread-safe; separate handles are independent.  All
+ *    device work of a handle is ordered on its stream (options.stream, a
+ *    hipStream_t; NULL = the null stream).  Calls that return host data
+ *    synchronise that stream.
+ *  - Device memory comes from a caller-owned workspace (sccs_query_workspace
+ *    gives its size; the caller allocates it, for example as a torch uint8
+ *    tensor, and keeps it alive until sccs_destroy) or, if the workspace
+ *    pointer is NULL, from hipMalloc inside sccs_create (freed by
+ *    sccs_destroy).
+ */
+#ifndef SCCS_H
+#define SCCS_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sccs_status;
+#define SCCS_OK 0
+#define SCCS_NOT_CONVERGED 1       /* sccs_fit stopped at max_sweeps */
+#define SCCS_ERR_INVALID_ARG (-1)  /* bad argument or malformed problem */
+#define SCCS_ERR_WORKSPACE (-2)    /* workspace too small or misaligned */
+#define SCCS_ERR_HIP (-3)          /* a HIP runtime call failed */
+#define SCCS_ERR_STATE (-4)        /* call not valid in the current state */
+#define SCCS_ERR_NUMERIC (-5)      /* non-finite g, h or beta; last finite beta kept */
+#define SCCS_ERR_SYNC (-6)         /* the device-wide reduction did not complete */
+
+enum { SCCS_PRIOR_NONE = 0, SCCS_PRIOR_NORMAL = 1, SCCS_PRIOR_LAPLACE = 2 };
+enum { SCCS_PREC_FP64 = 0, SCCS_PREC_MIXED = 1 };
+enum { SCCS_CRIT_FIXED = 0, SCCS_CRIT_REL_LOGPOST = 1, SCCS_CRIT_ABS_DXBETA = 2 };
+
+typedef struct sccs_handle sccs_handle;
+
+/*
+ * One SCCS problem in the matrix form of Section 2.3 (Eq. 5-6), host memory.
+ *   patient_ptr [N+1] int64: rows of patient i are [ptr[i], ptr[i+1]);
+ *                 ptr[0] = 0, non-decreasing, ptr[N] = n_rows.
+ *   offset      [K] int32: era length l_k >= 0.
+ *   count       [K] int32: events y_k >= 0; y_k > 0 requires l_k > 0.
+ *   col_ptr     [J+1] int64: X in compressed column storage (values all 1).
+ *   row_idx     [nnz] int32: rows of each column, strictly increasing.
+ *   patient_weight [N] int32 >= 0, or NULL for all ones.
+ * Limits: N, K, J >= 1; K < 2^31; nnz < 2^31.  Patients without events
+ * (n_i = 0) are accepted and carry no information (cases-only design).
+ */
+typedef struct sccs_problem {
+  int32_t n_patients;
+  int64_t n_rows;
+  int32_t n_cols;
+  int64_t nnz;
+  const int64_t* patient_ptr;
+  const int32_t* offset;
+  const int32_t* count;
+  const int64_t* col_ptr;
+  const int32_t* row_idx;
+  const int32_t* patient_weight;
+} sccs_problem;
+
+typedef struct sccs_options {
+  int32_t precision;       /* SCCS_PREC_FP64 or SCCS_PREC_MIXED (FP32 exp(X beta) and row products) */
+  int32_t n_workgroups;    /* persistent workgroups; 0 = one per compute unit */
+  int32_t refresh_period;  /* sweeps between exact recomputation of w and den from beta;
+                              0 = never, -1 = default (0 for FP64, 1 for mixed) */
+  int32_t reserved;        /* must be 0 */
+  void* stream;            /* hipStream_t */
+} sccs_options;
+
+typedef struct sccs_fit_opts {
+  int32_t criterion;   /* SCCS_CRIT_* */
+  int32_t max_sweeps;  /* >= 1 */
+  double tol;          /* REL_LOGPOST: |P_t - P_{t-1}| < tol |P_t|;
+                          ABS_DXBETA: sum_k |eta_k^t - eta_k^{t-1}| < tol (Section 2.2 uses 5e-4) */
+} sccs_fit_opts;
+
+typedef struct sccs_fit_result {
+  int32_t sweeps;      /* sweeps run by this call */
+  int32_t converged;   /* 1 if the criterion was met */
+  double loglik;       /* L(beta) at exit (Eq. 2, from the maintained state) */
+  double logpost;      /* L + log p(beta), constants dropped */
+} sccs_fit_result;
+
+/* Options with defaults: FP64, one workgroup per CU, default refresh, NULL stream. */
+void sccs_default_options(sccs_options* opts);
+
+/* Device bytes sccs_create needs for this problem and these options.
+ * Validates the problem (same checks as sccs_create). */
+sccs_status sccs_query_workspace(const sccs_problem* prob, const sccs_options* opts, size_t* bytes);
+
+/* Validate and repack the problem into device memory and set beta = 0,
+ * trust = 1, no prior.  workspace: device pointer of >= the queried bytes,
+ * 256-byte aligned, owned by the caller; NULL makes the library allocate.
+ * Setup (Algorithm 1, initialisation): n_i, Y'X_j and the initial
+ * w = L, den = M L are computed on the device. */
+sccs_status sccs_create(const sccs_problem* prob, const sccs_options* opts, void* workspace,
+                        size_t workspace_bytes, sccs_handle** out);
+
+/* Release host-side memory (and the workspace if the library allocated it).
+ * NULL-safe.  Synchronises the stream first. */
+sccs_status sccs_destroy(sccs_handle* h);
+
+/* Prior of Eq. 3: kind SCCS_PRIOR_NONE / _NORMAL / _LAPLACE; variance > 0
+ * (ignored for NONE).  Changes nothing else (beta and trust are kept). */
+sccs_status sccs_set_prior(sccs_handle* h, int32_t kind, double variance);
+
+/* Warm start: copy beta [J] (host) and trust [J] (host, or NULL for all
+ * ones), then recompute w = L x exp(X beta) and den = M w exactly. */
+sccs_status sccs_set_beta(sccs_handle* h, const double* beta, const double* trust);
+
+/* Copy the current beta [J] and, if trust is not NULL, the trust bounds [J]
+ * to host memory.  Synchronises. */
+sccs_status sccs_get_beta(sccs_handle* h, double* beta, double* trust);
+
+/* Run exactly n_sweeps cycles over j = 0..J-1 (Algorithm 1 without the stop
+ * test) in one device launch.  If logpost is not NULL, the log posterior
+ * after the last sweep is written there (synchronises).  Needs a prior. */
+sccs_status sccs_sweep(sccs_handle* h, int32_t n_sweeps, double* logpost);
+
+/* Run cycles until the criterion holds or max_sweeps cycles ran, in one
+ * device launch; the stop test is evaluated on the device after every
+ * sweep.  Returns SCCS_OK if converged, SCCS_NOT_CONVERGED otherwise (or an
+ * error).  Synchronises. */
+sccs_status sccs_fit(sccs_handle* h, const sccs_fit_opts* fo, sccs_fit_result* res);
+
+/* Likelihood-only g_j and h_j (Eqs. 7-9) at the current beta, from the
+ * maintained state (diagnostic; no step is taken).  Synchronises. */
+sccs_status sccs_grad_hess(sccs_handle* h, int32_t j, double* g, double* hess);
+
+/* L(beta) and L + log p(beta) at the current beta from the maintained
+ * state.  Synchronises. */
+sccs_status sccs_objective(sccs_handle* h, double* loglik, double* logpost);
+
+/* Device-side timing of the most recent sccs_sweep / sccs_fit launch in
+ * milliseconds (HIP events on the handle's stream around the persistent
+ * kernel alone).  Synchronises. */
+sccs_status sccs_last_kernel_ms(sccs_handle* h, double* ms);
+
+/* Human-readable description of the last error on this handle (or of the
+ * last failed create when h is NULL).  Never NULL. */
+const char* sccs_last_error(const sccs_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,490 @@
+// C ABI of libsccs (include/sccs.h): handle management, workspace carving,
+// setup and the cooperative launches of the persistent CCD kernel.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sccs.h"
+#include "sccs_device.hpp"
+#include "sccs_kernels.hpp"
+#include "sccs_layout.hpp"
+
+using namespace sccs;
+
+struct sccs_handle {
+  std::string err;
+  int32_t N = 0, J = 0, G = 0, T = 0, prec = 0;
+  int64_t K = 0, nnz = 0;
+  hipStream_t stream = nullptr;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool owns_ws = false;
+  bool failed = false;
+  int32_t prior_kind = -1;
+  double var = 1.0;
+  int32_t refresh_period = 0;
+  size_t lds_bytes = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool timed = false;
+  KArgs args{};
+  // device pointers kept for setup and copies
+  int64_t* d_col_ptr = nullptr;
+  int32_t* d_count = nullptr;
+  int32_t* d_weight = nullptr;
+  Ctrl* h_ctrl = nullptr;  // pinned host mirror of the control block
+};
+
+static thread_local std::string g_create_error;
+
+namespace {
+
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base((char*)b) {}
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+struct Plan {
+  uint2* rp;
+  int32_t *tile_start, *own, *pb, *pptr, *era_ptr, *era_col, *offset, *count, *weight;
+  int64_t* col_ptr;
+  void* w;
+  double2* pat;
+  double *ytx, *beta, *trust;
+  uint64_t *slots, *oslots;
+  Ctrl* ctrl;
+};
+
+size_t carve(void* base, const Layout& L, int prec, bool has_weight, Plan& P) {
+  Carver c(base);
+  P.rp = c.take<uint2>((size_t)L.nnz + 1);
+  P.tile_start = c.take<int32_t>((size_t)L.n_tiles() + 1);
+  P.own = c.take<int32_t>((size_t)L.J * (L.G + 1));
+  P.pb = c.take<int32_t>((size_t)L.G + 1);
+  P.pptr = c.take<int32_t>((size_t)L.N + 1);
+  P.era_ptr = c.take<int32_t>((size_t)L.K + 1);
+  P.era_col = c.take<int32_t>((size_t)L.nnz + 1);
+  P.offset = c.take<int32_t>((size_t)L.K);
+  P.count = c.take<int32_t>((size_t)L.K);
+  P.weight = has_weight ? c.take<int32_t>((size_t)L.N) : nullptr;
+  P.col_ptr = c.take<int64_t>((size_t)L.J + 1);
+  P.w = prec == SCCS_PREC_FP64 ? (void*)c.take<double>((size_t)L.K) : (void*)c.take<float>((size_t)L.K);
+  P.pat = c.take<double2>((size_t)L.N);
+  P.ytx = c.take<double>((size_t)L.J);
+  P.beta = c.take<double>((size_t)L.J);
+  P.trust = c.take<double>((size_t)L.J);
+  P.slots = c.take<uint64_t>((size_t)2 * L.G * 2);
+  P.oslots = c.take<uint64_t>((size_t)2 * L.G * 4);
+  P.ctrl = c.take<Ctrl>(1);
+  return (c.off + 255) & ~(size_t)255;
+}
+
+sccs_status check_options(const sccs_options* o, std::string& err) {
+  if (!o) return SCCS_OK;
+  if (o->precision != SCCS_PREC_FP64 && o->precision != SCCS_PREC_MIXED) {
+    err = "options.precision must be SCCS_PREC_FP64 or SCCS_PREC_MIXED";
+    return SCCS_ERR_INVALID_ARG;
+  }
+  if (o->n_workgroups < 0 || o->n_workgroups > 64 * kMaxSlotsPerLane) {
+    err = "options.n_workgroups must be in [0, 256]";
+    return SCCS_ERR_INVALID_ARG;
+  }
+  if (o->refresh_period < -1) {
+    err = "options.refresh_period must be >= -1";
+    return SCCS_ERR_INVALID_ARG;
+  }
+  if (o->reserved != 0) {
+    err = "options.reserved must be 0";
+    return SCCS_ERR_INVALID_ARG;
+  }
+  return SCCS_OK;
+}
+
+sccs_status pick_workgroups(const sccs_options* o, int32_t& G, std::string& err) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) { err = "hipGetDevice failed"; return SCCS_ERR_HIP; }
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) {
+    err = "cannot query the compute-unit count";
+    return SCCS_ERR_HIP;
+  }
+  G = (o && o->n_workgroups > 0) ? o->n_workgroups : cus;
+  if (G > 64 * kMaxSlotsPerLane) G = 64 * kMaxSlotsPerLane;
+  if (G > cus) { err = "n_workgroups exceeds the number of compute units"; return SCCS_ERR_INVALID_ARG; }
+  return SCCS_OK;
+}
+
+const void* ccd_kernel(int prec, int mode) {
+  if (mode == kModeSweep)
+    return prec == SCCS_PREC_FP64 ? (const void*)k_ccd<double> : (const void*)k_ccd<float>;
+  return prec == SCCS_PREC_FP64 ? (const void*)k_diag<double> : (const void*)k_diag<float>;
+}
+
+#define HIPCHK(h, call)                                                        \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess) {                                                    \
+      (h)->err = std::string(#call) + ": " + hipGetErrorString(e_);            \
+      return SCCS_ERR_HIP;                                                     \
+    }                                                                          \
+  } while (0)
+
+sccs_status usable(sccs_handle* h) {
+  if (!h) return SCCS_ERR_INVALID_ARG;
+  if (h->failed) {
+    h->err = "handle unusable after a failed device reduction; destroy it";
+    return SCCS_ERR_STATE;
+  }
+  return SCCS_OK;
+}
+
+sccs_status read_ctrl(sccs_handle* h) {
+  HIPCHK(h, hipMemcpyAsync(h->h_ctrl, h->args.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (h->h_ctrl->status == SCCS_ERR_SYNC) {
+    h->failed = true;
+    h->err = "device-wide reduction timed out (workgroups not co-resident?)";
+    return SCCS_ERR_SYNC;
+  }
+  if (h->h_ctrl->status == SCCS_ERR_NUMERIC) {
+    h->err = "non-finite gradient, Hessian or coefficient; last finite beta kept";
+    return SCCS_ERR_NUMERIC;
+  }
+  return SCCS_OK;
+}
+
+sccs_status launch(sccs_handle* h, int mode, int n_sweeps, int criterion, double tol, int want_obj, int diag_j) {
+  KArgs a = h->args;
+  a.prior_kind = h->prior_kind < 0 ? SCCS_PRIOR_NONE : h->prior_kind;
+  a.var = h->var;
+  a.lambda = (a.prior_kind == SCCS_PRIOR_LAPLACE) ? std::sqrt(2.0 / h->var) : 0.0;
+  a.n_sweeps = n_sweeps;
+  a.criterion = criterion;
+  a.tol = tol;
+  a.refresh_period = h->refresh_period;
+  a.want_objective = want_obj;
+  a.mode = mode;
+  a.diag_j = diag_j;
+  void* params[] = {&a};
+  HIPCHK(h, hipMemsetAsync(&h->args.ctrl->status, 0, sizeof(int32_t), h->stream));
+  HIPCHK(h, hipEventRecord(h->ev0, h->stream));
+  HIPCHK(h, hipLaunchCooperativeKernel(ccd_kernel(h->prec, mode), dim3(h->G), dim3(kBlock), params,
+                                        (unsigned)h->lds_bytes, h->stream));
+  HIPCHK(h, hipEventRecord(h->ev1, h->stream));
+  h->timed = true;
+  return SCCS_OK;
+}
+
+sccs_status refresh_all(sccs_handle* h) {
+  KArgs a = h->args;
+  int grid = (h->N + 255) / 256;
+  if (grid > 4096) grid = 4096;
+  if (h->prec == SCCS_PREC_FP64)
+    hipLaunchKernelGGL(k_refresh<double>, dim3(grid), dim3(256), 0, h->stream, a);
+  else
+    hipLaunchKernelGGL(k_refresh<float>, dim3(grid), dim3(256), 0, h->stream, a);
+  HIPCHK(h, hipGetLastError());
+  // the maintained state is exact again
+  HIPCHK(h, hipMemsetAsync(&h->args.ctrl->since_refresh, 0, sizeof(int32_t), h->stream));
+  return SCCS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void sccs_default_options(sccs_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->precision = SCCS_PREC_FP64;
+  o->n_workgroups = 0;
+  o->refresh_period = -1;
+  o->stream = nullptr;
+}
+
+sccs_status sccs_query_workspace(const sccs_problem* prob, const sccs_options* opts, size_t* bytes) {
+  std::string err;
+  if (!bytes) { g_create_error = "bytes is NULL"; return SCCS_ERR_INVALID_ARG; }
+  sccs_status st = check_options(opts, err);
+  if (st == SCCS_OK) st = validate_problem(prob, err);
+  int32_t G = 0;
+  if (st == SCCS_OK) st = pick_workgroups(opts, G, err);
+  if (st != SCCS_OK) { g_create_error = err; return st; }
+  if (prob->n_cols > kMaxJ) { g_create_error = "n_cols exceeds 6144"; return SCCS_ERR_INVALID_ARG; }
+  Layout L;
+  try {
+    build_layout(prob, G, L);
+  } catch (const std::bad_alloc&) {
+    g_create_error = "host out of memory while building the layout";
+    return SCCS_ERR_INVALID_ARG;
+  }
+  Plan P;
+  *bytes = carve(nullptr, L, opts ? opts->precision : SCCS_PREC_FP64, prob->patient_weight != nullptr, P);
+  return SCCS_OK;
+}
+
+sccs_status sccs_create(const sccs_problem* prob, const sccs_options* opts_in, void* workspace,
+                        size_t workspace_bytes, sccs_handle** out) {
+  if (!out) { g_create_error = "out is NULL"; return SCCS_ERR_INVALID_ARG; }
+  *out = nullptr;
+  sccs_options opts;
+  sccs_default_options(&opts);
+  if (opts_in) opts = *opts_in;
+  std::string err;
+  sccs_status st = check_options(&opts, err);
+  if (st == SCCS_OK) st = validate_problem(prob, err);
+  int32_t G = 0;
+  if (st == SCCS_OK) st = pick_workgroups(&opts, G, err);
+  if (st == SCCS_OK && prob->n_cols > kMaxJ) { err = "n_cols exceeds 6144"; st = SCCS_ERR_INVALID_ARG; }
+  if (st != SCCS_OK) { g_create_error = err; return st; }
+  if (workspace && ((uintptr_t)workspace & 255u)) {
+    g_create_error = "workspace must be 256-byte aligned";
+    return SCCS_ERR_WORKSPACE;
+  }
+
+  sccs_handle* h = new (std::nothrow) sccs_handle();
+  if (!h) { g_create_error = "out of host memory"; return SCCS_ERR_INVALID_ARG; }
+  Layout L;
+  try {
+    build_layout(prob, G, L);
+  } catch (const std::bad_alloc&) {
+    delete h;
+    g_create_error = "host out of memory while building the layout";
+    return SCCS_ERR_INVALID_ARG;
+  }
+  const bool has_w = prob->patient_weight != nullptr;
+  Plan P;
+  size_t need = carve(nullptr, L, opts.precision, has_w, P);
+  if (workspace && workspace_bytes < need) {
+    delete h;
+    g_create_error = "workspace too small";
+    return SCCS_ERR_WORKSPACE;
+  }
+  h->N = L.N; h->J = L.J; h->G = G; h->T = L.n_tiles(); h->K = L.K; h->nnz = L.nnz;
+  h->prec = opts.precision;
+  h->stream = (hipStream_t)opts.stream;
+  h->refresh_period = opts.refresh_period >= 0 ? opts.refresh_period : (opts.precision == SCCS_PREC_MIXED ? 1 : 0);
+  h->lds_bytes = (size_t)3 * L.J * sizeof(double);
+
+  auto bail = [&](const std::string& m, sccs_status code) {
+    g_create_error = m;
+    if (h->owns_ws && h->ws) (void)hipFree(h->ws);
+    if (h->ev0) (void)hipEventDestroy(h->ev0);
+    if (h->ev1) (void)hipEventDestroy(h->ev1);
+    if (h->h_ctrl) (void)hipHostFree(h->h_ctrl);
+    delete h;
+    return code;
+  };
+
+  if (workspace) {
+    h->ws = workspace;
+    h->ws_bytes = workspace_bytes;
+  } else {
+    if (hipMalloc(&h->ws, need) != hipSuccess) return bail("hipMalloc of the workspace failed", SCCS_ERR_HIP);
+    h->owns_ws = true;
+    h->ws_bytes = need;
+  }
+  if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess)
+    return bail("hipEventCreate failed", SCCS_ERR_HIP);
+  if (hipHostMalloc((void**)&h->h_ctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess)
+    return bail("hipHostMalloc failed", SCCS_ERR_HIP);
+
+  // occupancy: every workgroup must be resident at once
+  for (int mode : {kModeSweep, kModeObjective}) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ccd_kernel(h->prec, mode), kBlock, h->lds_bytes) !=
+            hipSuccess ||
+        per_cu < 1)
+      return bail("the persistent kernel cannot be resident (registers or LDS)", SCCS_ERR_HIP);
+  }
+
+  carve(h->ws, L, opts.precision, has_w, P);
+  hipStream_t s = h->stream;
+  auto cp = [&](void* dst, const void* src, size_t bytes) {
+    return bytes == 0 || hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s) == hipSuccess;
+  };
+  bool ok = cp(P.rp, L.rp.data(), L.rp.size() * 4) && cp(P.tile_start, L.tile_start.data(), L.tile_start.size() * 4) &&
+            cp(P.own, L.own.data(), L.own.size() * 4) && cp(P.pb, L.pb.data(), L.pb.size() * 4) &&
+            cp(P.pptr, L.pptr.data(), L.pptr.size() * 4) && cp(P.era_ptr, L.era_ptr.data(), L.era_ptr.size() * 4) &&
+            cp(P.era_col, L.era_col.data(), L.era_col.size() * 4) &&
+            cp(P.offset, prob->offset, (size_t)L.K * 4) && cp(P.count, prob->count, (size_t)L.K * 4) &&
+            cp(P.col_ptr, prob->col_ptr, ((size_t)L.J + 1) * 8) &&
+            (!has_w || cp(P.weight, prob->patient_weight, (size_t)L.N * 4));
+  if (!ok) return bail("copy of the problem to the device failed", SCCS_ERR_HIP);
+  std::vector<double> ones((size_t)L.J, 1.0);
+  ok = hipMemsetAsync(P.beta, 0, (size_t)L.J * 8, s) == hipSuccess && cp(P.trust, ones.data(), (size_t)L.J * 8) &&
+       hipMemsetAsync(P.ctrl, 0, sizeof(Ctrl), s) == hipSuccess;
+  if (!ok) return bail("state initialisation failed", SCCS_ERR_HIP);
+  // reduction slots start with the tag that reductions 0 and 1 do not expect
+  size_t nslot = (size_t)2 * G * 2, noslot = (size_t)2 * G * 4;
+  hipLaunchKernelGGL(k_fill_u64, dim3(16), dim3(256), 0, s, P.slots, nslot, kSign);
+  hipLaunchKernelGGL(k_fill_u64, dim3(16), dim3(256), 0, s, P.oslots, noslot, kSign);
+  int gp = (L.N + 255) / 256;
+  if (gp > 4096) gp = 4096;
+  hipLaunchKernelGGL(k_setup_patients, dim3(gp), dim3(256), 0, s, P.pptr, P.count, P.weight, P.pat, L.N);
+  int gj = L.J < 4096 ? L.J : 4096;
+  hipLaunchKernelGGL(k_setup_ytx, dim3(gj), dim3(256), 0, s, P.col_ptr, P.rp, P.count, P.weight, P.ytx, L.J);
+  if (hipGetLastError() != hipSuccess) return bail("setup kernel launch failed", SCCS_ERR_HIP);
+
+  KArgs& a = h->args;
+  a.rp = P.rp; a.tile_start = P.tile_start; a.own = P.own; a.pb = P.pb; a.pptr = P.pptr;
+  a.era_ptr = P.era_ptr; a.era_col = P.era_col; a.offset = P.offset; a.w = P.w; a.pat = P.pat;
+  a.ytx = P.ytx; a.beta = P.beta; a.trust = P.trust; a.slots = P.slots; a.oslots = P.oslots;
+  a.ctrl = P.ctrl; a.N = L.N; a.J = L.J; a.G = G;
+  h->d_col_ptr = P.col_ptr; h->d_count = P.count; h->d_weight = P.weight;
+  if (refresh_all(h) != SCCS_OK) return bail(h->err, SCCS_ERR_HIP);
+  if (hipStreamSynchronize(s) != hipSuccess) return bail("setup failed on the device", SCCS_ERR_HIP);
+  *out = h;
+  return SCCS_OK;
+}
+
+sccs_status sccs_destroy(sccs_handle* h) {
+  if (!h) return SCCS_OK;
+  (void)hipStreamSynchronize(h->stream);
+  if (h->owns_ws && h->ws) (void)hipFree(h->ws);
+  if (h->ev0) (void)hipEventDestroy(h->ev0);
+  if (h->ev1) (void)hipEventDestroy(h->ev1);
+  if (h->h_ctrl) (void)hipHostFree(h->h_ctrl);
+  delete h;
+  return SCCS_OK;
+}
+
+sccs_status sccs_set_prior(sccs_handle* h, int32_t kind, double variance) {
+  sccs_status st = usable(h);
+  if (st) return st;
+  if (kind != SCCS_PRIOR_NONE && kind != SCCS_PRIOR_NORMAL && kind != SCCS_PRIOR_LAPLACE) {
+    h->err = "unknown prior kind";
+    return SCCS_ERR_INVALID_ARG;
+  }
+  if (kind != SCCS_PRIOR_NONE && !(variance > 0.0 && std::isfinite(variance))) {
+    h->err = "prior variance must be positive and finite";
+    return SCCS_ERR_INVALID_ARG;
+  }
+  h->prior_kind = kind;
+  h->var = kind == SCCS_PRIOR_NONE ? 1.0 : variance;
+  return SCCS_OK;
+}
+
+sccs_status sccs_set_beta(sccs_handle* h, const double* beta, const double* trust) {
+  sccs_status st = usable(h);
+  if (st) return st;
+  if (!beta) { h->err = "beta is NULL"; return SCCS_ERR_INVALID_ARG; }
+  for (int32_t j = 0; j < h->J; ++j) {
+    if (!std::isfinite(beta[j]) || (trust && !(trust[j] > 0.0 && std::isfinite(trust[j])))) {
+      h->err = "beta must be finite and trust positive";
+      return SCCS_ERR_INVALID_ARG;
+    }
+  }
+  std::vector<double> ones;
+  if (!trust) { ones.assign((size_t)h->J, 1.0); trust = ones.data(); }
+  HIPCHK(h, hipMemcpyAsync(h->args.beta, beta, (size_t)h->J * 8, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync(h->args.trust, trust, (size_t)h->J * 8, hipMemcpyHostToDevice, h->stream));
+  if (refresh_all(h) != SCCS_OK) return SCCS_ERR_HIP;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return SCCS_OK;
+}
+
+sccs_status sccs_get_beta(sccs_handle* h, double* beta, double* trust) {
+  sccs_status st = usable(h);
+  if (st) return st;
+  if (!beta) { h->err = "beta is NULL"; return SCCS_ERR_INVALID_ARG; }
+  HIPCHK(h, hipMemcpyAsync(beta, h->args.beta, (size_t)h->J * 8, hipMemcpyDeviceToHost, h->stream));
+  if (trust) HIPCHK(h, hipMemcpyAsync(trust, h->args.trust, (size_t)h->J * 8, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return SCCS_OK;
+}
+
+sccs_status sccs_sweep(sccs_handle* h, int32_t n_sweeps, double* logpost) {
+  sccs_status st = usable(h);
+  if (st) return st;
+  if (h->prior_kind < 0) { h->err = "set a prior before sweeping"; return SCCS_ERR_STATE; }
+  if (n_sweeps < 0) { h->err = "n_sweeps must be >= 0"; return SCCS_ERR_INVALID_ARG; }
+  if (n_sweeps == 0 && !logpost) return SCCS_OK;
+  if (n_sweeps == 0) {
+    double L;
+    return sccs_objective(h, &L, logpost);
+  }
+  st = launch(h, kModeSweep, n_sweeps, SCCS_CRIT_FIXED, 0.0, logpost != nullptr, 0);
+  if (st) return st;
+  st = read_ctrl(h);
+  if (st) return st;
+  if (logpost) *logpost = h->h_ctrl->logpost;
+  return SCCS_OK;
+}
+
+sccs_status sccs_fit(sccs_handle* h, const sccs_fit_opts* fo, sccs_fit_result* res) {
+  sccs_status st = usable(h);
+  if (st) return st;
+  if (!fo || !res) { h->err = "fit options and result must not be NULL"; return SCCS_ERR_INVALID_ARG; }
+  if (h->prior_kind < 0) { h->err = "set a prior before fitting"; return SCCS_ERR_STATE; }
+  if (fo->max_sweeps < 1 || fo->criterion < SCCS_CRIT_FIXED || fo->criterion > SCCS_CRIT_ABS_DXBETA ||
+      !(fo->tol >= 0.0)) {
+    h->err = "invalid fit options";
+    return SCCS_ERR_INVALID_ARG;
+  }
+  st = launch(h, kModeSweep, fo->max_sweeps, fo->criterion, fo->tol, 1, 0);
+  if (st) return st;
+  st = read_ctrl(h);
+  if (st) return st;
+  res->sweeps = h->h_ctrl->sweeps;
+  res->converged = h->h_ctrl->converged;
+  res->loglik = h->h_ctrl->loglik;
+  res->logpost = h->h_ctrl->logpost;
+  if (fo->criterion == SCCS_CRIT_FIXED) return SCCS_OK;
+  return res->converged ? SCCS_OK : SCCS_NOT_CONVERGED;
+}
+
+sccs_status sccs_grad_hess(sccs_handle* h, int32_t j, double* g, double* hess) {
+  sccs_status st = usable(h);
+  if (st) return st;
+  if (j < 0 || j >= h->J || !g || !hess) { h->err = "invalid column or NULL output"; return SCCS_ERR_INVALID_ARG; }
+  st = launch(h, kModeGradHess, 0, SCCS_CRIT_FIXED, 0.0, 0, j);
+  if (st) return st;
+  st = read_ctrl(h);
+  if (st) return st;
+  *g = h->h_ctrl->g;
+  *hess = h->h_ctrl->h;
+  return SCCS_OK;
+}
+
+sccs_status sccs_objective(sccs_handle* h, double* loglik, double* logpost) {
+  sccs_status st = usable(h);
+  if (st) return st;
+  if (!loglik || !logpost) { h->err = "NULL output"; return SCCS_ERR_INVALID_ARG; }
+  st = launch(h, kModeObjective, 0, SCCS_CRIT_FIXED, 0.0, 1, 0);
+  if (st) return st;
+  st = read_ctrl(h);
+  if (st) return st;
+  *loglik = h->h_ctrl->loglik;
+  *logpost = h->h_ctrl->logpost;
+  return SCCS_OK;
+}
+
+sccs_status sccs_last_kernel_ms(sccs_handle* h, double* ms) {
+  if (!h || !ms) return SCCS_ERR_INVALID_ARG;
+  if (!h->timed) { h->err = "no kernel launched yet"; return SCCS_ERR_STATE; }
+  HIPCHK(h, hipEventSynchronize(h->ev1));
+  float f = 0.f;
+  HIPCHK(h, hipEventElapsedTime(&f, h->ev0, h->ev1));
+  *ms = f;
+  return SCCS_OK;
+}
+
+const char* sccs_last_error(const sccs_handle* h) {
+  if (!h) return g_create_error.c_str();
+  return h->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,50 @@
+// Host layout builder for libsccs: validation of an SCCS problem and the
+// index structures the persistent CCD kernel walks.
+//
+// Ownership.  The G persistent workgroups each own a contiguous patient range
+// [pb[b], pb[b+1]) (balanced by era count), for every column.  All state of a
+// patient (den_i) and of its eras (w_k) is only ever read or written by its
+// owner, so consecutive coordinates need no device-wide synchronisation
+// beyond the reduction of the two partial sums of Eqs. 7 and 9.
+//
+// Tiles.  The nonzeros of column j (compressed column storage, Section 2.4
+// "Representation in Memory") are cut into tiles of at most 64 entries -- one
+// wavefront -- that hold whole patient segments and never straddle an
+// ownership boundary.  A patient with more than 64 nonzeros in one column
+// gets a tile of its own (a "long" tile, walked in 64-wide chunks).  Tiles
+// cover [0, nnz) in order: tile t is [tile_start[t], tile_start[t+1]).
+// own[j*(G+1) + b] is the first tile of column j owned by workgroup b;
+// own[j*(G+1) + G] closes column j.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "sccs.h"
+
+namespace sccs {
+
+constexpr int kTile = 64;
+
+struct Layout {
+  int32_t N = 0, J = 0, G = 0;
+  int64_t K = 0, nnz = 0;
+  std::vector<int32_t> pb;          // [G+1] patient bounds per workgroup
+  std::vector<uint32_t> rp;         // [2*nnz] (row, patient) per nonzero, CSC order
+  std::vector<int32_t> tile_start;  // [T+1]
+  std::vector<int32_t> own;         // [J*(G+1)]
+  std::vector<int32_t> pptr;        // [N+1] patient_ptr as int32
+  std::vector<int32_t> era_ptr;     // [K+1] compressed row storage of X
+  std::vector<int32_t> era_col;     // [nnz]
+  int32_t n_tiles() const { return (int32_t)tile_start.size() - 1; }
+  int32_t max_tiles_per_wg = 0;     // over all (column, workgroup) pairs
+};
+
+// Check every rule stated for sccs_problem.  Returns SCCS_OK or
+// SCCS_ERR_INVALID_ARG with a message in err.
+sccs_status validate_problem(const sccs_problem* p, std::string& err);
+
+// Build the layout for G workgroups.  The problem must have been validated.
+void build_layout(const sccs_problem* p, int32_t G, Layout& L);
+
+}  // namespace sccs

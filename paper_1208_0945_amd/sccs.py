@@ -1,0 +1,235 @@
+"""Thin ctypes binding of libsccs (include/sccs.h).
+
+Argument marshalling only: every step of the CCD path runs in the HIP
+library.  PyTorch provides the device workspace and the stream.  The binding
+raises if ``libsccs.so`` has not been built -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsccs.so")
+
+OK, NOT_CONVERGED = 0, 1
+ERR_INVALID_ARG, ERR_WORKSPACE, ERR_HIP, ERR_STATE, ERR_NUMERIC, ERR_SYNC = -1, -2, -3, -4, -5, -6
+PRIOR_NONE, PRIOR_NORMAL, PRIOR_LAPLACE = 0, 1, 2
+PREC_FP64, PREC_MIXED = 0, 1
+CRIT_FIXED, CRIT_REL_LOGPOST, CRIT_ABS_DXBETA = 0, 1, 2
+
+EXPORTS = ("sccs_default_options", "sccs_query_workspace", "sccs_create", "sccs_destroy",
+           "sccs_set_prior", "sccs_set_beta", "sccs_get_beta", "sccs_sweep", "sccs_fit",
+           "sccs_grad_hess", "sccs_objective", "sccs_last_kernel_ms", "sccs_last_error")
+
+
+class SccsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libsccs status {status}: {msg}")
+        self.status = status
+
+
+class Problem_(ctypes.Structure):
+    _fields_ = [("n_patients", ctypes.c_int32), ("n_rows", ctypes.c_int64),
+                ("n_cols", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("patient_ptr", ctypes.c_void_p), ("offset", ctypes.c_void_p),
+                ("count", ctypes.c_void_p), ("col_ptr", ctypes.c_void_p),
+                ("row_idx", ctypes.c_void_p), ("patient_weight", ctypes.c_void_p)]
+
+
+class Options_(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("n_workgroups", ctypes.c_int32),
+                ("refresh_period", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
+
+
+class FitOpts_(ctypes.Structure):
+    _fields_ = [("criterion", ctypes.c_int32), ("max_sweeps", ctypes.c_int32), ("tol", ctypes.c_double)]
+
+
+class FitResult_(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("loglik", ctypes.c_double), ("logpost", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Open libsccs.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} not built; run python -m paper_1208_0945_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        H = ctypes.c_void_p
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.sccs_default_options.argtypes = [ctypes.POINTER(Options_)]
+        L.sccs_default_options.restype = None
+        L.sccs_query_workspace.argtypes = [ctypes.POINTER(Problem_), ctypes.POINTER(Options_),
+                                           ctypes.POINTER(ctypes.c_size_t)]
+        L.sccs_create.argtypes = [ctypes.POINTER(Problem_), ctypes.POINTER(Options_), ctypes.c_void_p,
+                                  ctypes.c_size_t, ctypes.POINTER(H)]
+        L.sccs_destroy.argtypes = [H]
+        L.sccs_set_prior.argtypes = [H, ctypes.c_int32, ctypes.c_double]
+        L.sccs_set_beta.argtypes = [H, ctypes.c_void_p, ctypes.c_void_p]
+        L.sccs_get_beta.argtypes = [H, ctypes.c_void_p, ctypes.c_void_p]
+        L.sccs_sweep.argtypes = [H, ctypes.c_int32, dp]
+        L.sccs_fit.argtypes = [H, ctypes.POINTER(FitOpts_), ctypes.POINTER(FitResult_)]
+        L.sccs_grad_hess.argtypes = [H, ctypes.c_int32, dp, dp]
+        L.sccs_objective.argtypes = [H, dp, dp]
+        L.sccs_last_kernel_ms.argtypes = [H, dp]
+        L.sccs_last_error.argtypes = [H]
+        L.sccs_last_error.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if name not in ("sccs_default_options", "sccs_last_error"):
+                getattr(L, name).restype = ctypes.c_int32
+        _lib = L
+    return _lib
+
+
+def _arr(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+class ProblemArrays:
+    """Contiguous host copies of a problem plus the C structure that points at them."""
+
+    def __init__(self, prob, weight: Optional[np.ndarray] = None):
+        self.patient_ptr = _arr(prob.patient_ptr, np.int64)
+        self.offset = _arr(prob.offset, np.int32)
+        self.count = _arr(prob.count, np.int32)
+        self.col_ptr = _arr(prob.col_ptr, np.int64)
+        self.row_idx = _arr(prob.row_idx, np.int32)
+        self.weight = None if weight is None else _arr(weight, np.int32)
+        self.n_cols = int(prob.n_cols)
+        self.s = Problem_(int(prob.n_patients), int(self.patient_ptr[-1]), self.n_cols,
+                          int(self.col_ptr[-1]), self.patient_ptr.ctypes.data, self.offset.ctypes.data,
+                          self.count.ctypes.data, self.col_ptr.ctypes.data,
+                          self.row_idx.ctypes.data if self.row_idx.size else None,
+                          None if self.weight is None else self.weight.ctypes.data)
+
+
+def options(precision: int = PREC_FP64, n_workgroups: int = 0, refresh_period: int = -1,
+            stream: Optional[int] = None) -> Options_:
+    o = Options_()
+    lib().sccs_default_options(ctypes.byref(o))
+    o.precision = precision
+    o.n_workgroups = n_workgroups
+    o.refresh_period = refresh_period
+    o.stream = stream
+    return o
+
+
+def query_workspace(prob, weight=None, **opt) -> int:
+    P = ProblemArrays(prob, weight)
+    o = options(**opt)
+    n = ctypes.c_size_t()
+    st = lib().sccs_query_workspace(ctypes.byref(P.s), ctypes.byref(o), ctypes.byref(n))
+    if st != OK:
+        raise SccsError(st, lib().sccs_last_error(None).decode())
+    return int(n.value)
+
+
+class Handle:
+    """One fit state on the GPU.  The workspace is a torch uint8 tensor kept
+    alive by this object; the stream defaults to torch's current stream."""
+
+    def __init__(self, prob, weight=None, precision: int = PREC_FP64, n_workgroups: int = 0,
+                 refresh_period: int = -1, stream=None, workspace: str = "torch"):
+        import torch
+        self.torch = torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        P = ProblemArrays(prob, weight)
+        o = options(precision, n_workgroups, refresh_period, stream.cuda_stream)
+        n = ctypes.c_size_t()
+        L = lib()
+        st = L.sccs_query_workspace(ctypes.byref(P.s), ctypes.byref(o), ctypes.byref(n))
+        if st != OK:
+            raise SccsError(st, L.sccs_last_error(None).decode())
+        self.workspace_bytes = int(n.value)
+        if workspace == "torch":
+            self.ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device="cuda")
+            ptr = self.ws.data_ptr()
+            ptr = (ptr + 255) & ~255
+        else:
+            self.ws, ptr = None, None
+        h = ctypes.c_void_p()
+        st = L.sccs_create(ctypes.byref(P.s), ctypes.byref(o), ptr, self.workspace_bytes, ctypes.byref(h))
+        if st != OK:
+            raise SccsError(st, L.sccs_last_error(None).decode())
+        self.h = h
+        self.J = P.n_cols
+        self.precision = precision
+
+    def _check(self, st: int, allow=(OK,)) -> int:
+        if st not in allow:
+            raise SccsError(st, lib().sccs_last_error(self.h).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sccs_destroy(self.h)
+            self.h = None
+            self.ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_prior(self, kind: int, variance: float = 1.0):
+        self._check(lib().sccs_set_prior(self.h, int(kind), float(variance)))
+
+    def set_beta(self, beta, trust=None):
+        b = _arr(beta, np.float64)
+        t = None if trust is None else _arr(trust, np.float64)
+        self._check(lib().sccs_set_beta(self.h, b.ctypes.data, None if t is None else t.ctypes.data))
+
+    def get_beta(self) -> Tuple[np.ndarray, np.ndarray]:
+        b = np.zeros(self.J)
+        t = np.zeros(self.J)
+        self._check(lib().sccs_get_beta(self.h, b.ctypes.data, t.ctypes.data))
+        return b, t
+
+    def sweep(self, n: int = 1, want_logpost: bool = False) -> Optional[float]:
+        if want_logpost:
+            lp = ctypes.c_double()
+            self._check(lib().sccs_sweep(self.h, int(n), ctypes.byref(lp)))
+            return lp.value
+        self._check(lib().sccs_sweep(self.h, int(n), None))
+        return None
+
+    def fit(self, criterion: int = CRIT_REL_LOGPOST, max_sweeps: int = 100, tol: float = 1e-8) -> dict:
+        fo = FitOpts_(int(criterion), int(max_sweeps), float(tol))
+        r = FitResult_()
+        st = self._check(lib().sccs_fit(self.h, ctypes.byref(fo), ctypes.byref(r)), allow=(OK, NOT_CONVERGED))
+        return {"status": st, "sweeps": r.sweeps, "converged": bool(r.converged),
+                "loglik": r.loglik, "logpost": r.logpost}
+
+    def grad_hess(self, j: int) -> Tuple[float, float]:
+        g, h = ctypes.c_double(), ctypes.c_double()
+        self._check(lib().sccs_grad_hess(self.h, int(j), ctypes.byref(g), ctypes.byref(h)))
+        return g.value, h.value
+
+    def objective(self) -> Tuple[float, float]:
+        L_, P_ = ctypes.c_double(), ctypes.c_double()
+        self._check(lib().sccs_objective(self.h, ctypes.byref(L_), ctypes.byref(P_)))
+        return L_.value, P_.value
+
+    def last_kernel_ms(self) -> float:
+        ms = ctypes.c_double()
+        self._check(lib().sccs_last_kernel_ms(self.h, ctypes.byref(ms)))
+        return ms.value

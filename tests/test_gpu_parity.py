@@ -1,0 +1,271 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle
+on the same seeded inputs.
+
+FP64 results differ from the oracle only in summation order (segmented and
+tree sums on the GPU, sequential sums in the oracle; incremental den on the
+GPU, recomputed den in the oracle), so trajectories must agree far inside
+the 1e-6 relative tolerance on beta; the tests use 1e-9 on small problems.
+The mixed-precision form is held to the 1e-6 relative bar on beta.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1208_0945_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-9
+MIXED_TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def sccs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1208_0945_amd import sccs as s
+    s.lib()
+    return s
+
+
+def rel_inf(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def zipf_small(n_patients=20000, n_cols=300, seed=0, p0=0.1):
+    return synth.zipf_problem("zipf_small", n_patients, n_cols, p0, seed_path=(8, seed))
+
+
+def run_gpu(sccs, prob, kind, var, sweeps, weight=None, precision=0, n_workgroups=0, beta0=None):
+    with sccs.Handle(prob, weight=weight, precision=precision, n_workgroups=n_workgroups) as h:
+        h.set_prior(kind, var)
+        if beta0 is not None:
+            h.set_beta(beta0)
+        if sweeps:
+            h.sweep(sweeps)
+        return h.get_beta()
+
+
+def test_first_coordinates_at_zero_match_oracle(sccs):
+    prob = synth.tiny()
+    with sccs.Handle(prob) as h:
+        for j in range(prob.n_cols):
+            g, hh = h.grad_hess(j)
+            go, ho = oracle.grad_hess(prob, np.zeros(prob.n_cols), j)
+            assert abs(g - go) <= 1e-12 * max(1.0, abs(go))
+            assert abs(hh - ho) <= 1e-12 * abs(ho)
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-11), (1, 2e-6)])
+def test_grad_hess_at_warm_start_match_oracle(sccs, precision, tol):
+    prob = zipf_small(n_patients=5000, n_cols=40, seed=1)
+    beta = synth.random_beta(prob.n_cols, 0.5, 11)
+    with sccs.Handle(prob, precision=precision) as h:
+        h.set_beta(beta)
+        for j in range(prob.n_cols):
+            g, hh = h.grad_hess(j)
+            go, ho = oracle.grad_hess(prob, beta, j)
+            assert abs(g - go) <= tol * max(1.0, abs(ho)), (j, g, go)
+            assert abs(hh - ho) <= tol * max(1.0, abs(ho)), (j, hh, ho)
+
+
+@pytest.mark.parametrize("kind,var", [(1, 1.0), (2, 2.0), (0, 1.0), (2, 0.02)])
+@pytest.mark.parametrize("sweeps", [1, 2, 20])
+def test_tiny_trajectory_matches_oracle(sccs, kind, var, sweeps):
+    prob = synth.tiny()
+    ref = oracle.ccd(prob, kind, var, sweeps)
+    beta, trust = run_gpu(sccs, prob, kind, var, sweeps)
+    assert rel_inf(beta, ref["beta"]) <= FP64_TOL
+    assert np.max(np.abs(trust - ref["trust"])) <= 1e-9 * np.max(ref["trust"])
+    assert np.array_equal(beta == 0.0, ref["beta"] == 0.0)
+
+
+def test_tiny_fit_to_convergence(sccs):
+    """Config: tiny, Normal var 1, until relative log-posterior change < 1e-8."""
+    prob = synth.tiny()
+    ref = oracle.ccd(prob, 1, 1.0, 500, oracle.CRIT_REL_LOGPOST, 1e-8)
+    with sccs.Handle(prob) as h:
+        h.set_prior(1, 1.0)
+        r = h.fit(sccs.CRIT_REL_LOGPOST, 500, 1e-8)
+        beta, _ = h.get_beta()
+        assert r["converged"]
+        assert abs(r["sweeps"] - ref["sweeps"]) <= 1
+        assert abs(r["logpost"] - ref["logpost"]) <= 1e-10 * abs(ref["logpost"])
+    # replay exactly the oracle's sweep count
+    beta2, _ = run_gpu(sccs, prob, 1, 1.0, ref["sweeps"])
+    assert rel_inf(beta2, ref["beta"]) <= FP64_TOL
+
+
+def test_abs_dxbeta_criterion(sccs):
+    prob = synth.tiny(seed=2)
+    ref = oracle.ccd(prob, 2, 2.0, 500, oracle.CRIT_ABS_DXBETA, 5e-4)
+    with sccs.Handle(prob) as h:
+        h.set_prior(2, 2.0)
+        r = h.fit(sccs.CRIT_ABS_DXBETA, 500, 5e-4)
+        assert r["converged"] and abs(r["sweeps"] - ref["sweeps"]) <= 1
+
+
+@pytest.mark.parametrize("n_workgroups", [1, 3, 64, 0])
+def test_zipf_laplace_20_sweeps(sccs, n_workgroups):
+    """Mid-shaped (Zipf columns, 1+Poisson(9) eras) at 20k patients, Laplace
+    lambda = 1, 20 sweeps; several workgroup counts (ownership splits)."""
+    prob = zipf_small()
+    ref = oracle.ccd(prob, 2, 2.0, 20)
+    beta, _ = run_gpu(sccs, prob, 2, 2.0, 20, n_workgroups=n_workgroups)
+    assert rel_inf(beta, ref["beta"]) <= FP64_TOL
+    assert np.array_equal(beta == 0.0, ref["beta"] == 0.0)
+
+
+def ragged_problem():
+    """Patients from 1 to 300 eras; a column covering every era of the long
+    patients (segments longer than one wavefront), an empty column, a single
+    nonzero column and patients without events."""
+    rng = np.random.default_rng(77)
+    sizes = np.concatenate([[300, 1, 130, 65, 64, 63, 2], rng.integers(1, 12, size=400)])
+    ptr = np.zeros(len(sizes) + 1, np.int64)
+    ptr[1:] = np.cumsum(sizes)
+    K = int(ptr[-1])
+    offset = rng.integers(1, 365, size=K).astype(np.int32)
+    count = rng.poisson(0.3, size=K).astype(np.int32)
+    count[ptr[5]:ptr[6]] = 0                      # a patient with n_i = 0
+    count[ptr[0]] = max(count[ptr[0]], 1)
+    cols = []
+    long_rows = np.concatenate([np.arange(ptr[i], ptr[i + 1]) for i in (0, 2, 3, 4)])
+    cols.append(np.unique(np.concatenate([long_rows, np.flatnonzero(rng.random(K) < 0.1)])))
+    cols.append(np.zeros(0, np.int64))            # empty column
+    cols.append(np.array([ptr[7]]))               # one nonzero
+    for _ in range(5):
+        cols.append(np.flatnonzero(rng.random(K) < rng.uniform(0.02, 0.5)))
+    col_ptr = np.zeros(len(cols) + 1, np.int64)
+    col_ptr[1:] = np.cumsum([len(c) for c in cols])
+    return synth.Problem("ragged", len(sizes), ptr, offset, count, len(cols), col_ptr,
+                         np.concatenate(cols).astype(np.int32), np.zeros(len(cols)))
+
+
+@pytest.mark.parametrize("kind,var", [(1, 0.5), (2, 0.5)])
+@pytest.mark.parametrize("n_workgroups", [1, 5, 0])
+def test_ragged_and_long_segments(sccs, kind, var, n_workgroups):
+    prob = ragged_problem()
+    ref = oracle.ccd(prob, kind, var, 10)
+    beta, _ = run_gpu(sccs, prob, kind, var, 10, n_workgroups=n_workgroups)
+    assert rel_inf(beta, ref["beta"]) <= FP64_TOL
+    assert beta[1] == 0.0  # empty column never moves
+
+
+@pytest.mark.parametrize("mode", ["cv", "bootstrap"])
+def test_patient_weights(sccs, mode):
+    prob = zipf_small(n_patients=8000, n_cols=100, seed=3)
+    if mode == "cv":
+        w = (synth.cv_folds(prob.n_patients, 10, seed=1) != 3).astype(np.int32)
+    else:
+        w = np.random.default_rng(5).multinomial(prob.n_patients, np.full(prob.n_patients, 1.0 / prob.n_patients)).astype(np.int32)
+    ref = oracle.ccd(prob, 2, 2.0, 10, weight=w)
+    beta, _ = run_gpu(sccs, prob, 2, 2.0, 10, weight=w)
+    assert rel_inf(beta, ref["beta"]) <= FP64_TOL
+
+
+def test_objective_matches_oracle(sccs):
+    prob = zipf_small(n_patients=5000, n_cols=50, seed=4)
+    with sccs.Handle(prob) as h:
+        h.set_prior(2, 0.5)
+        h.sweep(3)
+        beta, _ = h.get_beta()
+        L, P = h.objective()
+        lp = h.sweep(1, want_logpost=True)
+        beta4, _ = h.get_beta()
+    Lo = oracle.loglik(prob, beta)
+    assert abs(L - Lo) <= 1e-11 * abs(Lo)
+    assert abs(P - (Lo + oracle.log_prior(2, 0.5, beta))) <= 1e-11 * abs(Lo)
+    Lo4 = oracle.loglik(prob, beta4) + oracle.log_prior(2, 0.5, beta4)
+    assert abs(lp - Lo4) <= 1e-11 * abs(Lo4)
+
+
+def test_deterministic(sccs):
+    prob = zipf_small(n_patients=10000, n_cols=120, seed=5)
+    a, _ = run_gpu(sccs, prob, 1, 0.5, 5)
+    b, _ = run_gpu(sccs, prob, 1, 0.5, 5)
+    assert np.array_equal(a, b)
+
+
+def test_checkpoint_resume(sccs):
+    prob = zipf_small(n_patients=10000, n_cols=120, seed=6)
+    straight, _ = run_gpu(sccs, prob, 2, 2.0, 20)
+    with sccs.Handle(prob) as h:
+        h.set_prior(2, 2.0)
+        h.sweep(10)
+        beta, trust = h.get_beta()
+    with sccs.Handle(prob) as h:
+        h.set_prior(2, 2.0)
+        h.set_beta(beta, trust)
+        h.sweep(10)
+        resumed, _ = h.get_beta()
+    assert rel_inf(resumed, straight) <= 1e-11
+    ref = oracle.ccd(prob, 2, 2.0, 20)
+    assert rel_inf(resumed, ref["beta"]) <= FP64_TOL
+
+
+@pytest.mark.parametrize("kind,var", [(2, 2.0), (1, 0.5)])
+def test_mixed_precision_error_bound(sccs, kind, var):
+    prob = zipf_small(n_patients=20000, n_cols=200, seed=7)
+    ref = oracle.ccd(prob, kind, var, 20)
+    beta, _ = run_gpu(sccs, prob, kind, var, 20, precision=1)
+    err = rel_inf(beta, ref["beta"])
+    print(f"mixed-precision rel_inf error vs FP64 oracle: {err:.3e}")
+    assert err <= MIXED_TOL
+
+
+def test_numeric_failure_reported(sccs):
+    """A warm start far outside the range of exp (beta_0 = 800) makes
+    w = l e^800 overflow; the first visit then sees a non-finite gradient.
+    The library reports it and keeps the last finite beta."""
+    prob = synth.tiny()
+    beta0 = np.zeros(prob.n_cols)
+    beta0[0] = 800.0
+    for precision in (0, 1):
+        with sccs.Handle(prob, precision=precision) as h:
+            h.set_prior(1, 1.0)
+            h.set_beta(beta0)
+            with pytest.raises(sccs.SccsError) as e:
+                h.sweep(2)
+            assert e.value.status == sccs.ERR_NUMERIC
+            beta, _ = h.get_beta()
+            assert np.all(np.isfinite(beta)) and beta[0] == 800.0
+            # the handle stays usable after a reset of the start point
+            h.set_beta(np.zeros(prob.n_cols))
+            h.sweep(1)
+
+
+def test_errors_without_prior_and_bad_args(sccs):
+    prob = synth.tiny()
+    with sccs.Handle(prob) as h:
+        with pytest.raises(sccs.SccsError) as e:
+            h.sweep(1)
+        assert e.value.status == sccs.ERR_STATE
+        with pytest.raises(sccs.SccsError):
+            h.set_prior(1, -1.0)
+        with pytest.raises(sccs.SccsError):
+            h.grad_hess(prob.n_cols)
+        with pytest.raises(sccs.SccsError):
+            h.set_beta(np.full(prob.n_cols, np.nan))
+
+
+def test_full_size_mid_parity(sccs):
+    """Full mid workload (2M patients, ~20M eras, J = 2000, Laplace lambda = 1)
+    in the benchmark's launch configuration: the first 3 sweeps against the
+    oracle, then g_j, h_j of sampled columns at the reached beta."""
+    prob = synth.mid()
+    ref = oracle.ccd(prob, 2, 2.0, 3)
+    with sccs.Handle(prob) as h:
+        h.set_prior(2, 2.0)
+        h.sweep(3)
+        beta, _ = h.get_beta()
+        assert rel_inf(beta, ref["beta"]) <= FP64_TOL
+        c = np.diff(prob.col_ptr)
+        for j in [int(np.argmax(c)), int(np.argmin(c)), int(np.argsort(c)[len(c) // 2]), 7]:
+            g, hh = h.grad_hess(j)
+            go, ho = oracle.grad_hess(prob, beta, j)
+            assert abs(g - go) <= 1e-9 * max(1.0, abs(ho)), (j, g, go)
+            assert abs(hh - ho) <= 1e-9 * abs(ho), (j, hh, ho)
