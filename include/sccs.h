@@ -176,6 +176,58 @@ sccs_status sccs_last_kernel_ms(sccs_handle* h, double* ms);
  * last failed create when h is NULL).  Never NULL. */
 const char* sccs_last_error(const sccs_handle* h);
 
+/* ------------------------------------------------------------ batched form
+ *
+ * F <= 64 independent fits advanced in lockstep by one persistent launch
+ * (Section 2.5: cross-validation over a prior grid and bootstrap replicates
+ * need many fits; different outcomes over one drug vocabulary likewise).
+ * All problems of a batch share n_cols.  Per coordinate, one device-wide
+ * reduction carries the partial sums of all fits.  Each fit walks a chain
+ * of priors in order: link l starts from the beta where link l-1 ended
+ * (warm start, Section 2.5), with every trust bound reset to 1, and ends
+ * when the stopping rule holds or after max_sweeps sweeps; its beta and
+ * result are recorded.  Per fit, patient weights (for example the training
+ * indicator of a cross-validation fold) override the problem's own.
+ */
+typedef struct sccs_batch sccs_batch;
+
+typedef struct sccs_fit_spec {
+  int32_t problem;               /* index into the problem array */
+  int32_t n_links;               /* >= 1 priors visited in order */
+  const int32_t* prior_kind;     /* [n_links] SCCS_PRIOR_* */
+  const double* variance;        /* [n_links] > 0 (ignored for NONE) */
+  const int32_t* patient_weight; /* [N of its problem] >= 0, or NULL */
+} sccs_fit_spec;
+
+/* Device bytes for sccs_batch_create (validates as sccs_batch_create). */
+sccs_status sccs_batch_query_workspace(const sccs_problem* probs, int32_t n_probs, const sccs_fit_spec* fits,
+                                       int32_t n_fits, const sccs_options* opts, size_t* bytes);
+
+/* Validate, repack every problem once (fits of one problem share its index
+ * data), set up every fit at beta = 0.  workspace as for sccs_create.
+ * Errors as for sccs_create; n_fits in [1, 64]. */
+sccs_status sccs_batch_create(const sccs_problem* probs, int32_t n_probs, const sccs_fit_spec* fits,
+                              int32_t n_fits, const sccs_options* opts, void* workspace, size_t workspace_bytes,
+                              sccs_batch** out);
+
+/* Run every fit's chain to its end in one launch.  fo->criterion is
+ * SCCS_CRIT_FIXED (each link runs exactly max_sweeps sweeps) or
+ * SCCS_CRIT_REL_LOGPOST (per link, until |P_t - P_{t-1}| < tol |P_t| or
+ * max_sweeps).  Synchronises. */
+sccs_status sccs_batch_run(sccs_batch* b, const sccs_fit_opts* fo);
+
+/* beta [J] (host, nullable) and the result of link `link` of fit `fit`. */
+sccs_status sccs_batch_get(sccs_batch* b, int32_t fit, int32_t link, double* beta, sccs_fit_result* res);
+
+/* Device time of the last sccs_batch_run launch (ms). */
+sccs_status sccs_batch_last_kernel_ms(sccs_batch* b, double* ms);
+
+/* NULL-safe. */
+sccs_status sccs_batch_destroy(sccs_batch* b);
+
+/* Description of the last error on b, or of the last failed create. */
+const char* sccs_batch_last_error(const sccs_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -2,6 +2,7 @@
 // setup and the cooperative launches of the persistent CCD kernel.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -12,6 +13,7 @@
 #include "sccs.h"
 #include "sccs_device.hpp"
 #include "sccs_kernels.hpp"
+#include "sccs_batch.hpp"
 #include "sccs_layout.hpp"
 
 using namespace sccs;
@@ -29,6 +31,7 @@ struct sccs_handle {
   double var = 1.0;
   int32_t refresh_period = 0;
   size_t lds_bytes = 0;
+  int32_t nbits = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool timed = false;
   KArgs args{};
@@ -63,7 +66,7 @@ struct Plan {
   void* w;
   double2* pat;
   double *ytx, *beta, *trust;
-  uint64_t *slots, *oslots;
+  uint64_t *slots, *slots2, *oslots, *oslots2;
   Ctrl* ctrl;
 };
 
@@ -85,8 +88,11 @@ size_t carve(void* base, const Layout& L, int prec, bool has_weight, Plan& P) {
   P.ytx = c.take<double>((size_t)L.J);
   P.beta = c.take<double>((size_t)L.J);
   P.trust = c.take<double>((size_t)L.J);
-  P.slots = c.take<uint64_t>((size_t)2 * L.G * 2);
-  P.oslots = c.take<uint64_t>((size_t)2 * L.G * 4);
+  const size_t n1 = (size_t)2 * kMaxWorkgroups * kSlotWords, n2 = (size_t)2 * kReplicas * kGroups * kSlotWords;
+  P.slots = c.take<uint64_t>(n1);
+  P.slots2 = c.take<uint64_t>(n2);
+  P.oslots = c.take<uint64_t>(n1);
+  P.oslots2 = c.take<uint64_t>(n2);
   P.ctrl = c.take<Ctrl>(1);
   return (c.off + 255) & ~(size_t)255;
 }
@@ -97,7 +103,7 @@ sccs_status check_options(const sccs_options* o, std::string& err) {
     err = "options.precision must be SCCS_PREC_FP64 or SCCS_PREC_MIXED";
     return SCCS_ERR_INVALID_ARG;
   }
-  if (o->n_workgroups < 0 || o->n_workgroups > 64 * kMaxSlotsPerLane) {
+  if (o->n_workgroups < 0 || o->n_workgroups > kMaxWorkgroups) {
     err = "options.n_workgroups must be in [0, 256]";
     return SCCS_ERR_INVALID_ARG;
   }
@@ -121,7 +127,7 @@ sccs_status pick_workgroups(const sccs_options* o, int32_t& G, std::string& err)
     return SCCS_ERR_HIP;
   }
   G = (o && o->n_workgroups > 0) ? o->n_workgroups : cus;
-  if (G > 64 * kMaxSlotsPerLane) G = 64 * kMaxSlotsPerLane;
+  if (G > kMaxWorkgroups) G = kMaxWorkgroups;
   if (G > cus) { err = "n_workgroups exceeds the number of compute units"; return SCCS_ERR_INVALID_ARG; }
   return SCCS_OK;
 }
@@ -169,6 +175,7 @@ sccs_status launch(sccs_handle* h, int mode, int n_sweeps, int criterion, double
   KArgs a = h->args;
   a.prior_kind = h->prior_kind < 0 ? SCCS_PRIOR_NONE : h->prior_kind;
   a.var = h->var;
+  a.inv_var = 1.0 / h->var;
   a.lambda = (a.prior_kind == SCCS_PRIOR_LAPLACE) ? std::sqrt(2.0 / h->var) : 0.0;
   a.n_sweeps = n_sweeps;
   a.criterion = criterion;
@@ -276,7 +283,17 @@ sccs_status sccs_create(const sccs_problem* prob, const sccs_options* opts_in, v
   h->prec = opts.precision;
   h->stream = (hipStream_t)opts.stream;
   h->refresh_period = opts.refresh_period >= 0 ? opts.refresh_period : (opts.precision == SCCS_PREC_MIXED ? 1 : 0);
-  h->lds_bytes = (size_t)3 * L.J * sizeof(double);
+  {
+    int32_t maxrange = 1;
+    for (int32_t b = 0; b < G; ++b) maxrange = std::max(maxrange, L.pb[b + 1] - L.pb[b]);
+    h->nbits = (maxrange + 31) / 32;
+  }
+  h->lds_bytes = (size_t)3 * L.J * sizeof(double) + (size_t)2 * h->nbits * sizeof(uint32_t);
+  if (h->lds_bytes > 150 * 1024) {
+    delete h;
+    g_create_error = "too many columns or patients per workgroup for the LDS budget";
+    return SCCS_ERR_INVALID_ARG;
+  }
 
   auto bail = [&](const std::string& m, sccs_status code) {
     g_create_error = m;
@@ -328,9 +345,13 @@ sccs_status sccs_create(const sccs_problem* prob, const sccs_options* opts_in, v
        hipMemsetAsync(P.ctrl, 0, sizeof(Ctrl), s) == hipSuccess;
   if (!ok) return bail("state initialisation failed", SCCS_ERR_HIP);
   // reduction slots start with the tag that reductions 0 and 1 do not expect
-  size_t nslot = (size_t)2 * G * 2, noslot = (size_t)2 * G * 4;
-  hipLaunchKernelGGL(k_fill_u64, dim3(16), dim3(256), 0, s, P.slots, nslot, kSign);
-  hipLaunchKernelGGL(k_fill_u64, dim3(16), dim3(256), 0, s, P.oslots, noslot, kSign);
+  {
+    const size_t n1 = (size_t)2 * kMaxWorkgroups * kSlotWords, n2 = (size_t)2 * kReplicas * kGroups * kSlotWords;
+    hipLaunchKernelGGL(k_fill_u64, dim3(16), dim3(256), 0, s, P.slots, n1, kSign);
+    hipLaunchKernelGGL(k_fill_u64, dim3(4), dim3(256), 0, s, P.slots2, n2, kSign);
+    hipLaunchKernelGGL(k_fill_u64, dim3(16), dim3(256), 0, s, P.oslots, n1, kSign);
+    hipLaunchKernelGGL(k_fill_u64, dim3(4), dim3(256), 0, s, P.oslots2, n2, kSign);
+  }
   int gp = (L.N + 255) / 256;
   if (gp > 4096) gp = 4096;
   hipLaunchKernelGGL(k_setup_patients, dim3(gp), dim3(256), 0, s, P.pptr, P.count, P.weight, P.pat, L.N);
@@ -341,8 +362,9 @@ sccs_status sccs_create(const sccs_problem* prob, const sccs_options* opts_in, v
   KArgs& a = h->args;
   a.rp = P.rp; a.tile_start = P.tile_start; a.own = P.own; a.pb = P.pb; a.pptr = P.pptr;
   a.era_ptr = P.era_ptr; a.era_col = P.era_col; a.offset = P.offset; a.w = P.w; a.pat = P.pat;
-  a.ytx = P.ytx; a.beta = P.beta; a.trust = P.trust; a.slots = P.slots; a.oslots = P.oslots;
-  a.ctrl = P.ctrl; a.N = L.N; a.J = L.J; a.G = G;
+  a.ytx = P.ytx; a.beta = P.beta; a.trust = P.trust; a.slots = P.slots; a.slots2 = P.slots2;
+  a.oslots = P.oslots; a.oslots2 = P.oslots2;
+  a.ctrl = P.ctrl; a.N = L.N; a.J = L.J; a.G = G; a.nbits = h->nbits;
   h->d_col_ptr = P.col_ptr; h->d_count = P.count; h->d_weight = P.weight;
   if (refresh_all(h) != SCCS_OK) return bail(h->err, SCCS_ERR_HIP);
   if (hipStreamSynchronize(s) != hipSuccess) return bail("setup failed on the device", SCCS_ERR_HIP);
@@ -488,3 +510,5 @@ const char* sccs_last_error(const sccs_handle* h) {
 }
 
 }  // extern "C"
+
+#include "sccs_batch_api.inc"

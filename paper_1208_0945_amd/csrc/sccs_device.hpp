@@ -5,9 +5,13 @@
 
 namespace sccs {
 
-constexpr int kBlock = 1024;             // threads per persistent workgroup
+constexpr int kBlock = 512;              // threads per persistent workgroup
 constexpr int kWaves = kBlock / 64;      // wavefronts per workgroup
-constexpr int kMaxSlotsPerLane = 4;      // => at most 256 workgroups
+constexpr int kMaxWorkgroups = 256;       // two-level reduction: <= 32 members per group
+constexpr int kGroups = 8;               // reduction groups (one per XCD under round-robin placement)
+constexpr int kPoller = kWaves - 1;      // wave that runs the device-wide reduction
+constexpr int kSlotWords = 16;           // one 128-byte line per reduction slot
+constexpr int kReplicas = 8;             // copies of the group totals
 constexpr int kMaxJ = 6144;              // beta, trust, beta_prev live in LDS
 constexpr uint64_t kSign = 0x8000000000000000ull;
 constexpr long long kSpinLimit = 1ll << 22;  // bounded waits (about a second), then abort
@@ -40,12 +44,14 @@ struct KArgs {
   const double* ytx;          // [J]
   double* beta;               // [J]
   double* trust;              // [J]
-  uint64_t* slots;            // [2][G][2] coordinate reduction
-  uint64_t* oslots;           // [2][G][4] objective reduction
+  uint64_t* slots;            // [2][256][16] coordinate reduction, level 1
+  uint64_t* slots2;           // [2][8 replicas][8 groups][16] group totals
+  uint64_t* oslots;           // objective reduction, same shapes
+  uint64_t* oslots2;
   Ctrl* ctrl;
   int32_t N, J, G;
   int32_t prior_kind;
-  double var, lambda;
+  double var, inv_var, lambda;
   int32_t n_sweeps;
   int32_t criterion;
   double tol;
@@ -53,6 +59,7 @@ struct KArgs {
   int32_t want_objective;     // evaluate P after the last sweep
   int32_t mode;               // 0 sweep, 1 grad/hess of diag_j, 2 objective only
   int32_t diag_j;
+  int32_t nbits;              // words of each per-workgroup patient bitmap (LDS)
 };
 
 enum { kModeSweep = 0, kModeGradHess = 1, kModeObjective = 2 };

@@ -70,65 +70,96 @@ __device__ __forceinline__ int load_agent_i(const int32_t* p) {
   return __hip_atomic_load(const_cast<int32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Device-wide sum of NV non-negative doubles per workgroup.  Called by all
-// threads of every workgroup with the workgroup's partials valid in thread 0.
-// Returns false (in all threads) if the wait timed out or another workgroup
-// aborted.  out[] receives the sums (all threads).
+// Poll NV tagged words at src (active lanes) until all carry `tag`; the
+// decoded values land in v (zeros in inactive lanes).  Returns false in the
+// whole wave on timeout or if another workgroup aborted.
 template <int NV>
-__device__ bool allreduce_nonneg(uint64_t* slots, uint32_t seq, int G, Ctrl* ctrl,
-                                 const double* part, double* out, double* lds_out, int* lds_ok) {
-  const int tid = threadIdx.x, lane = tid & 63;
-  const uint32_t par = seq & 1u, tag = (seq >> 1) & 1u;
-  uint64_t* mine = slots + ((size_t)par * G + blockIdx.x) * NV;
-  if (tid == 0) {
+__device__ __forceinline__ bool poll_tagged(const uint64_t* src, bool active, uint32_t tag, double* v, Ctrl* ctrl) {
+  bool need = active;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) store_agent(mine + v, tag_encode(part[v], tag));
+  for (int i = 0; i < NV; ++i) v[i] = 0.0;
+  long long spins = 0;
+  while (true) {
+    if (need) {
+      bool ready = true;
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        uint64_t x = load_agent(src + i);
+        ready = ready && ((uint32_t)(x >> 63) == tag);
+        v[i] = tag_decode(x);
+      }
+      if (ready) need = false;
+    }
+    if (__ballot(need) == 0ull) return true;
+    if (++spins > kSpinLimit) {
+      if ((threadIdx.x & 63) == 0) {
+        __hip_atomic_store(&ctrl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ctrl->status, (int)SCCS_ERR_SYNC, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      return false;
+    }
+    if ((spins & 255) == 0 && load_agent_i(&ctrl->abort)) return false;
+    __builtin_amdgcn_s_sleep(2);
   }
-  if (tid < 64) {
-    const uint64_t* base = slots + (size_t)par * G * NV;
-    double val[kMaxSlotsPerLane][NV];
-    uint32_t need = 0;
-    for (int q = 0; q < kMaxSlotsPerLane; ++q)
-      if (lane + 64 * q < G) need |= 1u << q;
-    long long spins = 0;
-    bool ok = true;
-    while (true) {
+}
+
+// Device-wide sum of NV non-negative doubles per workgroup, in two levels:
+// the workgroups form ng = min(8, G) groups (b mod ng, which follows the
+// round-robin placement of workgroups on the eight XCDs); the leader of a
+// group (workgroup g < ng) sums its members' tagged slots in member order and
+// publishes the tagged group total; every workgroup then sums the ng group
+// totals in group order, so every workgroup computes the same value bit for
+// bit.  Each level-1 slot has a 128-byte line of its own, and the group
+// totals are written in kReplicas copies (reader b polls copy b mod
+// kReplicas): polling 256 workgroups on one line serialises at the memory
+// side.  Must be called by all lanes of ONE wave of every workgroup, with the
+// workgroup's partials in part[] of that wave's lane 0.  Returns the sums in
+// out[] in all lanes of that wave.
+template <int NV>
+__device__ bool allreduce2_wave(uint64_t* s1, uint64_t* s2, uint32_t seq, int G, Ctrl* ctrl,
+                                const double* part, double* out) {
+  const int lane = threadIdx.x & 63, b = blockIdx.x;
+  const uint32_t par = seq & 1u, tag = (seq >> 1) & 1u;
+  const int ng = G < kGroups ? G : kGroups;
+  uint64_t* L1 = s1 + (size_t)par * kMaxWorkgroups * kSlotWords;
+  uint64_t* L2 = s2 + (size_t)par * kReplicas * kGroups * kSlotWords;
+  if (lane == 0) {
 #pragma unroll
-      for (int q = 0; q < kMaxSlotsPerLane; ++q) {
-        if (need & (1u << q)) {
-          const uint64_t* s = base + (size_t)(lane + 64 * q) * NV;
-          bool ready = true;
+    for (int v = 0; v < NV; ++v) store_agent(L1 + (size_t)b * kSlotWords + v, tag_encode(part[v], tag));
+  }
+  double v[NV];
+  if (b < ng) {
+    const int member = b + lane * ng;
+    if (!poll_tagged<NV>(L1 + (size_t)(member < G ? member : b) * kSlotWords, member < G, tag, v, ctrl)) return false;
 #pragma unroll
-          for (int v = 0; v < NV; ++v) {
-            uint64_t x = load_agent(s + v);
-            ready = ready && ((uint32_t)(x >> 63) == tag);
-            val[q][v] = tag_decode(x);
-          }
-          if (ready) need &= ~(1u << q);
-        }
-      }
-      if (__ballot(need != 0) == 0ull) break;
-      if (++spins > kSpinLimit) {
-        if (lane == 0) {
-          __hip_atomic_store(&ctrl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_store(&ctrl->status, (int)SCCS_ERR_SYNC, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        ok = false;
-        break;
-      }
-      if ((spins & 255) == 0 && load_agent_i(&ctrl->abort)) { ok = false; break; }
-      __builtin_amdgcn_s_sleep(1);
+    for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+    if (lane < kReplicas) {
+#pragma unroll
+      for (int i = 0; i < NV; ++i)
+        store_agent(L2 + ((size_t)lane * kGroups + b) * kSlotWords + i, tag_encode(v[i], tag));
     }
+  }
+  const int r = b % kReplicas;
+  if (!poll_tagged<NV>(L2 + ((size_t)r * kGroups + (lane < ng ? lane : 0)) * kSlotWords, lane < ng, tag, v, ctrl))
+    return false;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      double s = 0.0;
+  for (int i = 0; i < NV; ++i) out[i] = wave_sum(v[i]);
+  return true;
+}
+
+// Workgroup-level wrapper: wave 0 reduces, the result is broadcast through
+// LDS.  Called by all threads with the partials valid in thread 0.
+template <int NV>
+__device__ bool allreduce_nonneg(uint64_t* s1, uint64_t* s2, uint32_t seq, int G, Ctrl* ctrl,
+                                 const double* part, double* out, double* lds_out, int* lds_ok) {
+  if (threadIdx.x < 64) {
+    double o[NV];
+    bool ok = allreduce2_wave<NV>(s1, s2, seq, G, ctrl, part, o);
+    if (threadIdx.x == 0) {
 #pragma unroll
-      for (int q = 0; q < kMaxSlotsPerLane; ++q)
-        if (lane + 64 * q < G) s += val[q][v];
-      s = wave_sum(s);
-      if (lane == 0) lds_out[v] = s;
+      for (int v = 0; v < NV; ++v) lds_out[v] = o[v];
+      *lds_ok = ok ? 1 : 0;
     }
-    if (lane == 0) *lds_ok = ok ? 1 : 0;
   }
   __syncthreads();
   bool ok = *lds_ok != 0;
@@ -162,11 +193,34 @@ __device__ void block_sum(const double* v_in, double* out, double (*red)[4]) {
   __syncthreads();
 }
 
+// Same fixed-order sum, result valid in lane 0 of wave `dst` only; one
+// barrier.  red[] may be reused after the caller's next barrier.
+template <int NV>
+__device__ __forceinline__ void block_sum_to(const double* v_in, double* out, double (*red)[4], int dst) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double v[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v_in[i]);
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) red[wave][i] = v[i];
+  }
+  __syncthreads();
+  if (wave == dst && lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      double s = 0.0;
+      for (int q = 0; q < kWaves; ++q) s += red[q][i];
+      out[i] = s;
+    }
+  }
+}
+
 // ------------------------------------------------------------ Newton step
 
 // Eq. 4 with the prior; Laplace rules at the kink after Genkin et al.
-__device__ double prior_step(int kind, double var, double lambda, double b, double g, double h) {
-  if (kind == SCCS_PRIOR_NORMAL) return -(g - b / var) / (h - 1.0 / var);
+__device__ double prior_step(int kind, double inv_var, double lambda, double b, double g, double h) {
+  if (kind == SCCS_PRIOR_NORMAL) return -(g - b * inv_var) / (h - inv_var);
   double lam = (kind == SCCS_PRIOR_LAPLACE) ? lambda : 0.0;
   if (!(h < 0.0)) return 0.0;
   if (b > 0.0) {
@@ -207,17 +261,22 @@ struct Prec<float> {
 
 // ------------------------------------------------------------ segmented sums
 
-// Sum of v over the lanes of this lane's patient segment, valid in the
-// segment's head lane.  pid is sorted ascending over the active lanes
-// [0, len); inactive lanes hold v = 0.
-__device__ __forceinline__ double seg_sum(double v, uint32_t pid, int lane, int len, bool& head) {
+// Segment layout of a tile: head lanes start a patient segment, seg_end is
+// the last lane of this lane's segment.  pid is sorted ascending over the
+// active lanes [0, len).  Shuffles only, no memory.
+__device__ __forceinline__ void seg_layout(uint32_t pid, int lane, int len, bool& head, int& seg_end) {
   uint32_t pid_next = __shfl_down(pid, 1, 64);
   uint32_t pid_prev = __shfl_up(pid, 1, 64);
   bool act = lane < len;
   bool tail = act && (lane == len - 1 || pid_next != pid);
   head = act && (lane == 0 || pid_prev != pid);
   uint64_t tails = __ballot(tail);
-  int seg_end = act ? lane + (int)__builtin_ctzll(tails >> lane) : lane;
+  seg_end = act ? lane + (int)__builtin_ctzll(tails >> lane) : lane;
+}
+
+// Sum of v over this lane's segment (valid in head lanes): a suffix scan
+// restricted to the segment, fixed order.
+__device__ __forceinline__ double seg_sum_v(double v, int lane, int seg_end) {
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
     double o = __shfl_down(v, d, 64);
@@ -226,101 +285,269 @@ __device__ __forceinline__ double seg_sum(double v, uint32_t pid, int lane, int 
   return v;
 }
 
-// Phase A over the tiles of column j owned by this workgroup; per-lane
-// accumulators of G and H.
+__device__ __forceinline__ double seg_sum(double v, uint32_t pid, int lane, int len, bool& head) {
+  int seg_end;
+  seg_layout(pid, lane, len, head, seg_end);
+  return seg_sum_v(v, lane, seg_end);
+}
+
+// Contribution of one patient segment to G and H (the transform of Eq. 8
+// fused with the two inner products of Eqs. 7 and 9).
+__device__ __forceinline__ void accum_patient(double num, double2 pv, double& Gl, double& Hl) {
+  double r = num / pv.x;
+  double tg = pv.y * r;
+  Gl += tg;
+  Hl += tg * fmax(1.0 - r, 0.0);
+}
+
+// ---- one tile, loads included (used for every tile but a wave's first)
+
+// Phase A on tile t: gather w on the tile's rows, sum per patient segment,
+// accumulate the segment's terms of G and H.
+template <typename WT>
+__device__ __forceinline__ void tile_a(const KArgs& a, int t, double& Gl, double& Hl) {
+  const int lane = threadIdx.x & 63;
+  const WT* __restrict__ w = (const WT*)a.w;
+  const int e0 = a.tile_start[t], e1 = a.tile_start[t + 1];
+  const int len = e1 - e0;
+  if (len <= 64) {
+    bool act = lane < len;
+    uint2 rp = act ? a.rp[e0 + lane] : make_uint2(0u, 0xffffffffu);
+    double wv = act ? (double)w[rp.x] : 0.0;
+    bool head;
+    double num = seg_sum(wv, rp.y, lane, len, head);
+    if (head) accum_patient(num, a.pat[rp.y], Gl, Hl);
+  } else {
+    // a patient with more than 64 nonzeros in the column: one segment
+    double s = 0.0;
+    for (int e = e0 + lane; e < e1; e += 64) s += (double)w[a.rp[e].x];
+    s = wave_sum(s);
+    if (lane == 0) accum_patient(s, a.pat[a.rp[e0].y], Gl, Hl);
+  }
+}
+
+// Phase B on tile t: w_k <- w_k e^d on the tile's rows; den_i of each
+// segment moves by num_i (e^d - 1) (FP64), or by the exact change of the
+// stored FP32 weights summed in FP64 (mixed).
+template <typename WT>
+__device__ __forceinline__ void tile_b(const KArgs& a, int t, double ed, double em1) {
+  const int lane = threadIdx.x & 63;
+  WT* __restrict__ w = (WT*)a.w;
+  const WT edw = (WT)ed;
+  const int e0 = a.tile_start[t], e1 = a.tile_start[t + 1];
+  const int len = e1 - e0;
+  if (len <= 64) {
+    bool act = lane < len;
+    uint2 rp = act ? a.rp[e0 + lane] : make_uint2(0u, 0xffffffffu);
+    WT wo = act ? w[rp.x] : (WT)0;
+    WT wn = wo * edw;
+    if (act) w[rp.x] = wn;
+    bool head;
+    if (sizeof(WT) == 8) {
+      double s = seg_sum((double)wo, rp.y, lane, len, head);
+      if (head) a.pat[rp.y].x += s * em1;
+    } else {
+      double s = seg_sum((double)wn - (double)wo, rp.y, lane, len, head);
+      if (head) a.pat[rp.y].x += s;
+    }
+  } else {
+    double s = 0.0;
+    for (int e = e0 + lane; e < e1; e += 64) {
+      uint32_t row = a.rp[e].x;
+      WT wo = w[row];
+      WT wn = wo * edw;
+      w[row] = wn;
+      s += (sizeof(WT) == 8) ? (double)wo : ((double)wn - (double)wo);
+    }
+    s = wave_sum(s);
+    if (lane == 0) a.pat[a.rp[e0].y].x += (sizeof(WT) == 8) ? s * em1 : s;
+  }
+}
+
+// Phase A / B over all tiles of column j owned by this workgroup (the
+// diagnostic kernel's path).
 template <typename WT>
 __device__ void phase_a(const KArgs& a, int j, double& Gl, double& Hl) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const size_t base = (size_t)j * (a.G + 1) + blockIdx.x;
   const int t0 = a.own[base], t1 = a.own[base + 1];
+  for (int t = t0 + (threadIdx.x >> 6); t < t1; t += kWaves) tile_a<WT>(a, t, Gl, Hl);
+}
+
+// ---- the sweep's path
+//
+// Waves 0..kWorkers-1 ("workers") take tiles t0 + w, t0 + w + kWorkers, ...
+// of the current coordinate; the last wave runs the device-wide reduction.
+// Each worker keeps its first tile of a coordinate in registers: the index
+// data is prefetched two coordinates ahead, and the gathers of w and
+// (den_i, omega_i n_i) are issued one coordinate ahead, while the previous
+// coordinate's reduction is in flight.  Such a speculative gather is stale
+// only where the previous coordinate changed the state, i.e. for patients in
+// both columns; every workgroup marks the patients of each coordinate in an
+// LDS bitmap over its own patient range, and a speculative tile that holds a
+// marked patient is gathered again after the update.  The values used are
+// therefore exactly those of the sequential algorithm.
+
+constexpr int kWorkers = kWaves - 1;
+
+struct Pf {
+  int t, t1;     // the wave's first tile; end of the workgroup's tile range
+  int e0, len;   // that tile's nonzero range
+  uint2 rp;      // this lane's (row, patient)
+};
+
+struct Cache {
+  double wv;     // gathered weight
+  double num;    // segment sum (head lanes)
+  double den;    // den_i (head lanes)
+  double wn;     // omega_i n_i (head lanes)
+  bool head;
+  bool valid;    // gathered (possibly speculatively) for this coordinate
+};
+
+__device__ __forceinline__ void pf_range(const KArgs& a, int j, int& t0, int& t1) {
+  const size_t base = (size_t)j * (a.G + 1) + blockIdx.x;
+  t0 = a.own[base];
+  t1 = a.own[base + 1];
+}
+
+__device__ __forceinline__ void pf_tile(const KArgs& a, int t0, int t1, Pf& p) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  p.t = wave < kWorkers ? t0 + wave : t1;
+  p.t1 = t1;
+  p.e0 = 0;
+  p.len = 0;
+  p.rp = make_uint2(0u, 0xffffffffu);
+  if (p.t < t1) {
+    p.e0 = a.tile_start[p.t];
+    p.len = a.tile_start[p.t + 1] - p.e0;
+    if (p.len <= 64 && lane < p.len) p.rp = a.rp[p.e0 + lane];
+  }
+}
+
+// Gather the wave's first tile (short tiles only) into registers.
+template <typename WT>
+__device__ __forceinline__ void gather_first(const KArgs& a, const Pf& p, Cache& c) {
+  const int lane = threadIdx.x & 63;
+  c.valid = true;
+  c.head = false;
+  c.wv = 0.0;
+  c.num = 0.0;
+  c.den = 1.0;
+  c.wn = 0.0;
+  if (p.t < p.t1 && p.len <= 64) {
+    const WT* __restrict__ w = (const WT*)a.w;
+    bool head;
+    int seg_end;
+    seg_layout(p.rp.y, lane, p.len, head, seg_end);
+    const bool act = lane < p.len;
+    double wv = act ? (double)w[p.rp.x] : 0.0;
+    double2 pv = head ? a.pat[p.rp.y] : make_double2(1.0, 0.0);
+    c.num = seg_sum_v(wv, lane, seg_end);
+    c.wv = wv;
+    c.den = pv.x;
+    c.wn = pv.y;
+    c.head = head;
+  }
+}
+
+__device__ __forceinline__ void mark_patient(unsigned* bits, unsigned q) { atomicOr(&bits[q >> 5], 1u << (q & 31)); }
+
+// Does the wave's cached first tile hold a patient marked in bits?
+__device__ __forceinline__ bool first_tile_stale(const Pf& p, const unsigned* bits, int p0) {
+  const int lane = threadIdx.x & 63;
+  bool hit = false;
+  if (p.t < p.t1 && p.len <= 64 && lane < p.len) {
+    const unsigned q = p.rp.y - (unsigned)p0;
+    hit = (bits[q >> 5] >> (q & 31)) & 1u;
+  }
+  return __ballot(hit) != 0ull;
+}
+
+// Phase A on tile t (loads included) that also marks the tile's patients.
+template <typename WT>
+__device__ __forceinline__ void tile_a_mark(const KArgs& a, int t, double& Gl, double& Hl, unsigned* bits, int p0) {
+  const int lane = threadIdx.x & 63;
   const WT* __restrict__ w = (const WT*)a.w;
-  for (int t = t0 + wave; t < t1; t += kWaves) {
-    const int e0 = a.tile_start[t], e1 = a.tile_start[t + 1];
-    const int len = e1 - e0;
-    if (len <= 64) {
-      bool act = lane < len;
-      uint2 rp = act ? a.rp[e0 + lane] : make_uint2(0u, 0xffffffffu);
-      double wv = act ? (double)w[rp.x] : 0.0;
-      bool head;
-      double num = seg_sum(wv, rp.y, lane, len, head);
-      if (head) {
-        double2 pv = a.pat[rp.y];
-        double r = num / pv.x;
-        double tg = pv.y * r;
-        Gl += tg;
-        Hl += tg * fmax(1.0 - r, 0.0);
-      }
-    } else {
-      double s = 0.0;
-      for (int e = e0 + lane; e < e1; e += 64) s += (double)w[a.rp[e].x];
-      s = wave_sum(s);
-      if (lane == 0) {
-        double2 pv = a.pat[a.rp[e0].y];
-        double r = s / pv.x;
-        double tg = pv.y * r;
-        Gl += tg;
-        Hl += tg * fmax(1.0 - r, 0.0);
-      }
+  const int e0 = a.tile_start[t], e1 = a.tile_start[t + 1];
+  const int len = e1 - e0;
+  if (len <= 64) {
+    bool act = lane < len;
+    uint2 rp = act ? a.rp[e0 + lane] : make_uint2(0u, 0xffffffffu);
+    double wv = act ? (double)w[rp.x] : 0.0;
+    bool head;
+    double num = seg_sum(wv, rp.y, lane, len, head);
+    if (head) {
+      accum_patient(num, a.pat[rp.y], Gl, Hl);
+      mark_patient(bits, rp.y - (unsigned)p0);
+    }
+  } else {
+    double s = 0.0;
+    for (int e = e0 + lane; e < e1; e += 64) s += (double)w[a.rp[e].x];
+    s = wave_sum(s);
+    if (lane == 0) {
+      const uint32_t pid = a.rp[e0].y;
+      accum_patient(s, a.pat[pid], Gl, Hl);
+      mark_patient(bits, pid - (unsigned)p0);
     }
   }
 }
 
-// Phase B: w_k <- w_k e^d on the column's rows, den_i updated per segment.
-// ed = e^d and em1 = e^d - 1 are computed once per coordinate by the caller.
+// Phase A of the current coordinate for one worker wave: the cached first
+// tile (validated by the caller) plus its remaining tiles.
 template <typename WT>
-__device__ void phase_b(const KArgs& a, int j, double ed, double em1) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const size_t base = (size_t)j * (a.G + 1) + blockIdx.x;
-  const int t0 = a.own[base], t1 = a.own[base + 1];
-  WT* __restrict__ w = (WT*)a.w;
-  const WT edw = (WT)ed;
-  for (int t = t0 + wave; t < t1; t += kWaves) {
-    const int e0 = a.tile_start[t], e1 = a.tile_start[t + 1];
-    const int len = e1 - e0;
-    if (len <= 64) {
-      bool act = lane < len;
-      uint2 rp = act ? a.rp[e0 + lane] : make_uint2(0u, 0xffffffffu);
-      WT wo = act ? w[rp.x] : (WT)0;
-      WT wn = wo * edw;
-      if (act) w[rp.x] = wn;
-      bool head;
-      double s;
-      if (sizeof(WT) == 8) {
-        s = seg_sum((double)wo, rp.y, lane, len, head);
-        if (head) a.pat[rp.y].x += s * em1;
-      } else {
-        // mixed: track the exact change of the stored FP32 weights in FP64
-        s = seg_sum((double)wn - (double)wo, rp.y, lane, len, head);
-        if (head) a.pat[rp.y].x += s;
+__device__ __forceinline__ void phase_a_cached(const KArgs& a, const Pf& p, const Cache& c, double& Gl, double& Hl,
+                                               unsigned* bits, int p0) {
+  if (p.t < p.t1) {
+    if (p.len <= 64) {
+      if (c.head) {
+        accum_patient(c.num, make_double2(c.den, c.wn), Gl, Hl);
+        mark_patient(bits, p.rp.y - (unsigned)p0);
       }
     } else {
-      double s = 0.0;
-      for (int e = e0 + lane; e < e1; e += 64) {
-        uint32_t row = a.rp[e].x;
-        WT wo = w[row];
-        WT wn = wo * edw;
-        w[row] = wn;
-        s += (sizeof(WT) == 8) ? (double)wo : ((double)wn - (double)wo);
-      }
-      s = wave_sum(s);
-      if (lane == 0) {
-        double2* pp = &a.pat[a.rp[e0].y];
-        pp->x += (sizeof(WT) == 8) ? s * em1 : s;
-      }
+      tile_a_mark<WT>(a, p.t, Gl, Hl, bits, p0);
     }
   }
+  for (int t = p.t + kWorkers; t < p.t1; t += kWorkers) tile_a_mark<WT>(a, t, Gl, Hl, bits, p0);
+}
+
+template <typename WT>
+__device__ __forceinline__ void phase_b_cached(const KArgs& a, const Pf& p, const Cache& c, double ed, double em1) {
+  const int lane = threadIdx.x & 63;
+  WT* __restrict__ w = (WT*)a.w;
+  if (p.t < p.t1) {
+    if (p.len <= 64) {
+      const bool act = lane < p.len;
+      const WT wo = (WT)c.wv;
+      const WT wn = wo * (WT)ed;
+      if (act) w[p.rp.x] = wn;
+      if (sizeof(WT) == 8) {
+        if (c.head) a.pat[p.rp.y].x = c.den + c.num * em1;
+      } else {
+        bool head;
+        int seg_end;
+        seg_layout(p.rp.y, lane, p.len, head, seg_end);
+        double s = seg_sum_v((double)wn - (double)wo, lane, seg_end);
+        if (head) a.pat[p.rp.y].x = c.den + s;
+      }
+    } else {
+      tile_b<WT>(a, p.t, ed, em1);
+    }
+  }
+  for (int t = p.t + kWorkers; t < p.t1; t += kWorkers) tile_b<WT>(a, t, ed, em1);
 }
 
 // Exact recomputation of w = L x exp(X beta) and den = M w for patients
-// [p0, p1) (the dense evaluation of Listing 1's role, plus Step 3).
+// [p0, p1) (the dense evaluation of Listing 1's role, plus Step 3).  beta_j
+// is read at beta[j * stride].
 template <typename WT>
-__device__ __forceinline__ void refresh_range(const KArgs& a, const double* beta, int p0, int p1, int tid, int nthreads) {
+__device__ __forceinline__ void refresh_range(const KArgs& a, const double* beta, int p0, int p1, int tid,
+                                              int nthreads, int stride = 1) {
   WT* __restrict__ w = (WT*)a.w;
   for (int i = p0 + tid; i < p1; i += nthreads) {
     double den = 0.0;
     for (int k = a.pptr[i]; k < a.pptr[i + 1]; ++k) {
       double eta = 0.0;
-      for (int c = a.era_ptr[k]; c < a.era_ptr[k + 1]; ++c) eta += beta[a.era_col[c]];
+      for (int c = a.era_ptr[k]; c < a.era_ptr[k + 1]; ++c) eta += beta[(size_t)a.era_col[c] * stride];
       WT wk = Prec<WT>::weight(a.offset[k], eta);
       w[k] = wk;
       den += (double)wk;
@@ -369,7 +596,7 @@ __device__ __forceinline__ bool objective(const KArgs& a, const double* sbeta, c
   block_sum<2>(bl, bsum, red);
   if (tid == 0) { bc[4] = bsum[0]; bc[5] = bsum[1]; }
   double tot[4];
-  bool ok = allreduce_nonneg<4>(a.oslots, oseq, a.G, a.ctrl, part, tot, bc, bci);
+  bool ok = allreduce_nonneg<4>(a.oslots, a.oslots2, oseq, a.G, a.ctrl, part, tot, bc, bci);
   out3[0] = bc[4] - (tot[0] - tot[1]);  // loglik
   out3[1] = out3[0] + bc[5];            // logpost
   out3[2] = tot[2];                     // sum |delta eta|
@@ -410,42 +637,89 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
   }
   int sweep = 0, converged = 0;
   double L = 0.0, P = 0.0;
+  const int wave = tid >> 6, lane = tid & 63;
+  const bool worker = wave < kWorkers;
+  unsigned* bits0 = (unsigned*)(lds_dyn + 3 * a.J);   // patients of even coordinates
+  unsigned* bits1 = bits0 + a.nbits;                  // patients of odd coordinates
   while (ok && sweep < a.n_sweeps) {
-    if (a.criterion == SCCS_CRIT_ABS_DXBETA) {
+    if (a.criterion == SCCS_CRIT_ABS_DXBETA)
       for (int j = tid; j < a.J; j += kBlock) sprev[j] = sbeta[j];
-      __syncthreads();
+    for (int i = tid; i < 2 * a.nbits; i += kBlock) bits0[i] = 0u;
+    // pipeline start: indices of coordinates 0 and 1; nothing speculated
+    Pf pf_cur, pf_next;
+    {
+      int t0, t1;
+      pf_range(a, 0, t0, t1);
+      pf_tile(a, t0, t1, pf_cur);
+      pf_range(a, a.J > 1 ? 1 : 0, t0, t1);
+      pf_tile(a, t0, t1, pf_next);
     }
+    Cache c_cur, c_next;
+    c_cur.valid = false;
+    double ytx_cur = (wave == kPoller && lane == 0) ? a.ytx[0] : 0.0;
+    __syncthreads();
     for (int j = 0; j < a.J; ++j) {
-      double ytxj = 0.0;
-      if (tid == 0) ytxj = a.ytx[j];
+      unsigned* bits_cur = (j & 1) ? bits1 : bits0;
+      unsigned* bits_prev = (j & 1) ? bits0 : bits1;
+      const bool has_next = j + 1 < a.J;
+      int nt0 = 0, nt1 = 0;
+      if (j + 2 < a.J) pf_range(a, j + 2, nt0, nt1);
+      const double ytx_next = (wave == kPoller && lane == 0 && has_next) ? a.ytx[j + 1] : 0.0;
+
+      // phase A: validate the speculative first tile, then accumulate
       double Gl = 0.0, Hl = 0.0;
-      phase_a<WT>(a, j, Gl, Hl);
-      double loc[2] = {Gl, Hl}, part[2], tot[2];
-      block_sum<2>(loc, part, red);
-      if (!allreduce_nonneg<2>(a.slots, seq++, a.G, a.ctrl, part, tot, bc, bci)) { ok = false; break; }
-      if (tid == 0) {
-        double g = ytxj - tot[0], h = -tot[1];
-        double d = 0.0;
-        int bad = !(isfinite(g) && isfinite(h));
-        if (!bad) {
-          double bj = sbeta[j], tr = strust[j];
-          double dv = prior_step(a.prior_kind, a.var, a.lambda, bj, g, h);
-          d = fmin(fmax(dv, -tr), tr);
-          strust[j] = fmax(2.0 * fabs(d), 0.5 * tr);
-          double nb = bj + d;
-          if (!isfinite(nb)) { bad = 1; d = 0.0; }
-          else sbeta[j] = nb;
-        }
-        bc[0] = d;
-        bc[1] = exp(d);
-        bc[2] = expm1(d);
-        bci[1] = bad;
+      if (worker) {
+        if (!c_cur.valid || (j > 0 && first_tile_stale(pf_cur, bits_prev, p0))) gather_first<WT>(a, pf_cur, c_cur);
+        phase_a_cached<WT>(a, pf_cur, c_cur, Gl, Hl, bits_cur, p0);
       }
+      double loc[2] = {Gl, Hl}, part[2] = {0.0, 0.0};
+      block_sum_to<2>(loc, part, red, kPoller);
+      Pf pf_next2;
+      pf_next2.t = pf_next2.t1 = 0;
+      c_next.valid = false;
+      if (worker) {
+        // in the shadow of the reduction: clear the bitmap of coordinate
+        // j+1, gather coordinate j+1 speculatively, load indices of j+2
+        unsigned* bits_next = bits_prev;
+        for (int i = tid; i < a.nbits; i += kWorkers * 64) bits_next[i] = 0u;
+        if (has_next) gather_first<WT>(a, pf_next, c_next);
+        if (j + 2 < a.J) pf_tile(a, nt0, nt1, pf_next2);
+      } else {
+        // device-wide reduction, then the Newton / trust-region step (Eq. 4)
+        double tot[2];
+        const bool okr = allreduce2_wave<2>(a.slots, a.slots2, seq, a.G, a.ctrl, part, tot);
+        if (lane == 0) {
+          double g = ytx_cur - tot[0], h = -tot[1];
+          double d = 0.0;
+          int bad = !(isfinite(g) && isfinite(h));
+          if (okr && !bad) {
+            double bj = sbeta[j], tr = strust[j];
+            double dv = prior_step(a.prior_kind, a.inv_var, a.lambda, bj, g, h);
+            d = fmin(fmax(dv, -tr), tr);
+            strust[j] = fmax(2.0 * fabs(d), 0.5 * tr);
+            double nb = bj + d;
+            if (!isfinite(nb)) { bad = 1; d = 0.0; }
+            else sbeta[j] = nb;
+          }
+          const double em1 = expm1(d);
+          bc[0] = d;
+          bc[1] = 1.0 + em1;
+          bc[2] = em1;
+          bci[0] = okr ? 1 : 0;
+          bci[1] = bad;
+        }
+      }
+      ++seq;
       __syncthreads();
       const double d = bc[0], ed = bc[1], em1 = bc[2];
+      if (!bci[0]) { ok = false; break; }
       if (bci[1]) { status = SCCS_ERR_NUMERIC; ok = false; break; }
-      if (d != 0.0) phase_b<WT>(a, j, ed, em1);
+      if (worker && d != 0.0) phase_b_cached<WT>(a, pf_cur, c_cur, ed, em1);
       __syncthreads();
+      pf_cur = pf_next;
+      pf_next = pf_next2;
+      c_cur = c_next;
+      ytx_cur = ytx_next;
     }
     if (!ok) break;
     ++sweep;
@@ -514,7 +788,7 @@ __global__ void __launch_bounds__(kBlock) k_diag(KArgs a) {
     phase_a<WT>(a, j, Gl, Hl);
     double loc[2] = {Gl, Hl}, part[2], tot[2];
     block_sum<2>(loc, part, red);
-    bool ok = allreduce_nonneg<2>(a.slots, seq++, a.G, a.ctrl, part, tot, bc, bci);
+    bool ok = allreduce_nonneg<2>(a.slots, a.slots2, seq++, a.G, a.ctrl, part, tot, bc, bci);
     if (b == 0 && tid == 0 && ok) { a.ctrl->g = a.ytx[j] - tot[0]; a.ctrl->h = -tot[1]; }
   }
   __syncthreads();
@@ -563,11 +837,19 @@ __global__ void k_refresh(KArgs a) {
   refresh_range<WT>(a, a.beta, 0, a.N, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
+// Same, with beta taken from the x members of a (beta, trust) array.
+template <typename WT>
+__global__ void k_refresh_bt(KArgs a, const double2* bt) {
+  refresh_range<WT>(a, (const double*)bt, 0, a.N, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, 2);
+}
+
 template __global__ void k_ccd<double>(KArgs);
 template __global__ void k_ccd<float>(KArgs);
 template __global__ void k_diag<double>(KArgs);
 template __global__ void k_diag<float>(KArgs);
 template __global__ void k_refresh<double>(KArgs);
 template __global__ void k_refresh<float>(KArgs);
+template __global__ void k_refresh_bt<double>(KArgs, const double2*);
+template __global__ void k_refresh_bt<float>(KArgs, const double2*);
 
 }  // namespace sccs

@@ -23,7 +23,9 @@ CRIT_FIXED, CRIT_REL_LOGPOST, CRIT_ABS_DXBETA = 0, 1, 2
 
 EXPORTS = ("sccs_default_options", "sccs_query_workspace", "sccs_create", "sccs_destroy",
            "sccs_set_prior", "sccs_set_beta", "sccs_get_beta", "sccs_sweep", "sccs_fit",
-           "sccs_grad_hess", "sccs_objective", "sccs_last_kernel_ms", "sccs_last_error")
+           "sccs_grad_hess", "sccs_objective", "sccs_last_kernel_ms", "sccs_last_error",
+           "sccs_batch_query_workspace", "sccs_batch_create", "sccs_batch_run", "sccs_batch_get",
+           "sccs_batch_last_kernel_ms", "sccs_batch_destroy", "sccs_batch_last_error")
 
 
 class SccsError(RuntimeError):
@@ -50,6 +52,12 @@ class FitOpts_(ctypes.Structure):
     _fields_ = [("criterion", ctypes.c_int32), ("max_sweeps", ctypes.c_int32), ("tol", ctypes.c_double)]
 
 
+class FitSpec_(ctypes.Structure):
+    _fields_ = [("problem", ctypes.c_int32), ("n_links", ctypes.c_int32),
+                ("prior_kind", ctypes.c_void_p), ("variance", ctypes.c_void_p),
+                ("patient_weight", ctypes.c_void_p)]
+
+
 class FitResult_(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("loglik", ctypes.c_double), ("logpost", ctypes.c_double)]
@@ -58,13 +66,29 @@ class FitResult_(ctypes.Structure):
 _lib = None
 
 
+def _hip_runtimes_mapped():
+    try:
+        with open("/proc/self/maps") as f:
+            return sorted({l.split()[-1] for l in f if "libamdhip64" in l})
+    except OSError:
+        return []
+
+
 def lib() -> ctypes.CDLL:
-    """Open libsccs.so; raises if it has not been built."""
+    """Open libsccs.so; raises if it has not been built.
+
+    torch is imported first so that the library binds to the HIP runtime
+    torch already uses: its streams and device memory are handed to the
+    library, which is only valid within one runtime."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} not built; run python -m paper_1208_0945_amd.build")
+        import torch  # noqa: F401  (loads torch's HIP runtime first)
         L = ctypes.CDLL(LIB_PATH)
+        maps = _hip_runtimes_mapped()
+        if len(maps) > 1:
+            raise RuntimeError(f"two HIP runtimes are loaded ({maps}); import torch before libsccs")
         H = ctypes.c_void_p
         dp = ctypes.POINTER(ctypes.c_double)
         L.sccs_default_options.argtypes = [ctypes.POINTER(Options_)]
@@ -84,8 +108,18 @@ def lib() -> ctypes.CDLL:
         L.sccs_last_kernel_ms.argtypes = [H, dp]
         L.sccs_last_error.argtypes = [H]
         L.sccs_last_error.restype = ctypes.c_char_p
+        L.sccs_batch_query_workspace.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                                                 ctypes.POINTER(Options_), ctypes.POINTER(ctypes.c_size_t)]
+        L.sccs_batch_create.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                                        ctypes.POINTER(Options_), ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(H)]
+        L.sccs_batch_run.argtypes = [H, ctypes.POINTER(FitOpts_)]
+        L.sccs_batch_get.argtypes = [H, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(FitResult_)]
+        L.sccs_batch_last_kernel_ms.argtypes = [H, dp]
+        L.sccs_batch_destroy.argtypes = [H]
+        L.sccs_batch_last_error.argtypes = [H]
+        L.sccs_batch_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
-            if name not in ("sccs_default_options", "sccs_last_error"):
+            if name not in ("sccs_default_options", "sccs_last_error", "sccs_batch_last_error"):
                 getattr(L, name).restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -233,3 +267,88 @@ class Handle:
         ms = ctypes.c_double()
         self._check(lib().sccs_last_kernel_ms(self.h, ctypes.byref(ms)))
         return ms.value
+
+
+class FitSpec:
+    """One fit of a batch: a problem index, a chain of (prior kind, variance)
+    links visited with warm starts, and optional patient weights."""
+
+    def __init__(self, problem: int, links, weight=None):
+        self.problem = int(problem)
+        self.kinds = np.ascontiguousarray([int(k) for k, _ in links], dtype=np.int32)
+        self.vars = np.ascontiguousarray([float(v) for _, v in links], dtype=np.float64)
+        self.weight = None if weight is None else _arr(weight, np.int32)
+
+    def struct(self) -> FitSpec_:
+        return FitSpec_(self.problem, len(self.kinds), self.kinds.ctypes.data, self.vars.ctypes.data,
+                        None if self.weight is None else self.weight.ctypes.data)
+
+
+class Batch:
+    """Many fits in one persistent launch (sccs_batch_*)."""
+
+    def __init__(self, probs, specs, precision: int = PREC_FP64, n_workgroups: int = 0,
+                 refresh_period: int = -1, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self._probs = [ProblemArrays(p) for p in probs]
+        self._specs = list(specs)
+        parr = (Problem_ * len(self._probs))(*[P.s for P in self._probs])
+        sarr = (FitSpec_ * len(self._specs))(*[s.struct() for s in self._specs])
+        self._parr, self._sarr = parr, sarr
+        o = options(precision, n_workgroups, refresh_period, stream.cuda_stream)
+        L = lib()
+        n = ctypes.c_size_t()
+        st = L.sccs_batch_query_workspace(ctypes.addressof(parr), len(self._probs), ctypes.addressof(sarr),
+                                          len(self._specs), ctypes.byref(o), ctypes.byref(n))
+        if st != OK:
+            raise SccsError(st, L.sccs_batch_last_error(None).decode())
+        self.workspace_bytes = int(n.value)
+        self.ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device="cuda")
+        ptr = (self.ws.data_ptr() + 255) & ~255
+        h = ctypes.c_void_p()
+        st = L.sccs_batch_create(ctypes.addressof(parr), len(self._probs), ctypes.addressof(sarr),
+                                 len(self._specs), ctypes.byref(o), ptr, self.workspace_bytes, ctypes.byref(h))
+        if st != OK:
+            raise SccsError(st, L.sccs_batch_last_error(None).decode())
+        self.h = h
+        self.J = self._probs[0].n_cols
+
+    def _check(self, st):
+        if st != OK:
+            raise SccsError(st, lib().sccs_batch_last_error(self.h).decode())
+
+    def run(self, criterion: int = CRIT_REL_LOGPOST, max_sweeps: int = 100, tol: float = 1e-8):
+        fo = FitOpts_(int(criterion), int(max_sweeps), float(tol))
+        self._check(lib().sccs_batch_run(self.h, ctypes.byref(fo)))
+
+    def get(self, fit: int, link: int = 0):
+        b = np.zeros(self.J)
+        r = FitResult_()
+        self._check(lib().sccs_batch_get(self.h, int(fit), int(link), b.ctypes.data, ctypes.byref(r)))
+        return b, {"sweeps": r.sweeps, "converged": bool(r.converged), "loglik": r.loglik, "logpost": r.logpost}
+
+    def last_kernel_ms(self) -> float:
+        ms = ctypes.c_double()
+        self._check(lib().sccs_batch_last_kernel_ms(self.h, ctypes.byref(ms)))
+        return ms.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sccs_batch_destroy(self.h)
+            self.h = None
+            self.ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -20,12 +20,18 @@ def declared_functions():
 
 
 def test_library_exports_every_declared_function():
+    sccs.lib()                       # binds to torch's HIP runtime first
     lib = ctypes.CDLL(sccs.LIB_PATH)
     names = declared_functions()
     assert len(names) >= 12
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(sccs.EXPORTS)
+
+
+def test_single_hip_runtime_loaded():
+    sccs.lib()
+    assert len(sccs._hip_runtimes_mapped()) == 1
 
 
 def test_last_error_never_null():
@@ -104,3 +110,28 @@ def test_null_arguments_rejected():
     assert L.sccs_destroy(None) == sccs.OK
     assert L.sccs_set_prior(None, 1, 1.0) == sccs.ERR_INVALID_ARG
     assert L.sccs_sweep(None, 1, None) == sccs.ERR_INVALID_ARG
+
+
+def _batch_query(probs, specs, **opt):
+    parr = (sccs.Problem_ * len(probs))(*[sccs.ProblemArrays(p).s for p in probs])
+    keep = [sccs.ProblemArrays(p) for p in probs]
+    parr = (sccs.Problem_ * len(keep))(*[k.s for k in keep])
+    sarr = (sccs.FitSpec_ * len(specs))(*[s.struct() for s in specs])
+    n = ctypes.c_size_t()
+    o = sccs.options(**opt)
+    return sccs.lib().sccs_batch_query_workspace(ctypes.addressof(parr), len(keep), ctypes.addressof(sarr),
+                                                 len(specs), ctypes.byref(o), ctypes.byref(n))
+
+
+def test_batch_specs_validated_on_host():
+    p = _tiny()
+    ok_link = [(sccs.PRIOR_NORMAL, 1.0)]
+    assert _batch_query([p], [sccs.FitSpec(1, ok_link)]) == sccs.ERR_INVALID_ARG       # bad problem index
+    assert _batch_query([p], [sccs.FitSpec(0, [(sccs.PRIOR_LAPLACE, 0.0)])]) == sccs.ERR_INVALID_ARG
+    assert _batch_query([p], [sccs.FitSpec(0, [(7, 1.0)])]) == sccs.ERR_INVALID_ARG
+    assert _batch_query([p], [sccs.FitSpec(0, [])]) == sccs.ERR_INVALID_ARG
+    w = np.ones(p.n_patients, np.int32); w[0] = -2
+    assert _batch_query([p], [sccs.FitSpec(0, ok_link, weight=w)]) == sccs.ERR_INVALID_ARG
+    other = synth.tiny(n_patients=30, n_cols=5, seed=2)
+    assert _batch_query([p, other], [sccs.FitSpec(0, ok_link)]) == sccs.ERR_INVALID_ARG  # J differs
+    assert _batch_query([p], [sccs.FitSpec(0, ok_link)] * 65) == sccs.ERR_INVALID_ARG    # > 64 fits

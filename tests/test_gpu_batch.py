@@ -1,0 +1,105 @@
+"""GPU parity of the batched form: several fits advanced in lockstep in one
+persistent launch, each checked against the FP64 oracle run fit by fit.
+
+Configurations mirror the batched workloads at reduced size: independent
+outcomes over one shared drug vocabulary with uneven patient counts, and
+patient-level cross-validation folds walking a prior-variance path with warm
+starts (trust region reset per link).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1208_0945_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-9
+
+
+@pytest.fixture(scope="module")
+def sccs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1208_0945_amd import sccs as s
+    s.lib()
+    return s
+
+
+def rel_inf(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def outcomes(n_fits, n_cols=60, lo=2000, hi=30000, seed=0):
+    sizes = synth.outcome_sizes(n_fits, lo=lo, hi=hi, seed=seed)
+    return synth.batched_outcomes(n_fits, n_cols=n_cols, seed=seed, sizes=sizes)
+
+
+@pytest.mark.parametrize("n_fits,n_workgroups", [(1, 0), (5, 0), (20, 0), (5, 7)])
+def test_outcomes_fixed_sweeps_match_oracle(sccs, n_fits, n_workgroups):
+    probs = outcomes(n_fits)
+    with sccs.Batch(probs, [sccs.FitSpec(f, [(sccs.PRIOR_LAPLACE, 2.0)]) for f in range(n_fits)],
+                    n_workgroups=n_workgroups) as b:
+        b.run(sccs.CRIT_FIXED, max_sweeps=6)
+        for f, p in enumerate(probs):
+            beta, res = b.get(f, 0)
+            ref = oracle.ccd(p, oracle.PRIOR_LAPLACE, 2.0, 6)
+            assert res["sweeps"] == 6
+            assert rel_inf(beta, ref["beta"]) <= FP64_TOL, f
+            assert abs(res["logpost"] - ref["logpost"]) <= 1e-10 * abs(ref["logpost"])
+
+
+def test_outcomes_to_convergence(sccs):
+    probs = outcomes(6, seed=3)
+    with sccs.Batch(probs, [sccs.FitSpec(f, [(sccs.PRIOR_NORMAL, 0.5)]) for f in range(6)]) as b:
+        b.run(sccs.CRIT_REL_LOGPOST, max_sweeps=300, tol=1e-10)
+        for f, p in enumerate(probs):
+            beta, res = b.get(f, 0)
+            ref = oracle.ccd(p, oracle.PRIOR_NORMAL, 0.5, 300, oracle.CRIT_REL_LOGPOST, 1e-10)
+            assert res["converged"] and abs(res["sweeps"] - ref["sweeps"]) <= 1
+            assert rel_inf(beta, ref["beta"]) <= 1e-7
+
+
+def test_cv_folds_with_warm_started_prior_path(sccs):
+    """10 folds x a 4-step Laplace variance path (ascending, warm starts).
+    Each link runs a fixed number of sweeps so the trajectory is compared
+    exactly; the oracle replays the same warm-start chain."""
+    prob = synth.zipf_problem("cvsmall", 6000, 50, 0.1, seed_path=(9, 1))
+    folds = synth.cv_folds(prob.n_patients, 10, seed=2)
+    grid = [0.01, 0.1, 1.0, 10.0]
+    specs = [sccs.FitSpec(0, [(sccs.PRIOR_LAPLACE, v) for v in grid], weight=(folds != k).astype(np.int32))
+             for k in range(10)]
+    with sccs.Batch([prob], specs) as b:
+        b.run(sccs.CRIT_FIXED, max_sweeps=4)
+        for k in range(10):
+            w = (folds != k).astype(np.int32)
+            beta = np.zeros(prob.n_cols)
+            for l, v in enumerate(grid):
+                ref = oracle.ccd(prob, oracle.PRIOR_LAPLACE, v, 4, beta0=beta, weight=w)
+                beta = ref["beta"]
+                got, res = b.get(k, l)
+                assert res["sweeps"] == 4
+                assert rel_inf(got, beta) <= FP64_TOL, (k, l)
+
+
+def test_batch_mixed_precision(sccs):
+    probs = outcomes(4, seed=5)
+    with sccs.Batch(probs, [sccs.FitSpec(f, [(sccs.PRIOR_LAPLACE, 2.0)]) for f in range(4)],
+                    precision=sccs.PREC_MIXED) as b:
+        b.run(sccs.CRIT_FIXED, max_sweeps=10)
+        for f, p in enumerate(probs):
+            beta, _ = b.get(f, 0)
+            ref = oracle.ccd(p, oracle.PRIOR_LAPLACE, 2.0, 10)
+            assert rel_inf(beta, ref["beta"]) <= 1e-6
+
+
+def test_batch_rejects_bad_specs(sccs):
+    probs = outcomes(2)
+    with pytest.raises(sccs.SccsError):
+        sccs.Batch(probs, [sccs.FitSpec(5, [(sccs.PRIOR_NORMAL, 1.0)])])
+    with pytest.raises(sccs.SccsError):
+        sccs.Batch(probs, [sccs.FitSpec(0, [(sccs.PRIOR_NORMAL, -1.0)])])
+    other = synth.tiny(n_cols=7)
+    with pytest.raises(sccs.SccsError):
+        sccs.Batch([probs[0], other], [sccs.FitSpec(0, [(sccs.PRIOR_NORMAL, 1.0)])])
