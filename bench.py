@@ -79,6 +79,26 @@ def run_form(sccs, prob, precision, steps, warmup, c, p):
     return {"wall_s": wall, "kernel_ms": kernel_ms, "bytes": algo_bytes, "beta": beta}
 
 
+def profiled_traffic(kernel_ms):
+    """HBM bytes per launch of the sweep kernel from the committed counter
+    summary, if the kernel sources are unchanged since the counters were
+    taken; otherwise None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_ccd_mid_fp64_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    csrc = os.path.join(ROOT, "paper_1208_0945_amd", "csrc")
+    src = "".join(open(os.path.join(csrc, f)).read() for f in ("sccs_kernels.hpp", "sccs_device.hpp"))
+    if hashlib.sha256(src.encode()).hexdigest()[:16] != kv.get("kernel_source_sha"):
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(prob, sweeps):
     import oracle
     oracle.build(force=False)
@@ -95,6 +115,82 @@ def cpu_baseline(prob, sweeps):
                       f"(-O2), one-time setup ({t_setup:.2f} s) subtracted; {t:.1f} s total"}
 
 
+def copy_calibration(n_bytes: int = 1 << 30, reps: int = 3):
+    """A plain device copy of known size, to scale the FETCH_SIZE and
+    WRITE_SIZE counters of the sweep kernel to bytes."""
+    import torch
+    src = torch.empty(n_bytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_each_way": n_bytes, "reps": reps}), flush=True)
+
+
+def batched_outcomes_bench(sccs, synth, steps, precision):
+    """64 outcomes over one J = 1000 vocabulary, patient counts log-uniform
+    10k..2M, Laplace lambda = 1: one launch runs `steps` sweeps of all 64."""
+    t0 = time.perf_counter()
+    sizes = synth.outcome_sizes(64)
+    probs = synth.batched_outcomes(64, n_cols=1000, sizes=sizes, progress=lambda f: (
+        print(f"[bench] outcome {f} generated", file=sys.stderr, flush=True) if f % 8 == 7 else None))
+    print(f"[bench] generated 64 outcomes ({sum(p.n_patients for p in probs)} patients, "
+          f"{sum(p.nnz for p in probs)} nonzeros) in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    specs = [sccs.FitSpec(f, [(sccs.PRIOR_LAPLACE, 2.0)]) for f in range(len(probs))]
+    stats = [column_stats(p) for p in probs]
+    t0 = time.perf_counter()
+    with sccs.Batch(probs, specs, precision=precision) as b:
+        print(f"[bench] batch set up in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+        b.run(sccs.CRIT_FIXED, max_sweeps=1)            # warm-up launch (the chains restart from its beta)
+        t0 = time.perf_counter()
+        b.run(sccs.CRIT_FIXED, max_sweeps=steps)
+        wall = time.perf_counter() - t0
+        ms = b.last_kernel_ms()
+    # algorithmic bytes with every coordinate active (upper bound on phase B)
+    tot = sum(bytes_per_sweep(c, p_, np.ones(len(c), bool), precision) for c, p_ in stats) * steps
+    return {"metric": "batched outcomes: fit-sweeps/s (64 fits, J=1000, one launch)",
+            "value": 64 * steps / wall, "unit": "fit-sweeps/s", "steps": steps, "kernel_ms": ms,
+            "achieved_GBs_upper": tot / (ms * 1e-3) / 1e9,
+            "dtype": "f64" if precision == 0 else "mixed",
+            "config": {"workload": "64 outcomes, J=1000 Zipf(1.1), N log-uniform 1e4..2e6, Laplace lambda=1",
+                       "n_patients_total": int(sum(p.n_patients for p in probs)),
+                       "nnz_total": int(sum(p.nnz for p in probs))}}
+
+
+def cv_bench(sccs, synth, precision, max_sweeps, tol, n_folds=10, n_grid=16):
+    """The mid problem under 10-fold patient-level cross-validation x 16
+    Laplace variances logspace(-3, 1): 10 fold chains walk the grid upward
+    with warm starts, all in one launch; then the held-out log-likelihood
+    (Eq. 2 over the held-out patients) of every (fold, variance) fit."""
+    prob = synth.mid()
+    folds = synth.cv_folds(prob.n_patients, n_folds)
+    grid = synth.prior_grid(n_grid)
+    specs = [sccs.FitSpec(0, [(sccs.PRIOR_LAPLACE, float(v)) for v in grid], weight=(folds != k).astype(np.int32))
+             for k in range(n_folds)]
+    with sccs.Batch([prob], specs, precision=precision) as b:
+        t0 = time.perf_counter()
+        b.run(sccs.CRIT_REL_LOGPOST, max_sweeps=max_sweeps, tol=tol)
+        wall = time.perf_counter() - t0
+        ms = b.last_kernel_ms()
+        res = [[b.get(k, l) for l in range(n_grid)] for k in range(n_folds)]
+    sweeps = sum(r[1]["sweeps"] for row in res for r in row)
+    heldout = np.zeros((n_folds, n_grid))
+    for k in range(n_folds):
+        with sccs.Handle(prob, weight=(folds == k).astype(np.int32)) as h:
+            h.set_prior(sccs.PRIOR_NONE, 1.0)
+            for l in range(n_grid):
+                h.set_beta(res[k][l][0])
+                heldout[k, l] = h.objective()[0]
+    mean = heldout.mean(axis=0)
+    return {"metric": "batched CV: fit-sweeps/s (10 folds x 16 Laplace variances, warm starts, one launch)",
+            "value": sweeps / wall, "unit": "fit-sweeps/s", "kernel_ms": ms, "total_fit_sweeps": int(sweeps),
+            "dtype": "f64" if precision == 0 else "mixed",
+            "best_variance": float(grid[int(np.argmax(mean))]),
+            "heldout_loglik_mean_by_variance": [float(x) for x in mean],
+            "config": {"workload": f"mid SCCS ({prob.n_patients} patients, J={prob.n_cols}) x 10 folds x 16 variances",
+                       "max_sweeps_per_link": max_sweeps, "tol": tol}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +201,11 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=4)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", choices=["mid", "outcomes", "cv"], default="mid")
+    ap.add_argument("--mixed-only", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--cv-max-sweeps", type=int, default=50)
+    ap.add_argument("--cv-tol", type=float, default=1e-8)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -115,6 +216,17 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     from paper_1208_0945_amd import sccs, synth
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.workload == "outcomes":
+        for prec in ((1,) if args.mixed_only else (0, 1)):
+            print(json.dumps(batched_outcomes_bench(sccs, synth, args.steps, prec)), flush=True)
+        return
+    if args.workload == "cv":
+        print(json.dumps(cv_bench(sccs, synth, 1 if args.mixed_only else 0, args.cv_max_sweeps, args.cv_tol)),
+              flush=True)
+        return
 
     t0 = time.perf_counter()
     prob = synth.mid(n_patients=args.patients, n_cols=args.cols)
@@ -143,7 +255,7 @@ def main():
                    "n_patients": prob.n_patients, "n_eras": prob.n_rows, "n_cols": prob.n_cols,
                    "nnz": prob.nnz, "prior": "laplace", "variance": 2.0, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(ms),
                      "kernel": "k_ccd<double>", "kernel_ms_mean": ms,
                      "algo_bytes_per_launch": float(np.mean(fp["bytes"]))},
     }

@@ -219,7 +219,7 @@ def outcome_sizes(n_fits: int = 64, lo: float = 1e4, hi: float = 2e6, seed: int 
 
 
 def batched_outcomes(n_fits: int = 64, n_cols: int = 1000, seed: int = 0,
-                     sizes: Optional[Sequence[int]] = None) -> List[Problem]:
+                     sizes: Optional[Sequence[int]] = None, progress=None) -> List[Problem]:
     """Independent outcomes over one shared J-drug vocabulary (shared Zipf
     popularity), patient counts log-uniform 10k..2M."""
     if sizes is None:
@@ -231,6 +231,8 @@ def batched_outcomes(n_fits: int = 64, n_cols: int = 1000, seed: int = 0,
         beta = sparse_beta(n_cols, 50, 0.7, _rng(4, seed, 10, f))
         out.append(make_problem(f"outcome{f}", int(n), n_cols, 9.0, probs, beta,
                                 seed_path=(4, seed, f)))
+        if progress is not None:
+            progress(f)
     return out
 
 
