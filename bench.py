@@ -173,14 +173,8 @@ def cv_bench(sccs, synth, precision, max_sweeps, tol, n_folds=10, n_grid=16):
         wall = time.perf_counter() - t0
         ms = b.last_kernel_ms()
         res = [[b.get(k, l) for l in range(n_grid)] for k in range(n_folds)]
+        heldout = np.array([[b.heldout(k, l) for l in range(n_grid)] for k in range(n_folds)])
     sweeps = sum(r[1]["sweeps"] for row in res for r in row)
-    heldout = np.zeros((n_folds, n_grid))
-    for k in range(n_folds):
-        with sccs.Handle(prob, weight=(folds == k).astype(np.int32)) as h:
-            h.set_prior(sccs.PRIOR_NONE, 1.0)
-            for l in range(n_grid):
-                h.set_beta(res[k][l][0])
-                heldout[k, l] = h.objective()[0]
     mean = heldout.mean(axis=0)
     return {"metric": "batched CV: fit-sweeps/s (10 folds x 16 Laplace variances, warm starts, one launch)",
             "value": sweeps / wall, "unit": "fit-sweeps/s", "kernel_ms": ms, "total_fit_sweeps": int(sweeps),
@@ -189,6 +183,49 @@ def cv_bench(sccs, synth, precision, max_sweeps, tol, n_folds=10, n_grid=16):
             "heldout_loglik_mean_by_variance": [float(x) for x in mean],
             "config": {"workload": f"mid SCCS ({prob.n_patients} patients, J={prob.n_cols}) x 10 folds x 16 variances",
                        "max_sweeps_per_link": max_sweeps, "tol": tol}}
+
+
+def full_bench(sccs, synth, steps):
+    """Full-scale workload, precision form against the FP64 GPU path: 10M
+    patients, ~100M eras, J = 4000 Zipf drugs (p_j = 0.482 rank^-1.1),
+    Normal prior variance 0.5; `steps` sweeps each; then a seeded 1% patient
+    subsample refit to convergence by the GPU (both forms) and the oracle."""
+    import oracle
+    t0 = time.perf_counter()
+    prob = synth.full()
+    print(f"[bench] generated {prob.summary()} in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    out = {"metric": "full-scale SCCS: sweeps/s, FP64 and mixed, and mixed error vs the FP64 oracle",
+           "config": {"workload": "full SCCS: 10M patients, J=4000 Zipf(1.1) p0=0.482, Normal var 0.5",
+                      "n_patients": prob.n_patients, "n_eras": prob.n_rows, "nnz": prob.nnz}}
+    betas = {}
+    for prec, name in ((0, "fp64"), (1, "mixed")):
+        t0 = time.perf_counter()
+        with sccs.Handle(prob, precision=prec) as h:
+            print(f"[bench] {name} handle set up in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+            h.set_prior(sccs.PRIOR_NORMAL, 0.5)
+            h.sweep(1)
+            t0 = time.perf_counter()
+            h.sweep(steps)
+            wall = time.perf_counter() - t0
+            out[name] = {"sweeps_per_s": steps / wall, "kernel_ms_per_sweep": h.last_kernel_ms() / steps}
+            betas[name] = h.get_beta()[0]
+        print(f"[bench] {name}: {out[name]}", file=sys.stderr, flush=True)
+    out["mixed_vs_fp64_gpu_rel_err"] = float(np.max(np.abs(betas["mixed"] - betas["fp64"])) /
+                                            np.max(np.abs(betas["fp64"])))
+    sub = synth.subsample_patients(prob, 0.01)
+    del prob
+    ref = oracle.ccd(sub, oracle.PRIOR_NORMAL, 0.5, 500, oracle.CRIT_REL_LOGPOST, 1e-12)
+    print(f"[bench] oracle refit of the 1% subsample: {ref['sweeps']} sweeps", file=sys.stderr, flush=True)
+    errs = {}
+    for prec, name in ((0, "fp64"), (1, "mixed")):
+        with sccs.Handle(sub, precision=prec) as h:
+            h.set_prior(sccs.PRIOR_NORMAL, 0.5)
+            h.sweep(ref["sweeps"])
+            b = h.get_beta()[0]
+        errs[name] = float(np.max(np.abs(b - ref["beta"])) / np.max(np.abs(ref["beta"])))
+    out["subsample_refit"] = {"n_patients": sub.n_patients, "nnz": sub.nnz, "oracle_sweeps": ref["sweeps"],
+                              "rel_err_vs_oracle": errs}
+    return out
 
 
 def main():
@@ -201,7 +238,8 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=4)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=["mid", "outcomes", "cv"], default="mid")
+    ap.add_argument("--workload", choices=["mid", "outcomes", "cv", "full"], default="mid")
+    ap.add_argument("--tune", action="store_true", help="run the autotuner on the mid workload and print its table")
     ap.add_argument("--mixed-only", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--cv-max-sweeps", type=int, default=50)
@@ -222,6 +260,14 @@ def main():
     if args.workload == "outcomes":
         for prec in ((1,) if args.mixed_only else (0, 1)):
             print(json.dumps(batched_outcomes_bench(sccs, synth, args.steps, prec)), flush=True)
+        return
+    if args.tune:
+        prob = synth.mid(n_patients=args.patients, n_cols=args.cols)
+        best, table = sccs.tune(prob, sccs.PRIOR_LAPLACE, 2.0, n_sweeps=3)
+        print(json.dumps({"tune_best": best, "candidates": table}), flush=True)
+        return
+    if args.workload == "full":
+        print(json.dumps(full_bench(sccs, synth, args.steps)), flush=True)
         return
     if args.workload == "cv":
         print(json.dumps(cv_bench(sccs, synth, 1 if args.mixed_only else 0, args.cv_max_sweeps, args.cv_tol)),

@@ -99,7 +99,8 @@ typedef struct sccs_options {
   int32_t n_workgroups;    /* persistent workgroups; 0 = one per compute unit */
   int32_t refresh_period;  /* sweeps between exact recomputation of w and den from beta;
                               0 = never, -1 = default (0 for FP64, 1 for mixed) */
-  int32_t reserved;        /* must be 0 */
+  int32_t tile_nnz;        /* nonzeros per tile (one wavefront each): 0 = 64, else 8..64;
+                              a patient with more nonzeros in a column gets a tile of its own */
   void* stream;            /* hipStream_t */
 } sccs_options;
 
@@ -117,7 +118,7 @@ typedef struct sccs_fit_result {
   double logpost;      /* L + log p(beta), constants dropped */
 } sccs_fit_result;
 
-/* Options with defaults: FP64, one workgroup per CU, default refresh, NULL stream. */
+/* Options with defaults: FP64, one workgroup per CU, default refresh, 64-nonzero tiles, NULL stream. */
 void sccs_default_options(sccs_options* opts);
 
 /* Device bytes sccs_create needs for this problem and these options.
@@ -172,6 +173,24 @@ sccs_status sccs_objective(sccs_handle* h, double* loglik, double* logpost);
  * kernel alone).  Synchronises. */
 sccs_status sccs_last_kernel_ms(sccs_handle* h, double* ms);
 
+/* Autotuner: times candidate schedules -- workgroup counts (all compute
+ * units, 3/4, 1/2, 1/4 of them) x tile sizes (16, 32, 64 nonzeros) -- on
+ * this problem with this prior, each for n_sweeps sweeps after one warm-up
+ * sweep from beta = 0, on temporary library-allocated handles; returns the
+ * fastest as options (opts with n_workgroups and tile_nnz filled in) and the
+ * per-candidate timings.  Synchronises; allocates and frees device memory. */
+#define SCCS_TUNE_MAX 16
+typedef struct sccs_tune_result {
+  int32_t n_candidates;
+  int32_t best;                               /* index of the fastest */
+  int32_t n_workgroups[SCCS_TUNE_MAX];
+  int32_t tile_nnz[SCCS_TUNE_MAX];
+  double ms_per_sweep[SCCS_TUNE_MAX];
+} sccs_tune_result;
+
+sccs_status sccs_tune(const sccs_problem* prob, const sccs_options* base, int32_t prior_kind, double variance,
+                      int32_t n_sweeps, sccs_options* best, sccs_tune_result* result);
+
 /* Human-readable description of the last error on this handle (or of the
  * last failed create when h is NULL).  Never NULL. */
 const char* sccs_last_error(const sccs_handle* h);
@@ -218,6 +237,13 @@ sccs_status sccs_batch_run(sccs_batch* b, const sccs_fit_opts* fo);
 
 /* beta [J] (host, nullable) and the result of link `link` of fit `fit`. */
 sccs_status sccs_batch_get(sccs_batch* b, int32_t fit, int32_t link, double* beta, sccs_fit_result* res);
+
+/* Held-out log-likelihood of link `link` of fit `fit`: Eq. 2 at the link's
+ * beta, summed over the patients whose weight in this fit is 0 (for a
+ * cross-validation fold, the patients left out of training; Section 2.5).
+ * Evaluated on the device when the link ends, from the maintained den_i.
+ * SCCS_ERR_STATE if the fit has no patient weights or the link has not run. */
+sccs_status sccs_batch_heldout(sccs_batch* b, int32_t fit, int32_t link, double* loglik);
 
 /* Device time of the last sccs_batch_run launch (ms). */
 sccs_status sccs_batch_last_kernel_ms(sccs_batch* b, double* ms);

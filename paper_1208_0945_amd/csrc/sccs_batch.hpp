@@ -28,6 +28,7 @@ struct LinkResult {
   int32_t converged;
   double loglik;
   double logpost;
+  double heldout;   // Eq. 2 over the fit's weight-0 patients (fits with weights)
 };
 
 // Device-resident description of one fit of a batch.
@@ -40,6 +41,8 @@ struct BatchFit {
   int32_t pad;
   double* beta_out;          // [n_links][J]
   LinkResult* res_out;       // [n_links]
+  const double* ho_n;        // [N] n_i of weight-0 patients, else 0; NULL without weights
+  const double* ytx_ho;      // [J] Y'X_j over the weight-0 patients
 };
 
 struct BatchArgs {
@@ -54,27 +57,31 @@ struct BatchArgs {
   double tol;
 };
 
-// Poll n tagged words (word e at src(e)) spread over the workgroup's
-// threads, every thread keeping all of its loads in flight at once; the
-// decoded values go to stage[dst(e)].  Returns false on timeout/abort
-// (also recorded in *flag).
-template <typename Src, typename Dst>
-__device__ __forceinline__ void poll_spread(int n, uint32_t tag, Src src, Dst dst, double* stage, Ctrl* ctrl,
-                                            int* flag) {
-  constexpr int kPer = (32 * kBatchSlotWords + kBlock - 1) / kBlock;
+// Poll the first nv words of n_members tagged slots, slot m at
+// base + m * stride, spread over the workgroup: thread tid watches word
+// tid % kBatchSlotWords of members tid / kBatchSlotWords + q * kMembersPerPass,
+// keeping all of its loads in flight at once.  Decoded values go to
+// stage[m * kBatchSlotWords + word].  On timeout/abort *flag is cleared.
+constexpr int kMembersPerPass = kBlock / kBatchSlotWords;
+constexpr int kPollPer = 32 / kMembersPerPass;   // up to 32 members per level
+__device__ __forceinline__ void poll_spread(const uint64_t* base, size_t stride, int n_members, int nv, uint32_t tag,
+                                            double* stage, Ctrl* ctrl, int* flag) {
+  const int word = threadIdx.x % kBatchSlotWords, m0 = threadIdx.x / kBatchSlotWords;
   uint32_t need = 0;
+  if (word < nv) {
 #pragma unroll
-  for (int q = 0; q < kPer; ++q)
-    if ((int)threadIdx.x + q * kBlock < n) need |= 1u << q;
+    for (int q = 0; q < kPollPer; ++q)
+      if (m0 + q * kMembersPerPass < n_members) need |= 1u << q;
+  }
   long long spins = 0;
   while (need) {
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
+    for (int q = 0; q < kPollPer; ++q) {
       if (need & (1u << q)) {
-        const int e = threadIdx.x + q * kBlock;
-        uint64_t x = load_agent(src(e));
+        const int m = m0 + q * kMembersPerPass;
+        uint64_t x = load_agent(base + (size_t)m * stride + word);
         if ((uint32_t)(x >> 63) == tag) {
-          stage[dst(e)] = tag_decode(x);
+          stage[m * kBatchSlotWords + word] = tag_decode(x);
           need &= ~(1u << q);
         }
       }
@@ -108,10 +115,7 @@ __device__ bool batch_allreduce(uint64_t* s1, uint64_t* s2, uint32_t seq, int G,
   __syncthreads();
   if (b < ng) {
     const int members = (G - b + ng - 1) / ng;
-    poll_spread(
-        members * nv, tag,
-        [&](int e) { return L1 + (size_t)(b + (e / nv) * ng) * kBatchSlotWords + (e % nv); },
-        [&](int e) { return (e / nv) * kBatchSlotWords + (e % nv); }, stage, ctrl, flag);
+    poll_spread(L1 + (size_t)b * kBatchSlotWords, (size_t)ng * kBatchSlotWords, members, nv, tag, stage, ctrl, flag);
     __syncthreads();
     if (tid < nv && *flag) {
       double s = 0.0;
@@ -123,9 +127,7 @@ __device__ bool batch_allreduce(uint64_t* s1, uint64_t* s2, uint32_t seq, int G,
   __syncthreads();
   if (*flag) {
     const int r = b % kReplicas;
-    poll_spread(
-        ng * nv, tag, [&](int e) { return L2 + ((size_t)r * kGroups + e / nv) * kBatchSlotWords + (e % nv); },
-        [&](int e) { return (e / nv) * kBatchSlotWords + (e % nv); }, stage, ctrl, flag);
+    poll_spread(L2 + (size_t)r * kGroups * kBatchSlotWords, kBatchSlotWords, ng, nv, tag, stage, ctrl, flag);
   }
   __syncthreads();
   if (tid < nv) {
@@ -148,6 +150,205 @@ struct WaveMap {
   __device__ int slice(int w) const { return P == 1 ? 0 : w % P; }
 };
 
+constexpr int kFitsPerWave = kMaxFits / kWaves;
+constexpr int kChunk = 4;   // pairs whose loads a wave keeps in flight together
+
+// Pair q of a wave: the fit it works on (F if none).  With P == 1 a wave
+// takes fits wave, wave + kWaves, ...; with P > 1 only pair 0 is used.
+// Pair fits increase with q, so the first pair with f >= F ends the list.
+__device__ __forceinline__ int pair_fit(const WaveMap& wm, int wave, int q, int F) {
+  if (wm.P == 1) return wave + q * kWaves;
+  return (q == 0 && wave < F * wm.P) ? wave / wm.P : F;
+}
+
+// Index data of coordinate j for every pair of this wave, into the wave's
+// LDS rows: ixs[q] = (first tile t0 + slice, end of range t1, e0, len of
+// that first tile), ixrp[q][lane] = (row, patient) of its lane-th nonzero.
+// Each stage (tile range, tile bounds, nonzeros) is issued for a chunk of
+// pairs before any of it is waited on.
+__device__ __forceinline__ void pair_index(const BatchArgs& A, const WaveMap& wm, int wave, int j,
+                                           const int* s_done, int (*ixs)[4], uint2 (*ixrp)[64]) {
+  const int lane = threadIdx.x & 63, b = blockIdx.x;
+  const int slice = wm.slice(wave);
+#pragma unroll 1
+  for (int q0 = 0; q0 < kFitsPerWave; q0 += kChunk) {
+    if (pair_fit(wm, wave, q0, A.F) >= A.F) break;
+    int t[kChunk], t1[kChunk], e0[kChunk], len[kChunk];
+#pragma unroll
+    for (int c = 0; c < kChunk; ++c) {
+      const int f = pair_fit(wm, wave, q0 + c, A.F);
+      t[c] = 0;
+      t1[c] = 0;
+      if (f < A.F && !s_done[f]) {
+        const size_t base = (size_t)j * (A.G + 1) + b;
+        t[c] = A.fits[f].k.own[base] + slice;
+        t1[c] = A.fits[f].k.own[base + 1];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kChunk; ++c) {
+      const int f = pair_fit(wm, wave, q0 + c, A.F);
+      e0[c] = 0;
+      len[c] = 0;
+      if (f < A.F && t[c] < t1[c]) {
+        e0[c] = A.fits[f].k.tile_start[t[c]];
+        len[c] = A.fits[f].k.tile_start[t[c] + 1] - e0[c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kChunk; ++c) {
+      const int f = pair_fit(wm, wave, q0 + c, A.F);
+      uint2 rp = make_uint2(0u, 0xffffffffu);
+      if (f < A.F && t[c] < t1[c] && len[c] <= 64 && lane < len[c]) rp = A.fits[f].k.rp[e0[c] + lane];
+      ixrp[q0 + c][lane] = rp;
+      if (lane == 0) {
+        ixs[q0 + c][0] = t[c];
+        ixs[q0 + c][1] = t1[c];
+        ixs[q0 + c][2] = e0[c];
+        ixs[q0 + c][3] = len[c];
+      }
+    }
+  }
+}
+
+// Phase A over this wave's pairs: the first tiles of a chunk of pairs are
+// gathered together from the staged indices, then any further tiles of the
+// pair's range (large columns) are walked one by one.  Partials go to
+// pp[f][slice].
+template <typename WT>
+__device__ __forceinline__ void pairs_phase_a(const BatchArgs& A, const WaveMap& wm, int wave, const int* s_done,
+                                              const int (*ixs)[4], const uint2 (*ixrp)[64],
+                                              double (*pp)[kWaves][2]) {
+  const int lane = threadIdx.x & 63, F = A.F, slice = wm.slice(wave);
+#pragma unroll 1
+  for (int q0 = 0; q0 < kFitsPerWave; q0 += kChunk) {
+    if (pair_fit(wm, wave, q0, F) >= F) break;
+    double wv[kChunk], den[kChunk], wn[kChunk];
+    bool head[kChunk];
+    int seg_end[kChunk];
+    uint32_t pid[kChunk];
+#pragma unroll
+    for (int c = 0; c < kChunk; ++c) {
+      const int f = pair_fit(wm, wave, q0 + c, F);
+      const int t = ixs[q0 + c][0], t1 = ixs[q0 + c][1], len = ixs[q0 + c][3];
+      const uint2 rp = ixrp[q0 + c][lane];
+      pid[c] = rp.y;
+      wv[c] = 0.0;
+      head[c] = false;
+      seg_end[c] = lane;
+      if (f < F && t < t1 && len <= 64) {
+        seg_layout(rp.y, lane, len, head[c], seg_end[c]);
+        if (lane < len) wv[c] = (double)((const WT*)A.fits[f].k.w)[rp.x];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kChunk; ++c) {
+      const int f = pair_fit(wm, wave, q0 + c, F);
+      den[c] = 1.0;
+      wn[c] = 0.0;
+      if (head[c]) {
+        const double2 pv = A.fits[f].k.pat[pid[c]];
+        den[c] = pv.x;
+        wn[c] = pv.y;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kChunk; ++c) {
+      const int f = pair_fit(wm, wave, q0 + c, F);
+      const double num = seg_sum_v(wv[c], lane, seg_end[c]);
+      double Gl = 0.0, Hl = 0.0;
+      if (head[c]) accum_patient(num, make_double2(den[c], wn[c]), Gl, Hl);
+      Gl = wave_sum(Gl);
+      Hl = wave_sum(Hl);
+      if (f < F && lane == 0) {
+        pp[f][slice][0] = Gl;
+        pp[f][slice][1] = Hl;
+      }
+    }
+  }
+#pragma unroll 1
+  for (int q = 0; q < kFitsPerWave; ++q) {
+    const int f = pair_fit(wm, wave, q, F);
+    if (f >= F) break;
+    if (s_done[f]) continue;
+    const int t0 = ixs[q][0], t1 = ixs[q][1], len0 = ixs[q][3];
+    double Gl = 0.0, Hl = 0.0;
+    bool any = false;
+    if (t0 < t1 && len0 > 64) { tile_a<WT>(A.fits[f].k, t0, Gl, Hl); any = true; }
+    for (int t = t0 + wm.P; t < t1; t += wm.P) { tile_a<WT>(A.fits[f].k, t, Gl, Hl); any = true; }
+    if (any) {
+      Gl = wave_sum(Gl);
+      Hl = wave_sum(Hl);
+      if (lane == 0) {
+        pp[f][slice][0] += Gl;
+        pp[f][slice][1] += Hl;
+      }
+    }
+  }
+}
+
+// Phase B over this wave's pairs with a nonzero step: the first tiles of a
+// chunk are re-gathered together (the lines are still in L2 from phase A)
+// and updated as tile_b does; further tiles follow one by one.
+template <typename WT>
+__device__ __forceinline__ void pairs_phase_b(const BatchArgs& A, const WaveMap& wm, int wave, const int* s_done,
+                                              const int (*ixs)[4], const uint2 (*ixrp)[64],
+                                              const double (*dd)[3]) {
+  const int lane = threadIdx.x & 63, F = A.F;
+#pragma unroll 1
+  for (int q0 = 0; q0 < kFitsPerWave; q0 += kChunk) {
+    if (pair_fit(wm, wave, q0, F) >= F) break;
+    WT wo[kChunk];
+    double den[kChunk];
+    bool head[kChunk], live[kChunk];
+    int seg_end[kChunk];
+#pragma unroll
+    for (int c = 0; c < kChunk; ++c) {
+      const int f = pair_fit(wm, wave, q0 + c, F);
+      const int t = ixs[q0 + c][0], t1 = ixs[q0 + c][1], len = ixs[q0 + c][3];
+      const uint2 rp = ixrp[q0 + c][lane];
+      live[c] = f < F && !s_done[f] && dd[f][0] != 0.0 && t < t1 && len <= 64;
+      wo[c] = (WT)0;
+      head[c] = false;
+      seg_end[c] = lane;
+      if (live[c]) {
+        seg_layout(rp.y, lane, len, head[c], seg_end[c]);
+        if (lane < len) wo[c] = ((const WT*)A.fits[f].k.w)[rp.x];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kChunk; ++c) {
+      const int f = pair_fit(wm, wave, q0 + c, F);
+      den[c] = 0.0;
+      if (head[c]) den[c] = A.fits[f].k.pat[ixrp[q0 + c][lane].y].x;
+    }
+#pragma unroll
+    for (int c = 0; c < kChunk; ++c) {
+      if (!live[c]) continue;
+      const int f = pair_fit(wm, wave, q0 + c, F);
+      const uint2 rp = ixrp[q0 + c][lane];
+      const WT wnew = wo[c] * (WT)dd[f][1];
+      if (lane < ixs[q0 + c][3]) ((WT*)A.fits[f].k.w)[rp.x] = wnew;
+      if (sizeof(WT) == 8) {
+        const double num = seg_sum_v((double)wo[c], lane, seg_end[c]);
+        if (head[c]) A.fits[f].k.pat[rp.y].x = den[c] + num * dd[f][2];
+      } else {
+        const double sdiff = seg_sum_v((double)wnew - (double)wo[c], lane, seg_end[c]);
+        if (head[c]) A.fits[f].k.pat[rp.y].x = den[c] + sdiff;
+      }
+    }
+  }
+#pragma unroll 1
+  for (int q = 0; q < kFitsPerWave; ++q) {
+    const int f = pair_fit(wm, wave, q, F);
+    if (f >= F) break;
+    if (s_done[f] || dd[f][0] == 0.0) continue;
+    const int t0 = ixs[q][0], t1 = ixs[q][1], len0 = ixs[q][3];
+    if (t0 < t1 && len0 > 64) tile_b<WT>(A.fits[f].k, t0, dd[f][1], dd[f][2]);
+    for (int t = t0 + wm.P; t < t1; t += wm.P) tile_b<WT>(A.fits[f].k, t, dd[f][1], dd[f][2]);
+  }
+}
+
 template <typename WT>
 __global__ void __launch_bounds__(kBlock) k_batch(BatchArgs A) {
   __shared__ double stage[32 * kBatchSlotWords];
@@ -158,8 +359,11 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchArgs A) {
   __shared__ int s_link[kMaxFits], s_sw[kMaxFits], s_kind[kMaxFits], s_done[kMaxFits];
   __shared__ int flag, bad_any, n_active, since_refresh;
   __shared__ double red[kWaves][4];
+  __shared__ int s_ixs[2][kWaves][kFitsPerWave][4];        // indices of coordinates j and j + 1
+  __shared__ uint2 s_ixrp[2][kWaves][kFitsPerWave][64];
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, b = blockIdx.x;
+  const int tid = threadIdx.x, b = blockIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int F = A.F, G = A.G, J = A.J;
   const WaveMap wm(F);
   uint32_t seq = A.ctrl->seq;
@@ -227,6 +431,44 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchArgs A) {
     return okr;
   };
 
+  // Eq. 2 over the weight-0 patients of every fit that has just finished a
+  // link: sum_j beta_j Y'X_j(held out) - sum_i n_i log den_i, the second
+  // sum split into positive and negative parts and reduced like the
+  // objective.  Workgroup 0 stores it in the link's result.
+  __shared__ int s_adv[kMaxFits];
+  __shared__ double s_ho[kMaxFits];
+  auto heldout = [&]() -> bool {
+    for (int f = 0; f < F; ++f) {
+      const BatchFit& bf = A.fits[f];
+      double loc[3] = {0.0, 0.0, 0.0};
+      if (s_adv[f] && bf.ho_n) {
+        const int p0 = bf.k.pb[b], p1 = bf.k.pb[b + 1];
+        for (int i = p0 + tid; i < p1; i += kBlock) {
+          const double hn = bf.ho_n[i];
+          if (hn != 0.0) {
+            double t = hn * log(bf.k.pat[i].x);
+            if (t > 0.0) loc[0] += t; else loc[1] -= t;
+          }
+        }
+        const double2* bt = bf.bt + (size_t)b * J;
+        for (int j = tid; j < J; j += kBlock) loc[2] += bt[j].x * bf.ytx_ho[j];
+      }
+      double o[3];
+      block_sum<3>(loc, o, red);
+      if (tid == 0) {
+        part[2 * f] = o[0];
+        part[2 * f + 1] = o[1];
+        s_ho[f] = o[2];
+      }
+    }
+    __syncthreads();
+    bool okr = batch_allreduce(A.s1, A.s2, seq++, G, 2 * F, A.ctrl, part, tot, stage, &flag);
+    if (okr && b == 0 && tid < F && s_adv[tid] && A.fits[tid].ho_n)
+      A.fits[tid].res_out[s_link[tid]].heldout = s_ho[tid] - (tot[2 * tid] - tot[2 * tid + 1]);
+    __syncthreads();
+    return okr;
+  };
+
   __shared__ double Lcur[kMaxFits], Pcur[kMaxFits];
   bool ok = true;
   int status = SCCS_OK;
@@ -244,23 +486,12 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchArgs A) {
     }
     __syncthreads();
     if (n_active == 0) break;
+    pair_index(A, wm, wave, 0, s_done, s_ixs[0][wave], s_ixrp[0][wave]);
     for (int j = 0; j < J && ok; ++j) {
-      // phase A for every (fit, slice) of this wave
-      for (int f = wm.first_fit(wave, F); f < F; f = wm.next_fit(f)) {
-        double Gl = 0.0, Hl = 0.0;
-        if (!s_done[f]) {
-          const KArgs& k = A.fits[f].k;
-          const size_t base = (size_t)j * (G + 1) + b;
-          const int t0 = k.own[base], t1 = k.own[base + 1];
-          for (int t = t0 + wm.slice(wave); t < t1; t += wm.P) tile_a<WT>(k, t, Gl, Hl);
-        }
-        Gl = wave_sum(Gl);
-        Hl = wave_sum(Hl);
-        if (lane == 0) {
-          pp[f][wm.slice(wave)][0] = Gl;
-          pp[f][wm.slice(wave)][1] = Hl;
-        }
-      }
+      const int cur = j & 1;
+      pairs_phase_a<WT>(A, wm, wave, s_done, s_ixs[cur][wave], s_ixrp[cur][wave], pp);
+      // index data of the next coordinate (static), loaded before the reduction
+      if (j + 1 < J) pair_index(A, wm, wave, j + 1, s_done, s_ixs[cur ^ 1][wave], s_ixrp[cur ^ 1][wave]);
       __syncthreads();
       if (tid < F) {
         double g = 0.0, h = 0.0;
@@ -300,13 +531,7 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchArgs A) {
       }
       __syncthreads();
       if (bad_any) { status = SCCS_ERR_NUMERIC; ok = false; break; }
-      for (int f = wm.first_fit(wave, F); f < F; f = wm.next_fit(f)) {
-        if (s_done[f] || dd[f][0] == 0.0) continue;
-        const KArgs& k = A.fits[f].k;
-        const size_t base = (size_t)j * (G + 1) + b;
-        const int t0 = k.own[base], t1 = k.own[base + 1];
-        for (int t = t0 + wm.slice(wave); t < t1; t += wm.P) tile_b<WT>(k, t, dd[f][1], dd[f][2]);
-      }
+      pairs_phase_b<WT>(A, wm, wave, s_done, s_ixs[cur][wave], s_ixrp[cur][wave], dd);
       __syncthreads();
     }
     if (!ok) break;
@@ -326,7 +551,6 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchArgs A) {
     ok = objectives(Lcur, Pcur);
     if (!ok) break;
     // link bookkeeping, identical in every workgroup
-    __shared__ int s_adv[kMaxFits];
     if (tid < F) {
       const int f = tid;
       int adv = 0;
@@ -351,6 +575,15 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchArgs A) {
     }
     __syncthreads();
     if (bad_any) { status = SCCS_ERR_NUMERIC; ok = false; break; }
+    // held-out log-likelihood at the end of a link, for fits with a held-out set
+    {
+      bool any = false;
+      for (int f = 0; f < F; ++f) any = any || (s_adv[f] && A.fits[f].ho_n);
+      if (any) {
+        ok = heldout();
+        if (!ok) break;
+      }
+    }
     // record beta of finished links (workgroup 0), reset trust, move on
     for (int f = 0; f < F; ++f) {
       if (!s_adv[f]) continue;

@@ -73,7 +73,7 @@ struct Plan {
 size_t carve(void* base, const Layout& L, int prec, bool has_weight, Plan& P) {
   Carver c(base);
   P.rp = c.take<uint2>((size_t)L.nnz + 1);
-  P.tile_start = c.take<int32_t>((size_t)L.n_tiles() + 1);
+  P.tile_start = c.take<int32_t>((size_t)L.tiles_cap);
   P.own = c.take<int32_t>((size_t)L.J * (L.G + 1));
   P.pb = c.take<int32_t>((size_t)L.G + 1);
   P.pptr = c.take<int32_t>((size_t)L.N + 1);
@@ -111,8 +111,8 @@ sccs_status check_options(const sccs_options* o, std::string& err) {
     err = "options.refresh_period must be >= -1";
     return SCCS_ERR_INVALID_ARG;
   }
-  if (o->reserved != 0) {
-    err = "options.reserved must be 0";
+  if (o->tile_nnz != 0 && (o->tile_nnz < 8 || o->tile_nnz > kTile)) {
+    err = "options.tile_nnz must be 0 (64) or in [8, 64]";
     return SCCS_ERR_INVALID_ARG;
   }
   return SCCS_OK;
@@ -218,6 +218,7 @@ void sccs_default_options(sccs_options* o) {
   o->precision = SCCS_PREC_FP64;
   o->n_workgroups = 0;
   o->refresh_period = -1;
+  o->tile_nnz = 0;
   o->stream = nullptr;
 }
 
@@ -231,12 +232,7 @@ sccs_status sccs_query_workspace(const sccs_problem* prob, const sccs_options* o
   if (st != SCCS_OK) { g_create_error = err; return st; }
   if (prob->n_cols > kMaxJ) { g_create_error = "n_cols exceeds 6144"; return SCCS_ERR_INVALID_ARG; }
   Layout L;
-  try {
-    build_layout(prob, G, L);
-  } catch (const std::bad_alloc&) {
-    g_create_error = "host out of memory while building the layout";
-    return SCCS_ERR_INVALID_ARG;
-  }
+  layout_dims(prob, G, opts && opts->tile_nnz ? opts->tile_nnz : kTile, L);
   Plan P;
   *bytes = carve(nullptr, L, opts ? opts->precision : SCCS_PREC_FP64, prob->patient_weight != nullptr, P);
   return SCCS_OK;
@@ -264,11 +260,18 @@ sccs_status sccs_create(const sccs_problem* prob, const sccs_options* opts_in, v
   sccs_handle* h = new (std::nothrow) sccs_handle();
   if (!h) { g_create_error = "out of host memory"; return SCCS_ERR_INVALID_ARG; }
   Layout L;
+  const int32_t tile_nnz = opts.tile_nnz ? opts.tile_nnz : kTile;
   try {
-    build_layout(prob, G, L);
+    build_layout(prob, G, L, tile_nnz);
   } catch (const std::bad_alloc&) {
     delete h;
     g_create_error = "host out of memory while building the layout";
+    return SCCS_ERR_INVALID_ARG;
+  }
+  L.tiles_cap = tile_bound(L.nnz, L.J, G, tile_nnz) + 1;
+  if ((int64_t)L.tile_start.size() > L.tiles_cap) {
+    delete h;
+    g_create_error = "internal: tile count exceeds its bound";
     return SCCS_ERR_INVALID_ARG;
   }
   const bool has_w = prob->patient_weight != nullptr;
@@ -356,7 +359,7 @@ sccs_status sccs_create(const sccs_problem* prob, const sccs_options* opts_in, v
   if (gp > 4096) gp = 4096;
   hipLaunchKernelGGL(k_setup_patients, dim3(gp), dim3(256), 0, s, P.pptr, P.count, P.weight, P.pat, L.N);
   int gj = L.J < 4096 ? L.J : 4096;
-  hipLaunchKernelGGL(k_setup_ytx, dim3(gj), dim3(256), 0, s, P.col_ptr, P.rp, P.count, P.weight, P.ytx, L.J);
+  hipLaunchKernelGGL(k_setup_ytx, dim3(gj), dim3(256), 0, s, P.col_ptr, P.rp, P.count, P.weight, 0, P.ytx, L.J);
   if (hipGetLastError() != hipSuccess) return bail("setup kernel launch failed", SCCS_ERR_HIP);
 
   KArgs& a = h->args;
@@ -501,6 +504,65 @@ sccs_status sccs_last_kernel_ms(sccs_handle* h, double* ms) {
   float f = 0.f;
   HIPCHK(h, hipEventElapsedTime(&f, h->ev0, h->ev1));
   *ms = f;
+  return SCCS_OK;
+}
+
+sccs_status sccs_tune(const sccs_problem* prob, const sccs_options* base, int32_t prior_kind, double variance,
+                      int32_t n_sweeps, sccs_options* best, sccs_tune_result* result) {
+  if (!prob || !best || !result || n_sweeps < 1) {
+    g_create_error = "sccs_tune: NULL argument or n_sweeps < 1";
+    return SCCS_ERR_INVALID_ARG;
+  }
+  sccs_options o;
+  sccs_default_options(&o);
+  if (base) o = *base;
+  std::string err;
+  int32_t G = 0;
+  sccs_status st = check_options(&o, err);
+  if (st == SCCS_OK) {
+    sccs_options all = o;
+    all.n_workgroups = 0;
+    st = pick_workgroups(&all, G, err);
+  }
+  if (st) { g_create_error = err; return st; }
+  std::memset(result, 0, sizeof *result);
+  const int gs[4] = {G, (3 * G) / 4, G / 2, G / 4};
+  const int ts[3] = {16, 32, 64};
+  double best_ms = 1e300;
+  for (int gi = 0; gi < 4; ++gi) {
+    if (gs[gi] < 1 || (gi > 0 && gs[gi] == gs[gi - 1])) continue;
+    for (int ti = 0; ti < 3; ++ti) {
+      if (result->n_candidates >= SCCS_TUNE_MAX) break;
+      sccs_options c = o;
+      c.n_workgroups = gs[gi];
+      c.tile_nnz = ts[ti];
+      sccs_handle* h = nullptr;
+      st = sccs_create(prob, &c, nullptr, 0, &h);
+      if (st) return st;
+      double ms = 0.0;
+      st = sccs_set_prior(h, prior_kind, variance);
+      if (!st) st = sccs_sweep(h, 1, nullptr);
+      if (!st) st = sccs_sweep(h, n_sweeps, nullptr);
+      if (!st) st = sccs_last_kernel_ms(h, &ms);
+      if (st) {
+        g_create_error = std::string("sccs_tune: ") + h->err;
+        sccs_destroy(h);
+        return st;
+      }
+      sccs_destroy(h);
+      const int k = result->n_candidates++;
+      result->n_workgroups[k] = gs[gi];
+      result->tile_nnz[k] = ts[ti];
+      result->ms_per_sweep[k] = ms / n_sweeps;
+      if (ms < best_ms) {
+        best_ms = ms;
+        result->best = k;
+      }
+    }
+  }
+  *best = o;
+  best->n_workgroups = result->n_workgroups[result->best];
+  best->tile_nnz = result->tile_nnz[result->best];
   return SCCS_OK;
 }
 

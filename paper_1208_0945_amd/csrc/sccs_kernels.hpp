@@ -813,15 +813,27 @@ __global__ void k_setup_patients(const int32_t* pptr, const int32_t* count, cons
   }
 }
 
+// n_i of the patients whose weight is 0 (the held-out set of a cross-
+// validation fold), 0 for every other patient.
+__global__ void k_setup_heldout(const int32_t* pptr, const int32_t* count, const int32_t* weight, double* hn, int N) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+    long long n = 0;
+    for (int k = pptr[i]; k < pptr[i + 1]; ++k) n += count[k];
+    hn[i] = weight[i] == 0 ? (double)n : 0.0;
+  }
+}
+
 // Y'X_j with patient weights: one workgroup per column, fixed-order sum.
+// complement != 0 sums over the weight-0 patients only (held-out set).
 __global__ void __launch_bounds__(256) k_setup_ytx(const int64_t* col_ptr, const uint2* rp, const int32_t* count,
-                                                   const int32_t* weight, double* ytx, int J) {
+                                                   const int32_t* weight, int complement, double* ytx, int J) {
   __shared__ double red[4];
   for (int j = blockIdx.x; j < J; j += gridDim.x) {
     double s = 0.0;
     for (long long e = col_ptr[j] + threadIdx.x; e < col_ptr[j + 1]; e += blockDim.x) {
       uint2 q = rp[e];
       double om = weight ? (double)weight[q.y] : 1.0;
+      if (complement) om = om == 0.0 ? 1.0 : 0.0;
       s += om * (double)count[q.x];
     }
     s = wave_sum(s);

@@ -1,13 +1,42 @@
-// Host layout builder for libsccs (see sccs_layout.hpp).
+// Host layout builder for libsccs (see sccs_layout.hpp).  Loops over
+// patients, nonzeros and columns run on a few host threads (std::thread, so
+// no OpenMP runtime is pulled into processes that already carry one).
 #include "sccs_layout.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <limits>
+#include <thread>
 
 namespace sccs {
 
-static sccs_status fail(std::string& err, const char* msg, long long a = -1) {
+namespace {
+
+int host_threads() {
+  unsigned n = std::thread::hardware_concurrency();
+  if (n == 0) n = 4;
+  return (int)std::min(n, 16u);
+}
+
+// f(lo, hi) over [0, n) split into contiguous chunks, one per thread.
+template <typename F>
+void parallel_ranges(int64_t n, F f) {
+  const int T = host_threads();
+  if (n < 1 << 16 || T == 1) {
+    f((int64_t)0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  th.reserve(T);
+  for (int t = 0; t < T; ++t) {
+    int64_t lo = n * t / T, hi = n * (t + 1) / T;
+    th.emplace_back([=] { f(lo, hi); });
+  }
+  for (auto& x : th) x.join();
+}
+
+sccs_status fail(std::string& err, const char* msg, long long a = -1) {
   char buf[256];
   if (a >= 0)
     std::snprintf(buf, sizeof buf, "%s (at %lld)", msg, a);
@@ -16,6 +45,8 @@ static sccs_status fail(std::string& err, const char* msg, long long a = -1) {
   err = buf;
   return SCCS_ERR_INVALID_ARG;
 }
+
+}  // namespace
 
 sccs_status validate_problem(const sccs_problem* p, std::string& err) {
   if (!p) return fail(err, "problem is NULL");
@@ -36,29 +67,48 @@ sccs_status validate_problem(const sccs_problem* p, std::string& err) {
   for (int64_t j = 0; j < J; ++j)
     if (p->col_ptr[j + 1] < p->col_ptr[j]) return fail(err, "col_ptr must be non-decreasing", j);
   if (p->col_ptr[J] != p->nnz) return fail(err, "col_ptr[J] must equal nnz");
-  for (int64_t k = 0; k < K; ++k) {
-    if (p->offset[k] < 0) return fail(err, "offset (era length) must be >= 0", k);
-    if (p->count[k] < 0) return fail(err, "count must be >= 0", k);
-    if (p->count[k] > 0 && p->offset[k] == 0) return fail(err, "an era with events must have positive length", k);
-  }
-  for (int64_t j = 0; j < J; ++j) {
-    for (int64_t e = p->col_ptr[j]; e < p->col_ptr[j + 1]; ++e) {
-      int32_t r = p->row_idx[e];
-      if (r < 0 || r >= K) return fail(err, "row_idx out of range", e);
-      if (e > p->col_ptr[j] && r <= p->row_idx[e - 1])
-        return fail(err, "row_idx must be strictly increasing within a column", e);
+  // first offending index (or -1) per check, found in parallel
+  std::atomic<int64_t> bad_len{-1}, bad_cnt{-1}, bad_evt{-1};
+  parallel_ranges(K, [&](int64_t lo, int64_t hi) {
+    for (int64_t k = lo; k < hi; ++k) {
+      if (p->offset[k] < 0) { bad_len = k; return; }
+      if (p->count[k] < 0) { bad_cnt = k; return; }
+      if (p->count[k] > 0 && p->offset[k] == 0) { bad_evt = k; return; }
     }
-  }
+  });
+  if (bad_len >= 0) return fail(err, "offset (era length) must be >= 0", bad_len);
+  if (bad_cnt >= 0) return fail(err, "count must be >= 0", bad_cnt);
+  if (bad_evt >= 0) return fail(err, "an era with events must have positive length", bad_evt);
+  std::atomic<int64_t> bad_range{-1}, bad_order{-1};
+  parallel_ranges(J, [&](int64_t lo, int64_t hi) {
+    for (int64_t j = lo; j < hi; ++j) {
+      for (int64_t e = p->col_ptr[j]; e < p->col_ptr[j + 1]; ++e) {
+        int32_t r = p->row_idx[e];
+        if (r < 0 || r >= K) { bad_range = e; return; }
+        if (e > p->col_ptr[j] && r <= p->row_idx[e - 1]) { bad_order = e; return; }
+      }
+    }
+  });
+  if (bad_range >= 0) return fail(err, "row_idx out of range", bad_range);
+  if (bad_order >= 0) return fail(err, "row_idx must be strictly increasing within a column", bad_order);
   if (p->patient_weight)
     for (int64_t i = 0; i < N; ++i)
       if (p->patient_weight[i] < 0) return fail(err, "patient_weight must be >= 0", i);
   return SCCS_OK;
 }
 
-void build_layout(const sccs_problem* p, int32_t G, Layout& L) {
+int64_t tile_bound(int64_t nnz, int32_t J, int32_t G, int32_t tile_nnz) {
+  // Within one (column, workgroup) range, two consecutive tiles hold more
+  // than tile_nnz nonzeros together (greedy packing; a long tile alone
+  // does), so a range with c nonzeros has fewer than 2c/tile_nnz + 2 tiles.
+  const int64_t ranges = std::min<int64_t>(nnz, (int64_t)J * G);
+  return 2 * nnz / tile_nnz + 2 * ranges + 1;
+}
+
+void build_layout(const sccs_problem* p, int32_t G, Layout& L, int32_t tile_nnz) {
   const int32_t N = p->n_patients, J = p->n_cols;
   const int64_t K = p->n_rows, nnz = p->nnz;
-  L.N = N; L.J = J; L.G = G; L.K = K; L.nnz = nnz;
+  L.N = N; L.J = J; L.G = G; L.K = K; L.nnz = nnz; L.tile_nnz = tile_nnz;
 
   // patient ranges balanced by era count
   L.pb.assign(G + 1, 0);
@@ -78,52 +128,76 @@ void build_layout(const sccs_problem* p, int32_t G, Layout& L) {
 
   L.pptr.resize((size_t)N + 1);
   std::vector<int32_t> era_pid((size_t)K);
-  for (int32_t i = 0; i < N; ++i) {
-    L.pptr[i] = (int32_t)p->patient_ptr[i];
-    for (int64_t k = p->patient_ptr[i]; k < p->patient_ptr[i + 1]; ++k) era_pid[k] = i;
-  }
+  parallel_ranges(N, [&](int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i) {
+      L.pptr[i] = (int32_t)p->patient_ptr[i];
+      for (int64_t k = p->patient_ptr[i]; k < p->patient_ptr[i + 1]; ++k) era_pid[k] = (int32_t)i;
+    }
+  });
   L.pptr[N] = (int32_t)K;
 
   L.rp.resize((size_t)nnz * 2);
-  for (int64_t e = 0; e < nnz; ++e) {
-    int32_t r = p->row_idx[e];
-    L.rp[2 * e] = (uint32_t)r;
-    L.rp[2 * e + 1] = (uint32_t)era_pid[r];
-  }
-
-  // tiles
-  L.tile_start.clear();
-  L.tile_start.reserve((size_t)(nnz / 32 + (int64_t)J * 4 + 16));
-  L.own.assign((size_t)J * (G + 1), 0);
-  L.max_tiles_per_wg = 0;
-  for (int32_t j = 0; j < J; ++j) {
-    int64_t e = p->col_ptr[j], end = p->col_ptr[j + 1];
-    for (int32_t b = 0; b < G; ++b) {
-      int32_t first = (int32_t)L.tile_start.size();
-      L.own[(size_t)j * (G + 1) + b] = first;
-      int64_t cur_start = -1, cur_len = 0;
-      while (e < end && owner[era_pid[p->row_idx[e]]] == b) {
-        // one patient segment
-        int32_t pid = era_pid[p->row_idx[e]];
-        int64_t s = e;
-        while (e < end && era_pid[p->row_idx[e]] == pid) ++e;
-        int64_t seg = e - s;
-        if (seg > kTile) {
-          L.tile_start.push_back((int32_t)s);  // long tile, one patient
-          cur_start = -1; cur_len = 0;
-        } else if (cur_start < 0 || cur_len + seg > kTile) {
-          L.tile_start.push_back((int32_t)s);
-          cur_start = s; cur_len = seg;
-        } else {
-          cur_len += seg;
-        }
-      }
-      int32_t nt = (int32_t)L.tile_start.size() - first;
-      L.max_tiles_per_wg = std::max(L.max_tiles_per_wg, nt);
+  parallel_ranges(nnz, [&](int64_t lo, int64_t hi) {
+    for (int64_t e = lo; e < hi; ++e) {
+      int32_t r = p->row_idx[e];
+      L.rp[2 * e] = (uint32_t)r;
+      L.rp[2 * e + 1] = (uint32_t)era_pid[r];
     }
-    L.own[(size_t)j * (G + 1) + G] = (int32_t)L.tile_start.size();
-  }
-  L.tile_start.push_back((int32_t)nnz);
+  });
+
+  // tiles, column by column in parallel: tile starts of column j, and the
+  // number of tiles of each (j, b) range
+  std::vector<std::vector<int32_t>> col_tiles(J);
+  std::vector<int32_t> range_tiles((size_t)J * G, 0);
+  parallel_ranges(J, [&](int64_t jlo, int64_t jhi) {
+    for (int64_t j = jlo; j < jhi; ++j) {
+      std::vector<int32_t>& ts = col_tiles[j];
+      int64_t e = p->col_ptr[j], end = p->col_ptr[j + 1];
+      for (int32_t b = 0; b < G; ++b) {
+        const size_t first = ts.size();
+        int64_t cur_len = -1;
+        while (e < end && owner[era_pid[p->row_idx[e]]] == b) {
+          const int32_t pid = era_pid[p->row_idx[e]];
+          const int64_t s = e;
+          while (e < end && era_pid[p->row_idx[e]] == pid) ++e;
+          const int64_t seg = e - s;
+          if (seg > tile_nnz) {
+            ts.push_back((int32_t)s);  // a patient with more nonzeros than a tile: a tile of its own
+            cur_len = -1;
+          } else if (cur_len < 0 || cur_len + seg > tile_nnz) {
+            ts.push_back((int32_t)s);
+            cur_len = seg;
+          } else {
+            cur_len += seg;
+          }
+        }
+        range_tiles[(size_t)j * G + b] = (int32_t)(ts.size() - first);
+      }
+    }
+  });
+  std::vector<int64_t> col_first((size_t)J + 1, 0);
+  for (int32_t j = 0; j < J; ++j) col_first[j + 1] = col_first[j] + (int64_t)col_tiles[j].size();
+  L.tile_start.resize((size_t)col_first[J] + 1);
+  L.own.assign((size_t)J * (G + 1), 0);
+  std::atomic<int32_t> max_per_wg{0};
+  parallel_ranges(J, [&](int64_t jlo, int64_t jhi) {
+    int32_t mx = 0;
+    for (int64_t j = jlo; j < jhi; ++j) {
+      std::copy(col_tiles[j].begin(), col_tiles[j].end(), L.tile_start.begin() + col_first[j]);
+      int64_t t = col_first[j];
+      for (int32_t b = 0; b < G; ++b) {
+        L.own[(size_t)j * (G + 1) + b] = (int32_t)t;
+        t += range_tiles[(size_t)j * G + b];
+        mx = std::max(mx, range_tiles[(size_t)j * G + b]);
+      }
+      L.own[(size_t)j * (G + 1) + G] = (int32_t)t;
+    }
+    int32_t cur = max_per_wg.load();
+    while (mx > cur && !max_per_wg.compare_exchange_weak(cur, mx)) {
+    }
+  });
+  L.tile_start[col_first[J]] = (int32_t)nnz;
+  L.max_tiles_per_wg = max_per_wg.load();
 
   // compressed row storage of X (columns ascending within a row)
   L.era_ptr.assign((size_t)K + 1, 0);
@@ -132,8 +206,7 @@ void build_layout(const sccs_problem* p, int32_t G, Layout& L) {
   L.era_col.resize((size_t)nnz);
   std::vector<int32_t> fill(L.era_ptr.begin(), L.era_ptr.end() - 1);
   for (int32_t j = 0; j < J; ++j)
-    for (int64_t e = p->col_ptr[j]; e < p->col_ptr[j + 1]; ++e)
-      L.era_col[(size_t)fill[p->row_idx[e]]++] = j;
+    for (int64_t e = p->col_ptr[j]; e < p->col_ptr[j + 1]; ++e) L.era_col[(size_t)fill[p->row_idx[e]]++] = j;
 }
 
 }  // namespace sccs

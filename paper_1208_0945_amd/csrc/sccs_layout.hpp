@@ -27,8 +27,9 @@ namespace sccs {
 constexpr int kTile = 64;
 
 struct Layout {
-  int32_t N = 0, J = 0, G = 0;
+  int32_t N = 0, J = 0, G = 0, tile_nnz = kTile;
   int64_t K = 0, nnz = 0;
+  int64_t tiles_cap = 0;            // workspace room for tile_start (>= tiles + 1)
   std::vector<int32_t> pb;          // [G+1] patient bounds per workgroup
   std::vector<uint32_t> rp;         // [2*nnz] (row, patient) per nonzero, CSC order
   std::vector<int32_t> tile_start;  // [T+1]
@@ -44,7 +45,18 @@ struct Layout {
 // SCCS_ERR_INVALID_ARG with a message in err.
 sccs_status validate_problem(const sccs_problem* p, std::string& err);
 
-// Build the layout for G workgroups.  The problem must have been validated.
-void build_layout(const sccs_problem* p, int32_t G, Layout& L);
+// Upper bound on the number of tiles (see the .cpp for the argument), so
+// that workspace sizes can be computed without building the layout.
+int64_t tile_bound(int64_t nnz, int32_t J, int32_t G, int32_t tile_nnz);
+
+// Dimensions only (vectors empty): enough to size the workspace.
+inline void layout_dims(const sccs_problem* p, int32_t G, int32_t tile_nnz, Layout& L) {
+  L.N = p->n_patients; L.J = p->n_cols; L.G = G; L.K = p->n_rows; L.nnz = p->nnz; L.tile_nnz = tile_nnz;
+  L.tiles_cap = tile_bound(p->nnz, p->n_cols, G, tile_nnz) + 1;
+}
+
+// Build the layout for G workgroups and tiles of at most tile_nnz nonzeros
+// (except single-patient tiles).  The problem must have been validated.
+void build_layout(const sccs_problem* p, int32_t G, Layout& L, int32_t tile_nnz = kTile);
 
 }  // namespace sccs

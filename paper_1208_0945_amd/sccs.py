@@ -25,7 +25,7 @@ EXPORTS = ("sccs_default_options", "sccs_query_workspace", "sccs_create", "sccs_
            "sccs_set_prior", "sccs_set_beta", "sccs_get_beta", "sccs_sweep", "sccs_fit",
            "sccs_grad_hess", "sccs_objective", "sccs_last_kernel_ms", "sccs_last_error",
            "sccs_batch_query_workspace", "sccs_batch_create", "sccs_batch_run", "sccs_batch_get",
-           "sccs_batch_last_kernel_ms", "sccs_batch_destroy", "sccs_batch_last_error")
+           "sccs_batch_heldout", "sccs_batch_last_kernel_ms", "sccs_batch_destroy", "sccs_batch_last_error", "sccs_tune")
 
 
 class SccsError(RuntimeError):
@@ -44,7 +44,7 @@ class Problem_(ctypes.Structure):
 
 class Options_(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("n_workgroups", ctypes.c_int32),
-                ("refresh_period", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("refresh_period", ctypes.c_int32), ("tile_nnz", ctypes.c_int32),
                 ("stream", ctypes.c_void_p)]
 
 
@@ -56,6 +56,12 @@ class FitSpec_(ctypes.Structure):
     _fields_ = [("problem", ctypes.c_int32), ("n_links", ctypes.c_int32),
                 ("prior_kind", ctypes.c_void_p), ("variance", ctypes.c_void_p),
                 ("patient_weight", ctypes.c_void_p)]
+
+
+class TuneResult_(ctypes.Structure):
+    _fields_ = [("n_candidates", ctypes.c_int32), ("best", ctypes.c_int32),
+                ("n_workgroups", ctypes.c_int32 * 16), ("tile_nnz", ctypes.c_int32 * 16),
+                ("ms_per_sweep", ctypes.c_double * 16)]
 
 
 class FitResult_(ctypes.Structure):
@@ -114,8 +120,11 @@ def lib() -> ctypes.CDLL:
                                         ctypes.POINTER(Options_), ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(H)]
         L.sccs_batch_run.argtypes = [H, ctypes.POINTER(FitOpts_)]
         L.sccs_batch_get.argtypes = [H, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(FitResult_)]
+        L.sccs_batch_heldout.argtypes = [H, ctypes.c_int32, ctypes.c_int32, dp]
         L.sccs_batch_last_kernel_ms.argtypes = [H, dp]
         L.sccs_batch_destroy.argtypes = [H]
+        L.sccs_tune.argtypes = [ctypes.POINTER(Problem_), ctypes.POINTER(Options_), ctypes.c_int32, ctypes.c_double,
+                                ctypes.c_int32, ctypes.POINTER(Options_), ctypes.POINTER(TuneResult_)]
         L.sccs_batch_last_error.argtypes = [H]
         L.sccs_batch_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -148,12 +157,13 @@ class ProblemArrays:
 
 
 def options(precision: int = PREC_FP64, n_workgroups: int = 0, refresh_period: int = -1,
-            stream: Optional[int] = None) -> Options_:
+            stream: Optional[int] = None, tile_nnz: int = 0) -> Options_:
     o = Options_()
     lib().sccs_default_options(ctypes.byref(o))
     o.precision = precision
     o.n_workgroups = n_workgroups
     o.refresh_period = refresh_period
+    o.tile_nnz = tile_nnz
     o.stream = stream
     return o
 
@@ -173,14 +183,14 @@ class Handle:
     alive by this object; the stream defaults to torch's current stream."""
 
     def __init__(self, prob, weight=None, precision: int = PREC_FP64, n_workgroups: int = 0,
-                 refresh_period: int = -1, stream=None, workspace: str = "torch"):
+                 refresh_period: int = -1, stream=None, workspace: str = "torch", tile_nnz: int = 0):
         import torch
         self.torch = torch
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
         P = ProblemArrays(prob, weight)
-        o = options(precision, n_workgroups, refresh_period, stream.cuda_stream)
+        o = options(precision, n_workgroups, refresh_period, stream.cuda_stream, tile_nnz)
         n = ctypes.c_size_t()
         L = lib()
         st = L.sccs_query_workspace(ctypes.byref(P.s), ctypes.byref(o), ctypes.byref(n))
@@ -269,6 +279,22 @@ class Handle:
         return ms.value
 
 
+def tune(prob, prior_kind: int, variance: float, n_sweeps: int = 2, precision: int = PREC_FP64, weight=None):
+    """Run the library's autotuner; returns (best options dict, candidate table)."""
+    import torch  # noqa: F401
+    P = ProblemArrays(prob, weight)
+    o = options(precision, 0, -1, torch.cuda.current_stream().cuda_stream)
+    best = Options_()
+    r = TuneResult_()
+    st = lib().sccs_tune(ctypes.byref(P.s), ctypes.byref(o), int(prior_kind), float(variance), int(n_sweeps),
+                         ctypes.byref(best), ctypes.byref(r))
+    if st != OK:
+        raise SccsError(st, lib().sccs_last_error(None).decode())
+    table = [{"n_workgroups": r.n_workgroups[k], "tile_nnz": r.tile_nnz[k], "ms_per_sweep": r.ms_per_sweep[k]}
+             for k in range(r.n_candidates)]
+    return {"n_workgroups": best.n_workgroups, "tile_nnz": best.tile_nnz}, table
+
+
 class FitSpec:
     """One fit of a batch: a problem index, a chain of (prior kind, variance)
     links visited with warm starts, and optional patient weights."""
@@ -288,7 +314,7 @@ class Batch:
     """Many fits in one persistent launch (sccs_batch_*)."""
 
     def __init__(self, probs, specs, precision: int = PREC_FP64, n_workgroups: int = 0,
-                 refresh_period: int = -1, stream=None):
+                 refresh_period: int = -1, stream=None, tile_nnz: int = 0):
         import torch
         if stream is None:
             stream = torch.cuda.current_stream()
@@ -298,7 +324,7 @@ class Batch:
         parr = (Problem_ * len(self._probs))(*[P.s for P in self._probs])
         sarr = (FitSpec_ * len(self._specs))(*[s.struct() for s in self._specs])
         self._parr, self._sarr = parr, sarr
-        o = options(precision, n_workgroups, refresh_period, stream.cuda_stream)
+        o = options(precision, n_workgroups, refresh_period, stream.cuda_stream, tile_nnz)
         L = lib()
         n = ctypes.c_size_t()
         st = L.sccs_batch_query_workspace(ctypes.addressof(parr), len(self._probs), ctypes.addressof(sarr),
@@ -329,6 +355,12 @@ class Batch:
         r = FitResult_()
         self._check(lib().sccs_batch_get(self.h, int(fit), int(link), b.ctypes.data, ctypes.byref(r)))
         return b, {"sweeps": r.sweeps, "converged": bool(r.converged), "loglik": r.loglik, "logpost": r.logpost}
+
+    def heldout(self, fit: int, link: int = 0) -> float:
+        """Eq. 2 over the fit's weight-0 patients at the link's beta."""
+        v = ctypes.c_double()
+        self._check(lib().sccs_batch_heldout(self.h, int(fit), int(link), ctypes.byref(v)))
+        return v.value
 
     def last_kernel_ms(self) -> float:
         ms = ctypes.c_double()

@@ -242,9 +242,39 @@ def cv_folds(n_patients: int, n_folds: int = 10, seed: int = 0) -> np.ndarray:
     return (rng.permutation(n_patients) % n_folds).astype(np.int32)
 
 
+def bootstrap_weights(n_patients: int, n_reps: int, seed: int = 0) -> np.ndarray:
+    """[n_reps, n_patients] patient multiplicities of seeded bootstrap
+    resamples (n_patients draws with replacement each)."""
+    rng = _rng(7, seed)
+    return np.stack([np.bincount(rng.integers(0, n_patients, size=n_patients), minlength=n_patients)
+                     for _ in range(n_reps)]).astype(np.int32)
+
+
 def prior_grid(n: int = 16, lo: float = 1e-3, hi: float = 10.0) -> np.ndarray:
     """Prior variances log-spaced from lo to hi, ascending."""
     return np.logspace(math.log10(lo), math.log10(hi), n)
+
+
+def subsample_patients(prob: Problem, frac: float, seed: int = 0) -> Problem:
+    """The sub-problem made of a seeded fraction of the patients (all their
+    eras), with rows and columns renumbered; data selection only."""
+    rng = _rng(6, seed)
+    keep = np.sort(rng.choice(prob.n_patients, size=max(1, int(round(frac * prob.n_patients))), replace=False))
+    lens = np.diff(prob.patient_ptr)[keep]
+    ptr = np.zeros(len(keep) + 1, dtype=np.int64)
+    np.cumsum(lens, out=ptr[1:])
+    rows = _rows_of(prob.patient_ptr, keep)            # old row of each new row
+    new_of_old = np.full(prob.n_rows, -1, dtype=np.int64)
+    new_of_old[rows] = np.arange(len(rows))
+    mapped = new_of_old[prob.row_idx]
+    col = np.repeat(np.arange(prob.n_cols), np.diff(prob.col_ptr))
+    sel = mapped >= 0
+    col_ptr = np.zeros(prob.n_cols + 1, dtype=np.int64)
+    np.cumsum(np.bincount(col[sel], minlength=prob.n_cols), out=col_ptr[1:])
+    return Problem(name=f"{prob.name}_sub{frac:g}", n_patients=len(keep), patient_ptr=ptr,
+                   offset=prob.offset[rows].copy(), count=prob.count[rows].copy(), n_cols=prob.n_cols,
+                   col_ptr=col_ptr, row_idx=mapped[sel].astype(np.int32), beta_true=prob.beta_true.copy(),
+                   seed_info=prob.seed_info + f" subsample={frac} seed={seed}")
 
 
 def random_beta(n_cols: int, scale: float, seed: int) -> np.ndarray:

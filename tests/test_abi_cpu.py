@@ -40,7 +40,7 @@ def test_last_error_never_null():
 
 def test_default_options():
     o = sccs.options()
-    assert o.precision == sccs.PREC_FP64 and o.refresh_period == -1 and o.reserved == 0
+    assert o.precision == sccs.PREC_FP64 and o.refresh_period == -1 and o.tile_nnz == 0
 
 
 def _tiny():
@@ -96,7 +96,7 @@ def test_negative_weight_rejected():
 
 
 @pytest.mark.parametrize("opt", [{"precision": 2}, {"n_workgroups": -1}, {"n_workgroups": 4096},
-                                 {"refresh_period": -2}])
+                                 {"refresh_period": -2}, {"tile_nnz": 4}, {"tile_nnz": 65}])
 def test_invalid_options_rejected(opt):
     assert _query(_tiny(), **opt) == sccs.ERR_INVALID_ARG
 

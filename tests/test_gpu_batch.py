@@ -81,6 +81,26 @@ def test_cv_folds_with_warm_started_prior_path(sccs):
                 got, res = b.get(k, l)
                 assert res["sweeps"] == 4
                 assert rel_inf(got, beta) <= FP64_TOL, (k, l)
+                # held-out Eq. 2 over fold k's patients at the oracle's iterate
+                ho = oracle.loglik(prob, beta, weight=(folds == k).astype(np.int32))
+                assert abs(b.heldout(k, l) - ho) <= 1e-8 * abs(ho), (k, l)
+
+
+def test_bootstrap_replicates(sccs):
+    """Bootstrap replicates as integer patient multiplicities (Section 2.5);
+    the out-of-bag patients (weight 0) form each replicate's held-out set."""
+    prob = synth.zipf_problem("boot", 3000, 30, 0.1, seed_path=(9, 3))
+    wts = synth.bootstrap_weights(prob.n_patients, 6, seed=4)
+    specs = [sccs.FitSpec(0, [(sccs.PRIOR_NORMAL, 0.5)], weight=w) for w in wts]
+    with sccs.Batch([prob], specs) as b:
+        b.run(sccs.CRIT_FIXED, max_sweeps=5)
+        for r, w in enumerate(wts):
+            ref = oracle.ccd(prob, oracle.PRIOR_NORMAL, 0.5, 5, weight=w)
+            got, res = b.get(r)
+            assert rel_inf(got, ref["beta"]) <= FP64_TOL, r
+            assert abs(res["logpost"] - ref["logpost"]) <= 1e-10 * abs(ref["logpost"])
+            oob = oracle.loglik(prob, ref["beta"], weight=(w == 0).astype(np.int32))
+            assert abs(b.heldout(r) - oob) <= 1e-8 * abs(oob), r
 
 
 def test_batch_mixed_precision(sccs):
@@ -103,3 +123,17 @@ def test_batch_rejects_bad_specs(sccs):
     other = synth.tiny(n_cols=7)
     with pytest.raises(sccs.SccsError):
         sccs.Batch([probs[0], other], [sccs.FitSpec(0, [(sccs.PRIOR_NORMAL, 1.0)])])
+
+
+def test_heldout_needs_weights_and_a_run(sccs):
+    """No weights: no held-out set.  Weights without a 0: empty set, L = 0."""
+    prob = synth.tiny()
+    ones = np.ones(prob.n_patients, dtype=np.int32)
+    specs = [sccs.FitSpec(0, [(sccs.PRIOR_NORMAL, 1.0)]), sccs.FitSpec(0, [(sccs.PRIOR_NORMAL, 1.0)], weight=ones)]
+    with sccs.Batch([prob], specs) as b:
+        with pytest.raises(sccs.SccsError):
+            b.heldout(1, 0)            # link has not run
+        b.run(sccs.CRIT_FIXED, max_sweeps=2)
+        with pytest.raises(sccs.SccsError):
+            b.heldout(0, 0)            # no weights
+        assert b.heldout(1, 0) == 0.0

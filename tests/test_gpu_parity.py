@@ -39,8 +39,8 @@ def zipf_small(n_patients=20000, n_cols=300, seed=0, p0=0.1):
     return synth.zipf_problem("zipf_small", n_patients, n_cols, p0, seed_path=(8, seed))
 
 
-def run_gpu(sccs, prob, kind, var, sweeps, weight=None, precision=0, n_workgroups=0, beta0=None):
-    with sccs.Handle(prob, weight=weight, precision=precision, n_workgroups=n_workgroups) as h:
+def run_gpu(sccs, prob, kind, var, sweeps, weight=None, precision=0, n_workgroups=0, beta0=None, tile_nnz=0):
+    with sccs.Handle(prob, weight=weight, precision=precision, n_workgroups=n_workgroups, tile_nnz=tile_nnz) as h:
         h.set_prior(kind, var)
         if beta0 is not None:
             h.set_beta(beta0)
@@ -108,13 +108,14 @@ def test_abs_dxbeta_criterion(sccs):
         assert r["converged"] and abs(r["sweeps"] - ref["sweeps"]) <= 1
 
 
-@pytest.mark.parametrize("n_workgroups", [1, 3, 64, 0])
-def test_zipf_laplace_20_sweeps(sccs, n_workgroups):
+@pytest.mark.parametrize("n_workgroups,tile_nnz", [(1, 0), (3, 0), (64, 0), (0, 0), (0, 16), (97, 32)])
+def test_zipf_laplace_20_sweeps(sccs, n_workgroups, tile_nnz):
     """Mid-shaped (Zipf columns, 1+Poisson(9) eras) at 20k patients, Laplace
-    lambda = 1, 20 sweeps; several workgroup counts (ownership splits)."""
+    lambda = 1, 20 sweeps; several workgroup counts (ownership splits) and
+    tile sizes."""
     prob = zipf_small()
     ref = oracle.ccd(prob, 2, 2.0, 20)
-    beta, _ = run_gpu(sccs, prob, 2, 2.0, 20, n_workgroups=n_workgroups)
+    beta, _ = run_gpu(sccs, prob, 2, 2.0, 20, n_workgroups=n_workgroups, tile_nnz=tile_nnz)
     assert rel_inf(beta, ref["beta"]) <= FP64_TOL
     assert np.array_equal(beta == 0.0, ref["beta"] == 0.0)
 
@@ -269,3 +270,14 @@ def test_full_size_mid_parity(sccs):
             go, ho = oracle.grad_hess(prob, beta, j)
             assert abs(g - go) <= 1e-9 * max(1.0, abs(ho)), (j, g, go)
             assert abs(hh - ho) <= 1e-9 * abs(ho), (j, hh, ho)
+
+
+def test_autotuner_picks_a_candidate_and_its_schedule_is_exact(sccs):
+    prob = zipf_small(n_patients=20000, n_cols=120, seed=9)
+    best, table = sccs.tune(prob, sccs.PRIOR_LAPLACE, 2.0, n_sweeps=2)
+    assert len(table) >= 6
+    assert any(t["n_workgroups"] == best["n_workgroups"] and t["tile_nnz"] == best["tile_nnz"] for t in table)
+    assert all(t["ms_per_sweep"] > 0 for t in table)
+    ref = oracle.ccd(prob, 2, 2.0, 5)
+    beta, _ = run_gpu(sccs, prob, 2, 2.0, 5, **best)
+    assert rel_inf(beta, ref["beta"]) <= FP64_TOL

@@ -1,0 +1,93 @@
+"""Host layout builder (ownership ranges, patient-aligned tiles, index pairs
+and the row-compressed copy of X) against brute force, no GPU needed."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1208_0945_amd import sccs, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1208_0945_amd", "csrc")
+
+
+@pytest.fixture(scope="module")
+def probe(tmp_path_factory):
+    out = str(tmp_path_factory.mktemp("layout") / "liblayout_probe.so")
+    subprocess.run(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-pthread", "-I", os.path.join(ROOT, "include"),
+                    "-I", CSRC, os.path.join(ROOT, "tests", "layout_probe.cpp"),
+                    os.path.join(CSRC, "sccs_layout.cpp"), "-o", out], check=True)
+    lib = ctypes.CDLL(out)
+    lib.layout_probe.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int] + [ctypes.c_void_p] * 8
+    return lib
+
+
+def run(probe, prob, G, tile_nnz):
+    P = sccs.ProblemArrays(prob)
+    K, N, J, nnz = prob.n_rows, prob.n_patients, prob.n_cols, prob.nnz
+    pb = np.zeros(G + 1, np.int32)
+    rp = np.zeros(2 * max(nnz, 1), np.uint32)
+    own = np.zeros(J * (G + 1), np.int32)
+    era_ptr = np.zeros(K + 1, np.int32)
+    era_col = np.zeros(max(nnz, 1), np.int32)
+    nt, bound = ctypes.c_longlong(), ctypes.c_longlong()
+    ts = np.zeros(2 * nnz // tile_nnz + 2 * min(nnz, J * G) + 4, np.int32)
+    rc = probe.layout_probe(ctypes.addressof(P.s), G, tile_nnz, pb.ctypes.data, rp.ctypes.data, ts.ctypes.data,
+                            ctypes.byref(nt), own.ctypes.data, era_ptr.ctypes.data, era_col.ctypes.data,
+                            ctypes.byref(bound))
+    assert rc == 0
+    return pb, rp.reshape(-1, 2)[:nnz], ts[:nt.value + 1], own.reshape(J, G + 1), era_ptr, era_col[:nnz], bound.value
+
+
+@pytest.mark.parametrize("G,tile_nnz", [(1, 64), (7, 64), (64, 32), (256, 16)])
+def test_layout_matches_brute_force(probe, G, tile_nnz):
+    prob = synth.zipf_problem("lay", 3000, 40, 0.3, seed_path=(11, G))
+    pb, rp, ts, own, era_ptr, era_col, bound = run(probe, prob, G, tile_nnz)
+    N, J, nnz = prob.n_patients, prob.n_cols, prob.nnz
+    era_pid = np.repeat(np.arange(N), np.diff(prob.patient_ptr))
+    # index pairs
+    assert np.array_equal(rp[:, 0], prob.row_idx)
+    assert np.array_equal(rp[:, 1], era_pid[prob.row_idx])
+    # ownership: monotone ranges covering all patients
+    assert pb[0] == 0 and pb[-1] == N and np.all(np.diff(pb) >= 0)
+    owner = np.searchsorted(pb, np.arange(N), side="right") - 1
+    # tiles partition [0, nnz) in order, within (column, workgroup) ranges
+    assert ts[0] == 0 and ts[-1] == nnz and np.all(np.diff(ts) > 0)
+    assert len(ts) - 1 < bound
+    for j in range(J):
+        lo, hi = prob.col_ptr[j], prob.col_ptr[j + 1]
+        assert own[j, 0] == np.searchsorted(ts, lo) or lo == hi
+        for b in range(G):
+            for t in range(own[j, b], own[j, b + 1]):
+                e0, e1 = ts[t], ts[t + 1]
+                assert lo <= e0 < e1 <= hi
+                pids = rp[e0:e1, 1]
+                assert np.all(owner[pids] == b)
+                # whole patient segments: no patient continues across a tile edge
+                if e0 > lo:
+                    assert rp[e0 - 1, 1] != rp[e0, 1] or owner[rp[e0 - 1, 1]] != b
+                if e1 - e0 > tile_nnz:
+                    assert np.all(pids == pids[0])
+        assert own[j, G] == (own[j + 1, 0] if j + 1 < J else len(ts) - 1)
+    # compressed row storage
+    X = np.zeros((prob.n_rows, J), bool)
+    for j in range(J):
+        X[prob.column(j), j] = True
+    assert np.array_equal(np.diff(era_ptr), X.sum(axis=1))
+    for k in range(0, prob.n_rows, 97):
+        assert np.array_equal(era_col[era_ptr[k]:era_ptr[k + 1]], np.flatnonzero(X[k]))
+
+
+def test_long_patient_segment_gets_own_tile(probe):
+    # one patient with 150 eras all in column 0, plus a few small patients
+    sizes = [150, 3, 2, 4]
+    ptr = np.concatenate([[0], np.cumsum(sizes)])
+    K = int(ptr[-1])
+    prob = synth.Problem("long", len(sizes), ptr.astype(np.int64), np.full(K, 10, np.int32),
+                         np.ones(K, np.int32), 1, np.array([0, K], np.int64), np.arange(K, dtype=np.int32),
+                         np.zeros(1))
+    pb, rp, ts, own, *_ = run(probe, prob, 1, 64)
+    lens = np.diff(ts)
+    assert lens[0] == 150 and np.all(lens[1:] <= 64)
