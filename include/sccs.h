@@ -78,7 +78,7 @@ typedef struct sccs_handle sccs_handle;
  *   col_ptr     [J+1] int64: X in compressed column storage (values all 1).
  *   row_idx     [nnz] int32: rows of each column, strictly increasing.
  *   patient_weight [N] int32 >= 0, or NULL for all ones.
- * Limits: N, K, J >= 1; K < 2^31; nnz < 2^31.  Patients without events
+ * Limits: N, K, J >= 1; N < 2^28; K < 2^31; nnz < 2^31.  Patients without events
  * (n_i = 0) are accepted and carry no information (cases-only design).
  */
 typedef struct sccs_problem {
@@ -101,6 +101,12 @@ typedef struct sccs_options {
                               0 = never, -1 = default (0 for FP64, 1 for mixed) */
   int32_t tile_nnz;        /* nonzeros per tile (one wavefront each): 0 = 64, else 8..64;
                               a patient with more nonzeros in a column gets a tile of its own */
+  int32_t max_group;       /* single fit: consecutive columns that share no patient have
+                              independent Newton steps and are visited with one device-wide
+                              reduction, up to max_group columns at a time (results equal
+                              those of visiting them one by one, up to summation order);
+                              0 = 4, else 1..4 (1 = one column per reduction).  The batched
+                              form always visits one column at a time. */
   void* stream;            /* hipStream_t */
 } sccs_options;
 
@@ -118,7 +124,8 @@ typedef struct sccs_fit_result {
   double logpost;      /* L + log p(beta), constants dropped */
 } sccs_fit_result;
 
-/* Options with defaults: FP64, one workgroup per CU, default refresh, 64-nonzero tiles, NULL stream. */
+/* Options with defaults: FP64, one workgroup per CU, default refresh, 64-nonzero tiles,
+ * groups of up to 4 columns, NULL stream. */
 void sccs_default_options(sccs_options* opts);
 
 /* Device bytes sccs_create needs for this problem and these options.

@@ -75,15 +75,16 @@ __device__ __forceinline__ void poll_spread(const uint64_t* base, size_t stride,
   }
   long long spins = 0;
   while (need) {
+    // issue every outstanding load of the round, then inspect them
+    uint64_t x[kPollPer];
+#pragma unroll
+    for (int q = 0; q < kPollPer; ++q)
+      x[q] = (need & (1u << q)) ? load_agent(base + (size_t)(m0 + q * kMembersPerPass) * stride + word) : 0ull;
 #pragma unroll
     for (int q = 0; q < kPollPer; ++q) {
-      if (need & (1u << q)) {
-        const int m = m0 + q * kMembersPerPass;
-        uint64_t x = load_agent(base + (size_t)m * stride + word);
-        if ((uint32_t)(x >> 63) == tag) {
-          stage[m * kBatchSlotWords + word] = tag_decode(x);
-          need &= ~(1u << q);
-        }
+      if ((need & (1u << q)) && (uint32_t)(x[q] >> 63) == tag) {
+        stage[(m0 + q * kMembersPerPass) * kBatchSlotWords + word] = tag_decode(x[q]);
+        need &= ~(1u << q);
       }
     }
     if (!need) break;
@@ -94,7 +95,7 @@ __device__ __forceinline__ void poll_spread(const uint64_t* base, size_t stride,
       return;
     }
     if ((spins & 255) == 0 && load_agent_i(&ctrl->abort)) { *flag = 0; return; }
-    __builtin_amdgcn_s_sleep(2);
+    if (kPollSleep) __builtin_amdgcn_s_sleep(kPollSleep);
   }
 }
 
@@ -247,7 +248,7 @@ __device__ __forceinline__ void pairs_phase_a(const BatchArgs& A, const WaveMap&
       den[c] = 1.0;
       wn[c] = 0.0;
       if (head[c]) {
-        const double2 pv = A.fits[f].k.pat[pid[c]];
+        const double2 pv = A.fits[f].k.pat[pid_of(pid[c])];
         den[c] = pv.x;
         wn[c] = pv.y;
       }
@@ -272,13 +273,17 @@ __device__ __forceinline__ void pairs_phase_a(const BatchArgs& A, const WaveMap&
     if (f >= F) break;
     if (s_done[f]) continue;
     const int t0 = ixs[q][0], t1 = ixs[q][1], len0 = ixs[q][3];
-    double Gl = 0.0, Hl = 0.0;
+    Acc<1> acc;
+    acc.zero();
     bool any = false;
-    if (t0 < t1 && len0 > 64) { tile_a<WT>(A.fits[f].k, t0, Gl, Hl); any = true; }
-    for (int t = t0 + wm.P; t < t1; t += wm.P) { tile_a<WT>(A.fits[f].k, t, Gl, Hl); any = true; }
+    if (t0 < t1 && len0 > 64) { tile_a<WT, 1, false>(A.fits[f].k, t0, acc); any = true; }
+    if (t0 + wm.P < t1) {
+      tiles_a<WT, 1, false>(A.fits[f].k, t0 + wm.P, t1, wm.P, acc);
+      any = true;
+    }
     if (any) {
-      Gl = wave_sum(Gl);
-      Hl = wave_sum(Hl);
+      const double Gl = wave_sum(acc.g[0]);
+      const double Hl = wave_sum(acc.h[0]);
       if (lane == 0) {
         pp[f][slice][0] += Gl;
         pp[f][slice][1] += Hl;
@@ -320,7 +325,7 @@ __device__ __forceinline__ void pairs_phase_b(const BatchArgs& A, const WaveMap&
     for (int c = 0; c < kChunk; ++c) {
       const int f = pair_fit(wm, wave, q0 + c, F);
       den[c] = 0.0;
-      if (head[c]) den[c] = A.fits[f].k.pat[ixrp[q0 + c][lane].y].x;
+      if (head[c]) den[c] = A.fits[f].k.pat[pid_of(ixrp[q0 + c][lane].y)].x;
     }
 #pragma unroll
     for (int c = 0; c < kChunk; ++c) {
@@ -331,10 +336,10 @@ __device__ __forceinline__ void pairs_phase_b(const BatchArgs& A, const WaveMap&
       if (lane < ixs[q0 + c][3]) ((WT*)A.fits[f].k.w)[rp.x] = wnew;
       if (sizeof(WT) == 8) {
         const double num = seg_sum_v((double)wo[c], lane, seg_end[c]);
-        if (head[c]) A.fits[f].k.pat[rp.y].x = den[c] + num * dd[f][2];
+        if (head[c]) A.fits[f].k.pat[pid_of(rp.y)].x = den[c] + num * dd[f][2];
       } else {
         const double sdiff = seg_sum_v((double)wnew - (double)wo[c], lane, seg_end[c]);
-        if (head[c]) A.fits[f].k.pat[rp.y].x = den[c] + sdiff;
+        if (head[c]) A.fits[f].k.pat[pid_of(rp.y)].x = den[c] + sdiff;
       }
     }
   }
@@ -344,8 +349,9 @@ __device__ __forceinline__ void pairs_phase_b(const BatchArgs& A, const WaveMap&
     if (f >= F) break;
     if (s_done[f] || dd[f][0] == 0.0) continue;
     const int t0 = ixs[q][0], t1 = ixs[q][1], len0 = ixs[q][3];
-    if (t0 < t1 && len0 > 64) tile_b<WT>(A.fits[f].k, t0, dd[f][1], dd[f][2]);
-    for (int t = t0 + wm.P; t < t1; t += wm.P) tile_b<WT>(A.fits[f].k, t, dd[f][1], dd[f][2]);
+    const Coef cf{&dd[f][1], &dd[f][2]};
+    if (t0 < t1 && len0 > 64) tile_b<WT>(A.fits[f].k, t0, cf);
+    tiles_b<WT>(A.fits[f].k, t0 + wm.P, t1, wm.P, cf);
   }
 }
 
@@ -487,6 +493,8 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchArgs A) {
     __syncthreads();
     if (n_active == 0) break;
     pair_index(A, wm, wave, 0, s_done, s_ixs[0][wave], s_ixrp[0][wave]);
+    double2 bt_next = make_double2(0.0, 0.0);   // thread f < F: fit f's (beta_j, trust_j) for the next step
+    double ytx_next = 0.0;
     for (int j = 0; j < J && ok; ++j) {
       const int cur = j & 1;
       pairs_phase_a<WT>(A, wm, wave, s_done, s_ixs[cur][wave], s_ixrp[cur][wave], pp);
@@ -501,15 +509,25 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchArgs A) {
       }
       __syncthreads();
       if (!batch_allreduce(A.s1, A.s2, seq++, G, 2 * F, A.ctrl, part, tot, stage, &flag)) { ok = false; break; }
-      // one Newton / trust-region step per fit (lanes of wave 0)
+      // one Newton / trust-region step per fit (lanes of wave 0); (beta_j,
+      // trust_j) and Y'X_j come from the previous coordinate's prefetch
       if (tid < F) {
         const int f = tid;
         double d = 0.0;
         if (!s_done[f]) {
           const BatchFit& bf = A.fits[f];
           double2* bt = bf.bt + (size_t)b * J + j;
-          double2 v = *bt;
-          double g = bf.k.ytx[j] - tot[2 * f], h = -tot[2 * f + 1];
+          if (j == 0) {
+            bt_next = *bt;
+            ytx_next = bf.k.ytx[0];
+          }
+          const double2 v = bt_next;
+          double g = ytx_next - tot[2 * f], h = -tot[2 * f + 1];
+          if (j + 1 < J) {
+            // the next coordinate's copies: nothing writes them before its step
+            bt_next = bt[1];
+            ytx_next = bf.k.ytx[j + 1];
+          }
           if (isfinite(g) && isfinite(h)) {
             double dv = prior_step(s_kind[f], s_ivar[f], s_lam[f], v.x, g, h);
             d = fmin(fmax(dv, -v.y), v.y);

@@ -39,6 +39,7 @@ struct sccs_handle {
   int64_t* d_col_ptr = nullptr;
   int32_t* d_count = nullptr;
   int32_t* d_weight = nullptr;
+  std::vector<int32_t> gcol;  // host copy of the column groups
   Ctrl* h_ctrl = nullptr;  // pinned host mirror of the control block
 };
 
@@ -61,7 +62,7 @@ struct Carver {
 
 struct Plan {
   uint2* rp;
-  int32_t *tile_start, *own, *pb, *pptr, *era_ptr, *era_col, *offset, *count, *weight;
+  int32_t *tile_start, *own, *gcol, *pb, *pptr, *era_ptr, *era_col, *offset, *count, *weight;
   int64_t* col_ptr;
   void* w;
   double2* pat;
@@ -75,6 +76,7 @@ size_t carve(void* base, const Layout& L, int prec, bool has_weight, Plan& P) {
   P.rp = c.take<uint2>((size_t)L.nnz + 1);
   P.tile_start = c.take<int32_t>((size_t)L.tiles_cap);
   P.own = c.take<int32_t>((size_t)L.J * (L.G + 1));
+  P.gcol = c.take<int32_t>((size_t)L.J + 1);
   P.pb = c.take<int32_t>((size_t)L.G + 1);
   P.pptr = c.take<int32_t>((size_t)L.N + 1);
   P.era_ptr = c.take<int32_t>((size_t)L.K + 1);
@@ -89,8 +91,8 @@ size_t carve(void* base, const Layout& L, int prec, bool has_weight, Plan& P) {
   P.beta = c.take<double>((size_t)L.J);
   P.trust = c.take<double>((size_t)L.J);
   const size_t n1 = (size_t)2 * kMaxWorkgroups * kSlotWords, n2 = (size_t)2 * kReplicas * kGroups * kSlotWords;
-  P.slots = c.take<uint64_t>(n1);
-  P.slots2 = c.take<uint64_t>(n2);
+  P.slots = c.take<uint64_t>(kMaxGroup * kSlots1PerClass);
+  P.slots2 = c.take<uint64_t>(kMaxGroup * kSlots2PerClass);
   P.oslots = c.take<uint64_t>(n1);
   P.oslots2 = c.take<uint64_t>(n2);
   P.ctrl = c.take<Ctrl>(1);
@@ -113,6 +115,10 @@ sccs_status check_options(const sccs_options* o, std::string& err) {
   }
   if (o->tile_nnz != 0 && (o->tile_nnz < 8 || o->tile_nnz > kTile)) {
     err = "options.tile_nnz must be 0 (64) or in [8, 64]";
+    return SCCS_ERR_INVALID_ARG;
+  }
+  if (o->max_group < 0 || o->max_group > kMaxGroup) {
+    err = "options.max_group must be 0 (4) or in [1, 4]";
     return SCCS_ERR_INVALID_ARG;
   }
   return SCCS_OK;
@@ -173,6 +179,12 @@ sccs_status read_ctrl(sccs_handle* h) {
 
 sccs_status launch(sccs_handle* h, int mode, int n_sweeps, int criterion, double tol, int want_obj, int diag_j) {
   KArgs a = h->args;
+  if (mode == kModeGradHess) {
+    // group of column diag_j, and its index within the group
+    const int g = (int)(std::upper_bound(h->gcol.begin(), h->gcol.end(), diag_j) - h->gcol.begin()) - 1;
+    a.diag_g = g;
+    a.diag_c = diag_j - h->gcol[g];
+  }
   a.prior_kind = h->prior_kind < 0 ? SCCS_PRIOR_NONE : h->prior_kind;
   a.var = h->var;
   a.inv_var = 1.0 / h->var;
@@ -219,6 +231,7 @@ void sccs_default_options(sccs_options* o) {
   o->n_workgroups = 0;
   o->refresh_period = -1;
   o->tile_nnz = 0;
+  o->max_group = 0;
   o->stream = nullptr;
 }
 
@@ -261,8 +274,11 @@ sccs_status sccs_create(const sccs_problem* prob, const sccs_options* opts_in, v
   if (!h) { g_create_error = "out of host memory"; return SCCS_ERR_INVALID_ARG; }
   Layout L;
   const int32_t tile_nnz = opts.tile_nnz ? opts.tile_nnz : kTile;
+  const int32_t max_group = opts.max_group ? opts.max_group : kMaxGroup;
+  std::vector<double> ytx;
   try {
-    build_layout(prob, G, L, tile_nnz);
+    build_layout(prob, G, L, tile_nnz, max_group);
+    host_ytx(prob, prob->patient_weight, ytx);
   } catch (const std::bad_alloc&) {
     delete h;
     g_create_error = "host out of memory while building the layout";
@@ -336,7 +352,8 @@ sccs_status sccs_create(const sccs_problem* prob, const sccs_options* opts_in, v
     return bytes == 0 || hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s) == hipSuccess;
   };
   bool ok = cp(P.rp, L.rp.data(), L.rp.size() * 4) && cp(P.tile_start, L.tile_start.data(), L.tile_start.size() * 4) &&
-            cp(P.own, L.own.data(), L.own.size() * 4) && cp(P.pb, L.pb.data(), L.pb.size() * 4) &&
+            cp(P.own, L.own.data(), L.own.size() * 4) && cp(P.gcol, L.gcol.data(), L.gcol.size() * 4) &&
+            cp(P.pb, L.pb.data(), L.pb.size() * 4) && cp(P.ytx, ytx.data(), ytx.size() * 8) &&
             cp(P.pptr, L.pptr.data(), L.pptr.size() * 4) && cp(P.era_ptr, L.era_ptr.data(), L.era_ptr.size() * 4) &&
             cp(P.era_col, L.era_col.data(), L.era_col.size() * 4) &&
             cp(P.offset, prob->offset, (size_t)L.K * 4) && cp(P.count, prob->count, (size_t)L.K * 4) &&
@@ -350,25 +367,25 @@ sccs_status sccs_create(const sccs_problem* prob, const sccs_options* opts_in, v
   // reduction slots start with the tag that reductions 0 and 1 do not expect
   {
     const size_t n1 = (size_t)2 * kMaxWorkgroups * kSlotWords, n2 = (size_t)2 * kReplicas * kGroups * kSlotWords;
-    hipLaunchKernelGGL(k_fill_u64, dim3(16), dim3(256), 0, s, P.slots, n1, kSign);
-    hipLaunchKernelGGL(k_fill_u64, dim3(4), dim3(256), 0, s, P.slots2, n2, kSign);
+    hipLaunchKernelGGL(k_fill_u64, dim3(64), dim3(256), 0, s, P.slots, kMaxGroup * kSlots1PerClass, kSign);
+    hipLaunchKernelGGL(k_fill_u64, dim3(16), dim3(256), 0, s, P.slots2, kMaxGroup * kSlots2PerClass, kSign);
     hipLaunchKernelGGL(k_fill_u64, dim3(16), dim3(256), 0, s, P.oslots, n1, kSign);
     hipLaunchKernelGGL(k_fill_u64, dim3(4), dim3(256), 0, s, P.oslots2, n2, kSign);
   }
   int gp = (L.N + 255) / 256;
   if (gp > 4096) gp = 4096;
   hipLaunchKernelGGL(k_setup_patients, dim3(gp), dim3(256), 0, s, P.pptr, P.count, P.weight, P.pat, L.N);
-  int gj = L.J < 4096 ? L.J : 4096;
-  hipLaunchKernelGGL(k_setup_ytx, dim3(gj), dim3(256), 0, s, P.col_ptr, P.rp, P.count, P.weight, 0, P.ytx, L.J);
   if (hipGetLastError() != hipSuccess) return bail("setup kernel launch failed", SCCS_ERR_HIP);
 
   KArgs& a = h->args;
-  a.rp = P.rp; a.tile_start = P.tile_start; a.own = P.own; a.pb = P.pb; a.pptr = P.pptr;
+  a.rp = P.rp; a.tile_start = P.tile_start; a.own = P.own; a.gcol = P.gcol; a.n_groups = L.n_groups;
+  a.pb = P.pb; a.pptr = P.pptr;
   a.era_ptr = P.era_ptr; a.era_col = P.era_col; a.offset = P.offset; a.w = P.w; a.pat = P.pat;
   a.ytx = P.ytx; a.beta = P.beta; a.trust = P.trust; a.slots = P.slots; a.slots2 = P.slots2;
   a.oslots = P.oslots; a.oslots2 = P.oslots2;
   a.ctrl = P.ctrl; a.N = L.N; a.J = L.J; a.G = G; a.nbits = h->nbits;
   h->d_col_ptr = P.col_ptr; h->d_count = P.count; h->d_weight = P.weight;
+  h->gcol = L.gcol;
   if (refresh_all(h) != SCCS_OK) return bail(h->err, SCCS_ERR_HIP);
   if (hipStreamSynchronize(s) != hipSuccess) return bail("setup failed on the device", SCCS_ERR_HIP);
   *out = h;

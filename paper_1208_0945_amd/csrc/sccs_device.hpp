@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "sccs_limits.hpp"
+
 namespace sccs {
 
 constexpr int kBlock = 512;              // threads per persistent workgroup
@@ -15,10 +17,22 @@ constexpr int kReplicas = 8;             // copies of the group totals
 constexpr int kMaxJ = 6144;              // beta, trust, beta_prev live in LDS
 constexpr uint64_t kSign = 0x8000000000000000ull;
 constexpr long long kSpinLimit = 1ll << 22;  // bounded waits (about a second), then abort
+#ifndef SCCS_POLL_SLEEP
+#define SCCS_POLL_SLEEP 0
+#endif
+// s_sleep between two polls of a reduction slot (units of 64 clocks); a
+// chain of reductions measured fastest with none.
+constexpr int kPollSleep = SCCS_POLL_SLEEP;
+
+// Coordinate reductions of a single fit use one slot array per group size
+// (class m - 1 for m columns), each with its own sequence number, so that
+// every reduction on a slot array writes and reads the same number of words.
+constexpr size_t kSlots1PerClass = (size_t)2 * kMaxWorkgroups * kSlotWords;  // level 1, both parities
+constexpr size_t kSlots2PerClass = (size_t)2 * kReplicas * kGroups * kSlotWords;
 
 // Control block shared by all workgroups of a launch (device memory).
 struct Ctrl {
-  uint32_t seq;        // coordinate-reduction sequence number (persists across launches)
+  uint32_t seq;        // batched form: reduction sequence number (persists across launches)
   uint32_t oseq;       // objective-reduction sequence number
   int32_t abort;       // set by a workgroup that timed out
   int32_t status;      // SCCS_OK or an error code
@@ -28,12 +42,14 @@ struct Ctrl {
   int32_t pad;
   double loglik, logpost;
   double g, h;         // diagnostic output
+  uint32_t gseq[kMaxGroup];  // single fit: sequence number of each reduction class
 };
 
 struct KArgs {
   const uint2* rp;            // [nnz] (row, patient)
   const int32_t* tile_start;  // [T+1]
-  const int32_t* own;         // [J*(G+1)]
+  const int32_t* own;         // [n_groups*(G+1)]
+  const int32_t* gcol;        // [n_groups+1] first column of each group
   const int32_t* pb;          // [G+1]
   const int32_t* pptr;        // [N+1]
   const int32_t* era_ptr;     // [K+1]
@@ -44,12 +60,13 @@ struct KArgs {
   const double* ytx;          // [J]
   double* beta;               // [J]
   double* trust;              // [J]
-  uint64_t* slots;            // [2][256][16] coordinate reduction, level 1
-  uint64_t* slots2;           // [2][8 replicas][8 groups][16] group totals
+  uint64_t* slots;            // [kMaxGroup classes][2][256][16] coordinate reductions, level 1
+  uint64_t* slots2;           // [kMaxGroup classes][2][8 replicas][8 groups][16] group totals
   uint64_t* oslots;           // objective reduction, same shapes
   uint64_t* oslots2;
   Ctrl* ctrl;
   int32_t N, J, G;
+  int32_t n_groups;
   int32_t prior_kind;
   double var, inv_var, lambda;
   int32_t n_sweeps;
@@ -59,6 +76,7 @@ struct KArgs {
   int32_t want_objective;     // evaluate P after the last sweep
   int32_t mode;               // 0 sweep, 1 grad/hess of diag_j, 2 objective only
   int32_t diag_j;
+  int32_t diag_g, diag_c;     // group of diag_j and its column within the group
   int32_t nbits;              // words of each per-workgroup patient bitmap (LDS)
 };
 

@@ -46,10 +46,31 @@ namespace sccs {
 
 // ------------------------------------------------------------ wave helpers
 
+// Sum over the 64 lanes, returned to every lane.  Data-parallel-primitive
+// (DPP) lane moves on the two 32-bit halves, so no LDS traffic and no wait
+// on the LDS/scalar-memory counter: pairs, quads (quad_perm), half rows and
+// rows (mirrors), then rows 0+1 and 2+3 (row_bcast:15 into rows 1 and 3)
+// and all four (row_bcast:31 into rows 2 and 3); lane 63 holds the total,
+// read back as a scalar.  The order of the additions is fixed.
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ double dpp_add(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, Ctrl, RowMask, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), Ctrl, RowMask, 0xf, false);
+  return v + __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v = dpp_add<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v = dpp_add<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]
+  v = dpp_add<0x141, 0xf>(v);  // row_half_mirror
+  v = dpp_add<0x140, 0xf>(v);  // row_mirror
+  v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 -> rows 1, 3
+  v = dpp_add<0x143, 0xc>(v);  // row_bcast:31 -> rows 2, 3
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
 __device__ __forceinline__ uint64_t tag_encode(double v, uint32_t tag) {
@@ -114,7 +135,11 @@ __device__ __forceinline__ bool poll_tagged(const uint64_t* src, bool active, ui
 // kReplicas): polling 256 workgroups on one line serialises at the memory
 // side.  Must be called by all lanes of ONE wave of every workgroup, with the
 // workgroup's partials in part[] of that wave's lane 0.  Returns the sums in
-// out[] in all lanes of that wave.
+// out[] in all lanes of that wave.  Every reduction on one slot array must
+// use the same NV: the tag a reader waits for is told apart only from the
+// tag that reduction s-2 left in the same word.  (NV is a compile-time
+// constant so that all polling loads of a round are issued before any is
+// waited on.)
 template <int NV>
 __device__ bool allreduce2_wave(uint64_t* s1, uint64_t* s2, uint32_t seq, int G, Ctrl* ctrl,
                                 const double* part, double* out) {
@@ -171,8 +196,9 @@ __device__ bool allreduce_nonneg(uint64_t* s1, uint64_t* s2, uint32_t seq, int G
 
 // Fixed-order workgroup sum: wave butterflies, then wave 0's partials summed
 // in wave order by thread 0 (result valid in thread 0 only).
-template <int NV>
-__device__ void block_sum(const double* v_in, double* out, double (*red)[4]) {
+template <int NV, int W>
+__device__ void block_sum(const double* v_in, double* out, double (*red)[W]) {
+  static_assert(NV <= W, "reduction rows too narrow");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double v[NV];
 #pragma unroll
@@ -193,10 +219,15 @@ __device__ void block_sum(const double* v_in, double* out, double (*red)[4]) {
   __syncthreads();
 }
 
-// Same fixed-order sum, result valid in lane 0 of wave `dst` only; one
-// barrier.  red[] may be reused after the caller's next barrier.
-template <int NV>
-__device__ __forceinline__ void block_sum_to(const double* v_in, double* out, double (*red)[4], int dst) {
+// Workgroup sum delivered to wave `dst`: wave sums, then the wave partials
+// combined inside wave dst (lane q*NV + i reads wave q's word i, one LDS read
+// per lane, all in flight at once; word i is the wave sum over its lanes).
+// The order is fixed.  Result valid in all lanes of wave dst; one barrier.
+// red[] may be reused after the caller's next barrier.
+template <int NV, int W>
+__device__ __forceinline__ void block_sum_to(const double* v_in, double* out, double (*red)[W], int dst) {
+  static_assert(NV <= W, "reduction rows too narrow");
+  static_assert(kWaves * NV <= 64, "one lane per (wave, word)");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double v[NV];
 #pragma unroll
@@ -206,13 +237,10 @@ __device__ __forceinline__ void block_sum_to(const double* v_in, double* out, do
     for (int i = 0; i < NV; ++i) red[wave][i] = v[i];
   }
   __syncthreads();
-  if (wave == dst && lane == 0) {
+  if (wave == dst) {
+    const double x = lane < kWaves * NV ? red[lane / NV][lane % NV] : 0.0;
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      double s = 0.0;
-      for (int q = 0; q < kWaves; ++q) s += red[q][i];
-      out[i] = s;
-    }
+    for (int i = 0; i < NV; ++i) out[i] = wave_sum(lane % NV == i ? x : 0.0);
   }
 }
 
@@ -300,12 +328,45 @@ __device__ __forceinline__ void accum_patient(double num, double2 pv, double& Gl
   Hl += tg * fmax(1.0 - r, 0.0);
 }
 
-// ---- one tile, loads included (used for every tile but a wave's first)
+// Column of a group (bits above the patient index of rp.y) and the patient.
+__device__ __forceinline__ uint32_t col_of(uint32_t key) { return key >> kGroupShift; }
+__device__ __forceinline__ uint32_t pid_of(uint32_t key) { return key & kPidMask; }
 
-// Phase A on tile t: gather w on the tile's rows, sum per patient segment,
-// accumulate the segment's terms of G and H.
-template <typename WT>
-__device__ __forceinline__ void tile_a(const KArgs& a, int t, double& Gl, double& Hl) {
+// Per-lane accumulators of G and H for the NC columns of a group; a head
+// lane adds its segment's terms to its own column's pair.
+template <int NC>
+struct Acc {
+  double g[NC], h[NC];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int i = 0; i < NC; ++i) g[i] = h[i] = 0.0;
+  }
+  __device__ __forceinline__ void add(uint32_t c, double num, double2 pv) {
+    const double r = num / pv.x;
+    const double tg = pv.y * r;
+    const double th = tg * fmax(1.0 - r, 0.0);
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      const bool mine = NC == 1 || c == (uint32_t)i;
+      g[i] += mine ? tg : 0.0;
+      h[i] += mine ? th : 0.0;
+    }
+  }
+};
+
+// Per-column update factors e^d and e^d - 1 (LDS arrays indexed by column).
+struct Coef {
+  const double* ed;
+  const double* em1;
+};
+
+// ---- one tile, loads included
+
+// Phase A on tile t: gather w on the tile's rows, sum per (column, patient)
+// segment, accumulate the segment's terms of G and H; optionally mark the
+// tile's patients in the workgroup's bitmap.
+template <typename WT, int NC, bool kMark>
+__device__ __forceinline__ void tile_a(const KArgs& a, int t, Acc<NC>& acc, unsigned* bits = nullptr, int p0 = 0) {
   const int lane = threadIdx.x & 63;
   const WT* __restrict__ w = (const WT*)a.w;
   const int e0 = a.tile_start[t], e1 = a.tile_start[t + 1];
@@ -316,41 +377,55 @@ __device__ __forceinline__ void tile_a(const KArgs& a, int t, double& Gl, double
     double wv = act ? (double)w[rp.x] : 0.0;
     bool head;
     double num = seg_sum(wv, rp.y, lane, len, head);
-    if (head) accum_patient(num, a.pat[rp.y], Gl, Hl);
+    if (head) {
+      acc.add(col_of(rp.y), num, a.pat[pid_of(rp.y)]);
+      if (kMark) atomicOr(&bits[(pid_of(rp.y) - p0) >> 5], 1u << ((pid_of(rp.y) - p0) & 31));
+    }
   } else {
-    // a patient with more than 64 nonzeros in the column: one segment
+    // one (column, patient) segment with more than 64 nonzeros
     double s = 0.0;
     for (int e = e0 + lane; e < e1; e += 64) s += (double)w[a.rp[e].x];
     s = wave_sum(s);
-    if (lane == 0) accum_patient(s, a.pat[a.rp[e0].y], Gl, Hl);
+    if (lane == 0) {
+      const uint32_t key = a.rp[e0].y;
+      acc.add(col_of(key), s, a.pat[pid_of(key)]);
+      if (kMark) atomicOr(&bits[(pid_of(key) - p0) >> 5], 1u << ((pid_of(key) - p0) & 31));
+    }
   }
 }
 
 // Phase B on tile t: w_k <- w_k e^d on the tile's rows; den_i of each
 // segment moves by num_i (e^d - 1) (FP64), or by the exact change of the
-// stored FP32 weights summed in FP64 (mixed).
+// stored FP32 weights summed in FP64 (mixed).  Columns with a zero step
+// are left untouched (their update is the identity).
 template <typename WT>
-__device__ __forceinline__ void tile_b(const KArgs& a, int t, double ed, double em1) {
+__device__ __forceinline__ void tile_b(const KArgs& a, int t, Coef cf) {
   const int lane = threadIdx.x & 63;
   WT* __restrict__ w = (WT*)a.w;
-  const WT edw = (WT)ed;
   const int e0 = a.tile_start[t], e1 = a.tile_start[t + 1];
   const int len = e1 - e0;
   if (len <= 64) {
     bool act = lane < len;
     uint2 rp = act ? a.rp[e0 + lane] : make_uint2(0u, 0xffffffffu);
-    WT wo = act ? w[rp.x] : (WT)0;
-    WT wn = wo * edw;
-    if (act) w[rp.x] = wn;
+    const uint32_t c = act ? col_of(rp.y) : 0u;
+    const double ed = cf.ed[c], em1 = cf.em1[c];
+    const bool upd = act && em1 != 0.0;
+    WT wo = upd ? w[rp.x] : (WT)0;
+    WT wn = wo * (WT)ed;
+    if (upd) w[rp.x] = wn;
     bool head;
     if (sizeof(WT) == 8) {
       double s = seg_sum((double)wo, rp.y, lane, len, head);
-      if (head) a.pat[rp.y].x += s * em1;
+      if (head && upd) a.pat[pid_of(rp.y)].x += s * em1;
     } else {
       double s = seg_sum((double)wn - (double)wo, rp.y, lane, len, head);
-      if (head) a.pat[rp.y].x += s;
+      if (head && upd) a.pat[pid_of(rp.y)].x += s;
     }
   } else {
+    const uint32_t key = a.rp[e0].y;
+    const double ed = cf.ed[col_of(key)], em1 = cf.em1[col_of(key)];
+    if (em1 == 0.0) return;
+    const WT edw = (WT)ed;
     double s = 0.0;
     for (int e = e0 + lane; e < e1; e += 64) {
       uint32_t row = a.rp[e].x;
@@ -360,39 +435,46 @@ __device__ __forceinline__ void tile_b(const KArgs& a, int t, double ed, double 
       s += (sizeof(WT) == 8) ? (double)wo : ((double)wn - (double)wo);
     }
     s = wave_sum(s);
-    if (lane == 0) a.pat[a.rp[e0].y].x += (sizeof(WT) == 8) ? s * em1 : s;
+    if (lane == 0) a.pat[pid_of(key)].x += (sizeof(WT) == 8) ? s * em1 : s;
   }
 }
 
-// Phase A / B over all tiles of column j owned by this workgroup (the
-// diagnostic kernel's path).
+// ---- tiles t, t + stride, ... < t1 of one range, in order
+
+template <typename WT, int NC, bool kMark>
+__device__ __forceinline__ void tiles_a(const KArgs& a, int t, int t1, int stride, Acc<NC>& acc,
+                                        unsigned* bits = nullptr, int p0 = 0) {
+  for (; t < t1; t += stride) tile_a<WT, NC, kMark>(a, t, acc, bits, p0);
+}
+
 template <typename WT>
-__device__ void phase_a(const KArgs& a, int j, double& Gl, double& Hl) {
-  const size_t base = (size_t)j * (a.G + 1) + blockIdx.x;
-  const int t0 = a.own[base], t1 = a.own[base + 1];
-  for (int t = t0 + (threadIdx.x >> 6); t < t1; t += kWaves) tile_a<WT>(a, t, Gl, Hl);
+__device__ __forceinline__ void tiles_b(const KArgs& a, int t, int t1, int stride, Coef cf) {
+  for (; t < t1; t += stride) tile_b<WT>(a, t, cf);
 }
 
 // ---- the sweep's path
 //
-// Waves 0..kWorkers-1 ("workers") take tiles t0 + w, t0 + w + kWorkers, ...
-// of the current coordinate; the last wave runs the device-wide reduction.
-// Each worker keeps its first tile of a coordinate in registers: the index
-// data is prefetched two coordinates ahead, and the gathers of w and
-// (den_i, omega_i n_i) are issued one coordinate ahead, while the previous
-// coordinate's reduction is in flight.  Such a speculative gather is stale
-// only where the previous coordinate changed the state, i.e. for patients in
-// both columns; every workgroup marks the patients of each coordinate in an
-// LDS bitmap over its own patient range, and a speculative tile that holds a
-// marked patient is gathered again after the update.  The values used are
-// therefore exactly those of the sequential algorithm.
+// Coordinates are visited group by group (column groups: consecutive,
+// pairwise patient-disjoint columns, whose Newton steps are independent;
+// one device-wide reduction per group carries all of the group's partial
+// sums).  Waves 0..kWorkers-1 ("workers") take tiles t0 + w, t0 + w +
+// kWorkers, ... of the current group; the last wave runs the device-wide
+// reduction.  Each worker keeps its first tile of a group in registers: the
+// index data is prefetched two groups ahead, and the gathers of w and
+// (den_i, omega_i n_i) are issued one group ahead, while the previous
+// group's reduction is in flight.  Such a speculative gather is stale only
+// where the previous group changed the state, i.e. for patients in both;
+// every workgroup marks the patients of each group in an LDS bitmap over its
+// own patient range, and a speculative tile that holds a marked patient is
+// gathered again after the update.  The values used are therefore exactly
+// those of the sequential algorithm.
 
 constexpr int kWorkers = kWaves - 1;
 
 struct Pf {
   int t, t1;     // the wave's first tile; end of the workgroup's tile range
   int e0, len;   // that tile's nonzero range
-  uint2 rp;      // this lane's (row, patient)
+  uint2 rp;      // this lane's (row, patient | column)
 };
 
 struct Cache {
@@ -401,11 +483,11 @@ struct Cache {
   double den;    // den_i (head lanes)
   double wn;     // omega_i n_i (head lanes)
   bool head;
-  bool valid;    // gathered (possibly speculatively) for this coordinate
+  bool valid;    // gathered (possibly speculatively) for this group
 };
 
-__device__ __forceinline__ void pf_range(const KArgs& a, int j, int& t0, int& t1) {
-  const size_t base = (size_t)j * (a.G + 1) + blockIdx.x;
+__device__ __forceinline__ void pf_range(const KArgs& a, int g, int& t0, int& t1) {
+  const size_t base = (size_t)g * (a.G + 1) + blockIdx.x;
   t0 = a.own[base];
   t1 = a.own[base + 1];
 }
@@ -441,7 +523,7 @@ __device__ __forceinline__ void gather_first(const KArgs& a, const Pf& p, Cache&
     seg_layout(p.rp.y, lane, p.len, head, seg_end);
     const bool act = lane < p.len;
     double wv = act ? (double)w[p.rp.x] : 0.0;
-    double2 pv = head ? a.pat[p.rp.y] : make_double2(1.0, 0.0);
+    double2 pv = head ? a.pat[pid_of(p.rp.y)] : make_double2(1.0, 0.0);
     c.num = seg_sum_v(wv, lane, seg_end);
     c.wv = wv;
     c.den = pv.x;
@@ -457,83 +539,57 @@ __device__ __forceinline__ bool first_tile_stale(const Pf& p, const unsigned* bi
   const int lane = threadIdx.x & 63;
   bool hit = false;
   if (p.t < p.t1 && p.len <= 64 && lane < p.len) {
-    const unsigned q = p.rp.y - (unsigned)p0;
+    const unsigned q = pid_of(p.rp.y) - (unsigned)p0;
     hit = (bits[q >> 5] >> (q & 31)) & 1u;
   }
   return __ballot(hit) != 0ull;
 }
 
-// Phase A on tile t (loads included) that also marks the tile's patients.
+// Phase A of the current group for one worker wave: the cached first tile
+// (validated by the caller) plus its remaining tiles.
 template <typename WT>
-__device__ __forceinline__ void tile_a_mark(const KArgs& a, int t, double& Gl, double& Hl, unsigned* bits, int p0) {
-  const int lane = threadIdx.x & 63;
-  const WT* __restrict__ w = (const WT*)a.w;
-  const int e0 = a.tile_start[t], e1 = a.tile_start[t + 1];
-  const int len = e1 - e0;
-  if (len <= 64) {
-    bool act = lane < len;
-    uint2 rp = act ? a.rp[e0 + lane] : make_uint2(0u, 0xffffffffu);
-    double wv = act ? (double)w[rp.x] : 0.0;
-    bool head;
-    double num = seg_sum(wv, rp.y, lane, len, head);
-    if (head) {
-      accum_patient(num, a.pat[rp.y], Gl, Hl);
-      mark_patient(bits, rp.y - (unsigned)p0);
-    }
-  } else {
-    double s = 0.0;
-    for (int e = e0 + lane; e < e1; e += 64) s += (double)w[a.rp[e].x];
-    s = wave_sum(s);
-    if (lane == 0) {
-      const uint32_t pid = a.rp[e0].y;
-      accum_patient(s, a.pat[pid], Gl, Hl);
-      mark_patient(bits, pid - (unsigned)p0);
-    }
-  }
-}
-
-// Phase A of the current coordinate for one worker wave: the cached first
-// tile (validated by the caller) plus its remaining tiles.
-template <typename WT>
-__device__ __forceinline__ void phase_a_cached(const KArgs& a, const Pf& p, const Cache& c, double& Gl, double& Hl,
+__device__ __forceinline__ void phase_a_cached(const KArgs& a, const Pf& p, const Cache& c, Acc<kMaxGroup>& acc,
                                                unsigned* bits, int p0) {
   if (p.t < p.t1) {
     if (p.len <= 64) {
       if (c.head) {
-        accum_patient(c.num, make_double2(c.den, c.wn), Gl, Hl);
-        mark_patient(bits, p.rp.y - (unsigned)p0);
+        acc.add(col_of(p.rp.y), c.num, make_double2(c.den, c.wn));
+        mark_patient(bits, pid_of(p.rp.y) - (unsigned)p0);
       }
     } else {
-      tile_a_mark<WT>(a, p.t, Gl, Hl, bits, p0);
+      tile_a<WT, kMaxGroup, true>(a, p.t, acc, bits, p0);
     }
   }
-  for (int t = p.t + kWorkers; t < p.t1; t += kWorkers) tile_a_mark<WT>(a, t, Gl, Hl, bits, p0);
+  tiles_a<WT, kMaxGroup, true>(a, p.t + kWorkers, p.t1, kWorkers, acc, bits, p0);
 }
 
 template <typename WT>
-__device__ __forceinline__ void phase_b_cached(const KArgs& a, const Pf& p, const Cache& c, double ed, double em1) {
+__device__ __forceinline__ void phase_b_cached(const KArgs& a, const Pf& p, const Cache& c, Coef cf) {
   const int lane = threadIdx.x & 63;
   WT* __restrict__ w = (WT*)a.w;
   if (p.t < p.t1) {
     if (p.len <= 64) {
       const bool act = lane < p.len;
+      const uint32_t col = act ? col_of(p.rp.y) : 0u;
+      const double ed = cf.ed[col], em1 = cf.em1[col];
+      const bool upd = act && em1 != 0.0;
       const WT wo = (WT)c.wv;
       const WT wn = wo * (WT)ed;
-      if (act) w[p.rp.x] = wn;
+      if (upd) w[p.rp.x] = wn;
       if (sizeof(WT) == 8) {
-        if (c.head) a.pat[p.rp.y].x = c.den + c.num * em1;
+        if (c.head && upd) a.pat[pid_of(p.rp.y)].x = c.den + c.num * em1;
       } else {
         bool head;
         int seg_end;
         seg_layout(p.rp.y, lane, p.len, head, seg_end);
-        double s = seg_sum_v((double)wn - (double)wo, lane, seg_end);
-        if (head) a.pat[p.rp.y].x = c.den + s;
+        double s = seg_sum_v(upd ? (double)wn - (double)wo : 0.0, lane, seg_end);
+        if (head && upd) a.pat[pid_of(p.rp.y)].x = c.den + s;
       }
     } else {
-      tile_b<WT>(a, p.t, ed, em1);
+      tile_b<WT>(a, p.t, cf);
     }
   }
-  for (int t = p.t + kWorkers; t < p.t1; t += kWorkers) tile_b<WT>(a, t, ed, em1);
+  tiles_b<WT>(a, p.t + kWorkers, p.t1, kWorkers, cf);
 }
 
 // Exact recomputation of w = L x exp(X beta) and den = M w for patients
@@ -561,7 +617,7 @@ __device__ __forceinline__ void refresh_range(const KArgs& a, const double* beta
 // for the change criterion sum_k |eta_k - eta_k(sweep start)| over owned eras.
 // Called by all threads of every workgroup; results valid in all threads.
 __device__ __forceinline__ bool objective(const KArgs& a, const double* sbeta, const double* sprev, int p0, int p1,
-                                       uint32_t oseq, double* out3, double (*red)[4], double* bc, int* bci) {
+                                          uint32_t oseq, double* out3, double (*red)[4], double* bc, int* bci) {
   const int tid = threadIdx.x;
   double loc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int i = p0 + tid; i < p1; i += kBlock) {
@@ -613,20 +669,26 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
   double* strust = lds_dyn + a.J;       // [J]
   double* sprev = lds_dyn + 2 * a.J;    // [J] beta at the start of the sweep
   __shared__ double red[kWaves][4];
+  __shared__ double redg[kWaves][2 * kMaxGroup];
   __shared__ double bc[8];
   __shared__ int bci[4];
+  __shared__ double s_ed[kMaxGroup], s_em1[kMaxGroup];
 
   const int tid = threadIdx.x, b = blockIdx.x;
   for (int j = tid; j < a.J; j += kBlock) {
     sbeta[j] = a.beta[j];
     strust[j] = a.trust[j];
   }
-  uint32_t seq = a.ctrl->seq;     // identical in all workgroups (written by the previous launch)
+  // identical in all workgroups (written by the previous launch)
+  uint32_t gseq[kMaxGroup];   // sequence number per reduction class
+#pragma unroll
+  for (int c = 0; c < kMaxGroup; ++c) gseq[c] = a.ctrl->gseq[c];
   uint32_t oseq = a.ctrl->oseq;
   int since_refresh = a.ctrl->since_refresh;
   __syncthreads();
 
   const int p0 = a.pb[b], p1 = a.pb[b + 1];
+  const int NG = a.n_groups;
   bool ok = true;
   int status = SCCS_OK;
   double lp_prev = 0.0;
@@ -639,87 +701,150 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
   double L = 0.0, P = 0.0;
   const int wave = tid >> 6, lane = tid & 63;
   const bool worker = wave < kWorkers;
-  unsigned* bits0 = (unsigned*)(lds_dyn + 3 * a.J);   // patients of even coordinates
-  unsigned* bits1 = bits0 + a.nbits;                  // patients of odd coordinates
+  unsigned* bits0 = (unsigned*)(lds_dyn + 3 * a.J);   // patients of even groups
+  unsigned* bits1 = bits0 + a.nbits;                  // patients of odd groups
+  const Coef cf{s_ed, s_em1};
   while (ok && sweep < a.n_sweeps) {
     if (a.criterion == SCCS_CRIT_ABS_DXBETA)
       for (int j = tid; j < a.J; j += kBlock) sprev[j] = sbeta[j];
     for (int i = tid; i < 2 * a.nbits; i += kBlock) bits0[i] = 0u;
-    // pipeline start: indices of coordinates 0 and 1; nothing speculated
+    // pipeline start: indices of groups 0 and 1; nothing speculated
     Pf pf_cur, pf_next;
     {
       int t0, t1;
       pf_range(a, 0, t0, t1);
       pf_tile(a, t0, t1, pf_cur);
-      pf_range(a, a.J > 1 ? 1 : 0, t0, t1);
+      pf_range(a, NG > 1 ? 1 : 0, t0, t1);
       pf_tile(a, t0, t1, pf_next);
     }
     Cache c_cur, c_next;
     c_cur.valid = false;
-    double ytx_cur = (wave == kPoller && lane == 0) ? a.ytx[0] : 0.0;
+    // group bounds gcol[g], gcol[g+1], gcol[g+2] roll through registers, each
+    // loaded two groups before it is needed
+    int j0 = a.gcol[0], gc1 = a.gcol[1], gc2 = NG > 1 ? a.gcol[2] : gc1;
+    int m = gc1 - j0;
+    double ytx_cur = (wave == kPoller && lane < m) ? a.ytx[j0 + lane] : 0.0;
     __syncthreads();
-    for (int j = 0; j < a.J; ++j) {
-      unsigned* bits_cur = (j & 1) ? bits1 : bits0;
-      unsigned* bits_prev = (j & 1) ? bits0 : bits1;
-      const bool has_next = j + 1 < a.J;
+    for (int g = 0; g < NG; ++g) {
+      unsigned* bits_cur = (g & 1) ? bits1 : bits0;
+      unsigned* bits_prev = (g & 1) ? bits0 : bits1;
+      const bool has_next = g + 1 < NG;
       int nt0 = 0, nt1 = 0;
-      if (j + 2 < a.J) pf_range(a, j + 2, nt0, nt1);
-      const double ytx_next = (wave == kPoller && lane == 0 && has_next) ? a.ytx[j + 1] : 0.0;
+      if (g + 2 < NG) pf_range(a, g + 2, nt0, nt1);
+      const int gc3 = g + 3 <= NG ? a.gcol[g + 3] : gc2;
+      const int j0n = gc1;
+      const int mn = has_next ? gc2 - gc1 : 0;
+      const double ytx_next = (wave == kPoller && lane < mn) ? a.ytx[j0n + lane] : 0.0;
 
       // phase A: validate the speculative first tile, then accumulate
-      double Gl = 0.0, Hl = 0.0;
+      Acc<kMaxGroup> acc;
+      acc.zero();
       if (worker) {
-        if (!c_cur.valid || (j > 0 && first_tile_stale(pf_cur, bits_prev, p0))) gather_first<WT>(a, pf_cur, c_cur);
-        phase_a_cached<WT>(a, pf_cur, c_cur, Gl, Hl, bits_cur, p0);
+        if (!c_cur.valid || (g > 0 && first_tile_stale(pf_cur, bits_prev, p0))) gather_first<WT>(a, pf_cur, c_cur);
+        phase_a_cached<WT>(a, pf_cur, c_cur, acc, bits_cur, p0);
       }
-      double loc[2] = {Gl, Hl}, part[2] = {0.0, 0.0};
-      block_sum_to<2>(loc, part, red, kPoller);
+      double loc[2 * kMaxGroup], part[2 * kMaxGroup];
+#pragma unroll
+      for (int i = 0; i < kMaxGroup; ++i) {
+        loc[2 * i] = acc.g[i];
+        loc[2 * i + 1] = acc.h[i];
+        part[2 * i] = part[2 * i + 1] = 0.0;
+      }
+      switch (m) {   // sum only the words of the group's columns (m is uniform)
+        case 1: block_sum_to<2>(loc, part, redg, kPoller); break;
+#if SCCS_MAX_GROUP >= 2
+        case 2: block_sum_to<4>(loc, part, redg, kPoller); break;
+#endif
+        default: block_sum_to<2 * kMaxGroup>(loc, part, redg, kPoller); break;
+      }
       Pf pf_next2;
       pf_next2.t = pf_next2.t1 = 0;
       c_next.valid = false;
       if (worker) {
-        // in the shadow of the reduction: clear the bitmap of coordinate
-        // j+1, gather coordinate j+1 speculatively, load indices of j+2
+        // in the shadow of the reduction: clear the bitmap of group g+1,
+        // gather group g+1 speculatively, load indices of group g+2
         unsigned* bits_next = bits_prev;
         for (int i = tid; i < a.nbits; i += kWorkers * 64) bits_next[i] = 0u;
         if (has_next) gather_first<WT>(a, pf_next, c_next);
-        if (j + 2 < a.J) pf_tile(a, nt0, nt1, pf_next2);
+        if (g + 2 < NG) pf_tile(a, nt0, nt1, pf_next2);
       } else {
-        // device-wide reduction, then the Newton / trust-region step (Eq. 4)
-        double tot[2];
-        const bool okr = allreduce2_wave<2>(a.slots, a.slots2, seq, a.G, a.ctrl, part, tot);
-        if (lane == 0) {
-          double g = ytx_cur - tot[0], h = -tot[1];
-          double d = 0.0;
-          int bad = !(isfinite(g) && isfinite(h));
+        // device-wide reduction of the group's 2m partials, then one
+        // Newton / trust-region step (Eq. 4) per column, lane c for column
+        // j0 + c (the columns are independent)
+        double tot[2 * kMaxGroup];
+        const int cls = m - 1;
+        uint32_t sq = gseq[0];
+#pragma unroll
+        for (int c = 1; c < kMaxGroup; ++c)
+          if (cls == c) sq = gseq[c];
+        uint64_t* s1 = a.slots + cls * kSlots1PerClass;
+        uint64_t* s2 = a.slots2 + cls * kSlots2PerClass;
+#pragma unroll
+        for (int i = 0; i < 2 * kMaxGroup; ++i) tot[i] = 0.0;
+        bool okr;
+        switch (m) {   // one width per slot class, fixed at compile time
+          case 1: okr = allreduce2_wave<2>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
+#if SCCS_MAX_GROUP >= 2
+          case 2: okr = allreduce2_wave<4>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
+#endif
+#if SCCS_MAX_GROUP >= 3
+          case 3: okr = allreduce2_wave<6>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
+#endif
+          default: okr = allreduce2_wave<2 * kMaxGroup>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
+        }
+
+        double Gc = 0.0, Hc = 0.0;
+#pragma unroll
+        for (int i = 0; i < kMaxGroup; ++i)
+          if (lane == i) {
+            Gc = tot[2 * i];
+            Hc = tot[2 * i + 1];
+          }
+        double d = 0.0;
+        int bad = 0;
+        if (lane < m) {
+          const double gg = ytx_cur - Gc, hh = -Hc;
+          bad = !(isfinite(gg) && isfinite(hh));
           if (okr && !bad) {
-            double bj = sbeta[j], tr = strust[j];
-            double dv = prior_step(a.prior_kind, a.inv_var, a.lambda, bj, g, h);
+            const int j = j0 + lane;
+            const double bj = sbeta[j], tr = strust[j];
+            const double dv = prior_step(a.prior_kind, a.inv_var, a.lambda, bj, gg, hh);
             d = fmin(fmax(dv, -tr), tr);
             strust[j] = fmax(2.0 * fabs(d), 0.5 * tr);
-            double nb = bj + d;
+            const double nb = bj + d;
             if (!isfinite(nb)) { bad = 1; d = 0.0; }
             else sbeta[j] = nb;
           }
+        }
+        if (lane < kMaxGroup) {
           const double em1 = expm1(d);
-          bc[0] = d;
-          bc[1] = 1.0 + em1;
-          bc[2] = em1;
+          s_ed[lane] = 1.0 + em1;
+          s_em1[lane] = em1;
+        }
+        const bool any_step = __ballot(d != 0.0) != 0ull;
+        const bool any_bad = __ballot(bad != 0) != 0ull;
+        if (lane == 0) {
           bci[0] = okr ? 1 : 0;
-          bci[1] = bad;
+          bci[1] = any_bad ? 1 : 0;
+          bci[2] = any_step ? 1 : 0;
         }
       }
-      ++seq;
       __syncthreads();
-      const double d = bc[0], ed = bc[1], em1 = bc[2];
+#pragma unroll
+      for (int c = 0; c < kMaxGroup; ++c)
+        if (m - 1 == c) ++gseq[c];
       if (!bci[0]) { ok = false; break; }
       if (bci[1]) { status = SCCS_ERR_NUMERIC; ok = false; break; }
-      if (worker && d != 0.0) phase_b_cached<WT>(a, pf_cur, c_cur, ed, em1);
+      if (worker && bci[2]) phase_b_cached<WT>(a, pf_cur, c_cur, cf);
       __syncthreads();
       pf_cur = pf_next;
       pf_next = pf_next2;
       c_cur = c_next;
       ytx_cur = ytx_next;
+      j0 = j0n;
+      m = mn;
+      gc1 = gc2;
+      gc2 = gc3;
     }
     if (!ok) break;
     ++sweep;
@@ -756,7 +881,7 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
       a.ctrl->converged = converged;
       a.ctrl->loglik = L;
       a.ctrl->logpost = P;
-      a.ctrl->seq = seq;
+      for (int c = 0; c < kMaxGroup; ++c) a.ctrl->gseq[c] = gseq[c];
       a.ctrl->oseq = oseq;
       a.ctrl->since_refresh = since_refresh;
       if (status != SCCS_OK) a.ctrl->status = status;
@@ -764,8 +889,9 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
   }
 }
 
-// Diagnostics: g_j, h_j of column diag_j at the current beta (mode 1), or the
-// objective (mode 2).  Same ownership and reductions as the sweep kernel.
+// Diagnostics: g_j, h_j of column diag_j (column diag_c of group diag_g) at
+// the current beta (mode 1), or the objective (mode 2).  Same ownership and
+// reductions as the sweep kernel.
 template <typename WT>
 __global__ void __launch_bounds__(kBlock) k_diag(KArgs a) {
   extern __shared__ double lds_dyn[];
@@ -775,7 +901,7 @@ __global__ void __launch_bounds__(kBlock) k_diag(KArgs a) {
   __shared__ int bci[4];
   const int tid = threadIdx.x, b = blockIdx.x;
   for (int j = tid; j < a.J; j += kBlock) sbeta[j] = a.beta[j];
-  uint32_t seq = a.ctrl->seq, oseq = a.ctrl->oseq;
+  uint32_t seq = a.ctrl->gseq[0], oseq = a.ctrl->oseq;   // one column: reduction class 0
   __syncthreads();
   const int p0 = a.pb[b], p1 = a.pb[b + 1];
   if (a.mode == kModeObjective) {
@@ -783,16 +909,25 @@ __global__ void __launch_bounds__(kBlock) k_diag(KArgs a) {
     bool ok = objective(a, sbeta, sbeta, p0, p1, oseq++, o3, red, bc, bci);
     if (b == 0 && tid == 0 && ok) { a.ctrl->loglik = o3[0]; a.ctrl->logpost = o3[1]; }
   } else {
-    const int j = a.diag_j;
-    double Gl = 0.0, Hl = 0.0;
-    phase_a<WT>(a, j, Gl, Hl);
-    double loc[2] = {Gl, Hl}, part[2], tot[2];
-    block_sum<2>(loc, part, red);
-    bool ok = allreduce_nonneg<2>(a.slots, a.slots2, seq++, a.G, a.ctrl, part, tot, bc, bci);
-    if (b == 0 && tid == 0 && ok) { a.ctrl->g = a.ytx[j] - tot[0]; a.ctrl->h = -tot[1]; }
+    Acc<kMaxGroup> acc;
+    acc.zero();
+    int t0, t1;
+    pf_range(a, a.diag_g, t0, t1);
+    for (int t = t0 + (tid >> 6); t < t1; t += kWaves) tile_a<WT, kMaxGroup, false>(a, t, acc);
+    double loc[2] = {0.0, 0.0}, part2[2];
+#pragma unroll
+    for (int i = 0; i < kMaxGroup; ++i)
+      if (i == a.diag_c) {
+        loc[0] = acc.g[i];
+        loc[1] = acc.h[i];
+      }
+    block_sum<2>(loc, part2, red);
+    double tot[2];
+    bool ok = allreduce_nonneg<2>(a.slots, a.slots2, seq++, a.G, a.ctrl, part2, tot, bc, bci);
+    if (b == 0 && tid == 0 && ok) { a.ctrl->g = a.ytx[a.diag_j] - tot[0]; a.ctrl->h = -tot[1]; }
   }
   __syncthreads();
-  if (b == 0 && tid == 0) { a.ctrl->seq = seq; a.ctrl->oseq = oseq; }
+  if (b == 0 && tid == 0) { a.ctrl->gseq[0] = seq; a.ctrl->oseq = oseq; }
 }
 
 // ------------------------------------------------------------ setup kernels

@@ -54,6 +54,7 @@ sccs_status validate_problem(const sccs_problem* p, std::string& err) {
     return fail(err, "n_patients, n_rows and n_cols must be >= 1");
   if (p->n_rows >= (int64_t)std::numeric_limits<int32_t>::max())
     return fail(err, "n_rows must be < 2^31");
+  if (p->n_patients > (int32_t)kPidMask) return fail(err, "n_patients must be < 2^28");
   if (p->nnz < 0 || p->nnz >= (int64_t)std::numeric_limits<int32_t>::max())
     return fail(err, "nnz must be in [0, 2^31)");
   if (!p->patient_ptr || !p->offset || !p->count || !p->col_ptr || (p->nnz > 0 && !p->row_idx))
@@ -105,10 +106,12 @@ int64_t tile_bound(int64_t nnz, int32_t J, int32_t G, int32_t tile_nnz) {
   return 2 * nnz / tile_nnz + 2 * ranges + 1;
 }
 
-void build_layout(const sccs_problem* p, int32_t G, Layout& L, int32_t tile_nnz) {
+void build_layout(const sccs_problem* p, int32_t G, Layout& L, int32_t tile_nnz, int32_t max_group) {
   const int32_t N = p->n_patients, J = p->n_cols;
   const int64_t K = p->n_rows, nnz = p->nnz;
   L.N = N; L.J = J; L.G = G; L.K = K; L.nnz = nnz; L.tile_nnz = tile_nnz;
+  if (max_group < 1) max_group = 1;
+  if (max_group > kMaxGroup) max_group = kMaxGroup;
 
   // patient ranges balanced by era count
   L.pb.assign(G + 1, 0);
@@ -122,9 +125,6 @@ void build_layout(const sccs_problem* p, int32_t G, Layout& L, int32_t tile_nnz)
     L.pb[G] = N;
     for (int32_t b = 1; b <= G; ++b) L.pb[b] = std::max(L.pb[b], L.pb[b - 1]);
   }
-  std::vector<int32_t> owner(N);
-  for (int32_t b = 0; b < G; ++b)
-    for (int32_t i = L.pb[b]; i < L.pb[b + 1]; ++i) owner[i] = b;
 
   L.pptr.resize((size_t)N + 1);
   std::vector<int32_t> era_pid((size_t)K);
@@ -136,33 +136,89 @@ void build_layout(const sccs_problem* p, int32_t G, Layout& L, int32_t tile_nnz)
   });
   L.pptr[N] = (int32_t)K;
 
-  L.rp.resize((size_t)nnz * 2);
-  parallel_ranges(nnz, [&](int64_t lo, int64_t hi) {
-    for (int64_t e = lo; e < hi; ++e) {
-      int32_t r = p->row_idx[e];
-      L.rp[2 * e] = (uint32_t)r;
-      L.rp[2 * e + 1] = (uint32_t)era_pid[r];
+  // column groups: greedy runs of pairwise patient-disjoint columns
+  L.gcol.assign(1, 0);
+  if (max_group == 1) {
+    for (int32_t j = 1; j <= J; ++j) L.gcol.push_back(j);
+  } else {
+    std::vector<int32_t> stamp((size_t)N, -1);
+    int32_t gid = 0, size = 0;
+    for (int32_t j = 0; j < J; ++j) {
+      bool clash = size >= max_group;
+      for (int64_t e = p->col_ptr[j]; e < p->col_ptr[j + 1] && !clash; ++e)
+        clash = stamp[era_pid[p->row_idx[e]]] == gid;
+      if (clash) {
+        L.gcol.push_back(j);
+        ++gid;
+        size = 0;
+      }
+      for (int64_t e = p->col_ptr[j]; e < p->col_ptr[j + 1]; ++e) stamp[era_pid[p->row_idx[e]]] = gid;
+      ++size;
     }
-  });
+    L.gcol.push_back(J);
+  }
+  const int32_t NG = (int32_t)L.gcol.size() - 1;
+  L.n_groups = NG;
 
-  // tiles, column by column in parallel: tile starts of column j, and the
-  // number of tiles of each (j, b) range
-  std::vector<std::vector<int32_t>> col_tiles(J);
-  std::vector<int32_t> range_tiles((size_t)J * G, 0);
+  // cwb[j*(G+1) + b]: first CSC position of column j at or after workgroup b's eras
+  std::vector<int64_t> cwb((size_t)J * (G + 1));
   parallel_ranges(J, [&](int64_t jlo, int64_t jhi) {
     for (int64_t j = jlo; j < jhi; ++j) {
-      std::vector<int32_t>& ts = col_tiles[j];
-      int64_t e = p->col_ptr[j], end = p->col_ptr[j + 1];
+      const int32_t* r0 = p->row_idx + p->col_ptr[j];
+      const int32_t* r1 = p->row_idx + p->col_ptr[j + 1];
+      for (int32_t b = 0; b < G; ++b) {
+        const int64_t era0 = p->patient_ptr[L.pb[b]];
+        cwb[(size_t)j * (G + 1) + b] = (int64_t)(std::lower_bound(r0, r1, (int32_t)era0) - p->row_idx);
+      }
+      cwb[(size_t)j * (G + 1) + G] = p->col_ptr[j + 1];
+    }
+  });
+  // start of each (group, workgroup) block in the group order
+  std::vector<int64_t> bstart((size_t)NG * G + 1, 0);
+  for (int32_t g = 0; g < NG; ++g)
+    for (int32_t b = 0; b < G; ++b) {
+      int64_t n = 0;
+      for (int32_t j = L.gcol[g]; j < L.gcol[g + 1]; ++j)
+        n += cwb[(size_t)j * (G + 1) + b + 1] - cwb[(size_t)j * (G + 1) + b];
+      bstart[(size_t)g * G + b + 1] = bstart[(size_t)g * G + b] + n;
+    }
+
+  // (row, patient | column-in-group) in group order
+  L.rp.resize((size_t)nnz * 2);
+  parallel_ranges(NG, [&](int64_t glo, int64_t ghi) {
+    for (int64_t g = glo; g < ghi; ++g)
+      for (int32_t b = 0; b < G; ++b) {
+        int64_t pos = bstart[(size_t)g * G + b];
+        for (int32_t j = L.gcol[g]; j < L.gcol[g + 1]; ++j) {
+          const uint32_t c = (uint32_t)(j - L.gcol[g]) << kGroupShift;
+          for (int64_t e = cwb[(size_t)j * (G + 1) + b]; e < cwb[(size_t)j * (G + 1) + b + 1]; ++e, ++pos) {
+            const int32_t r = p->row_idx[e];
+            L.rp[2 * pos] = (uint32_t)r;
+            L.rp[2 * pos + 1] = (uint32_t)era_pid[r] | c;
+          }
+        }
+      }
+  });
+
+  // tiles, group by group in parallel: tile starts of group g, and the
+  // number of tiles of each (g, b) block
+  std::vector<std::vector<int32_t>> grp_tiles(NG);
+  std::vector<int32_t> range_tiles((size_t)NG * G, 0);
+  parallel_ranges(NG, [&](int64_t glo, int64_t ghi) {
+    for (int64_t g = glo; g < ghi; ++g) {
+      std::vector<int32_t>& ts = grp_tiles[g];
       for (int32_t b = 0; b < G; ++b) {
         const size_t first = ts.size();
+        int64_t e = bstart[(size_t)g * G + b];
+        const int64_t end = bstart[(size_t)g * G + b + 1];
         int64_t cur_len = -1;
-        while (e < end && owner[era_pid[p->row_idx[e]]] == b) {
-          const int32_t pid = era_pid[p->row_idx[e]];
+        while (e < end) {
+          const uint32_t key = L.rp[2 * e + 1];
           const int64_t s = e;
-          while (e < end && era_pid[p->row_idx[e]] == pid) ++e;
+          while (e < end && L.rp[2 * e + 1] == key) ++e;
           const int64_t seg = e - s;
           if (seg > tile_nnz) {
-            ts.push_back((int32_t)s);  // a patient with more nonzeros than a tile: a tile of its own
+            ts.push_back((int32_t)s);  // a segment longer than a tile: a tile of its own
             cur_len = -1;
           } else if (cur_len < 0 || cur_len + seg > tile_nnz) {
             ts.push_back((int32_t)s);
@@ -171,32 +227,32 @@ void build_layout(const sccs_problem* p, int32_t G, Layout& L, int32_t tile_nnz)
             cur_len += seg;
           }
         }
-        range_tiles[(size_t)j * G + b] = (int32_t)(ts.size() - first);
+        range_tiles[(size_t)g * G + b] = (int32_t)(ts.size() - first);
       }
     }
   });
-  std::vector<int64_t> col_first((size_t)J + 1, 0);
-  for (int32_t j = 0; j < J; ++j) col_first[j + 1] = col_first[j] + (int64_t)col_tiles[j].size();
-  L.tile_start.resize((size_t)col_first[J] + 1);
-  L.own.assign((size_t)J * (G + 1), 0);
+  std::vector<int64_t> grp_first((size_t)NG + 1, 0);
+  for (int32_t g = 0; g < NG; ++g) grp_first[g + 1] = grp_first[g] + (int64_t)grp_tiles[g].size();
+  L.tile_start.resize((size_t)grp_first[NG] + 1);
+  L.own.assign((size_t)NG * (G + 1), 0);
   std::atomic<int32_t> max_per_wg{0};
-  parallel_ranges(J, [&](int64_t jlo, int64_t jhi) {
+  parallel_ranges(NG, [&](int64_t glo, int64_t ghi) {
     int32_t mx = 0;
-    for (int64_t j = jlo; j < jhi; ++j) {
-      std::copy(col_tiles[j].begin(), col_tiles[j].end(), L.tile_start.begin() + col_first[j]);
-      int64_t t = col_first[j];
+    for (int64_t g = glo; g < ghi; ++g) {
+      std::copy(grp_tiles[g].begin(), grp_tiles[g].end(), L.tile_start.begin() + grp_first[g]);
+      int64_t t = grp_first[g];
       for (int32_t b = 0; b < G; ++b) {
-        L.own[(size_t)j * (G + 1) + b] = (int32_t)t;
-        t += range_tiles[(size_t)j * G + b];
-        mx = std::max(mx, range_tiles[(size_t)j * G + b]);
+        L.own[(size_t)g * (G + 1) + b] = (int32_t)t;
+        t += range_tiles[(size_t)g * G + b];
+        mx = std::max(mx, range_tiles[(size_t)g * G + b]);
       }
-      L.own[(size_t)j * (G + 1) + G] = (int32_t)t;
+      L.own[(size_t)g * (G + 1) + G] = (int32_t)t;
     }
     int32_t cur = max_per_wg.load();
     while (mx > cur && !max_per_wg.compare_exchange_weak(cur, mx)) {
     }
   });
-  L.tile_start[col_first[J]] = (int32_t)nnz;
+  L.tile_start[grp_first[NG]] = (int32_t)nnz;
   L.max_tiles_per_wg = max_per_wg.load();
 
   // compressed row storage of X (columns ascending within a row)
@@ -207,6 +263,29 @@ void build_layout(const sccs_problem* p, int32_t G, Layout& L, int32_t tile_nnz)
   std::vector<int32_t> fill(L.era_ptr.begin(), L.era_ptr.end() - 1);
   for (int32_t j = 0; j < J; ++j)
     for (int64_t e = p->col_ptr[j]; e < p->col_ptr[j + 1]; ++e) L.era_col[(size_t)fill[p->row_idx[e]]++] = j;
+}
+
+}  // namespace sccs
+
+namespace sccs {
+
+void host_ytx(const sccs_problem* p, const int32_t* weight, std::vector<double>& ytx) {
+  const int32_t N = p->n_patients, J = p->n_cols;
+  std::vector<int32_t> era_pid((size_t)p->n_rows);
+  for (int32_t i = 0; i < N; ++i)
+    for (int64_t k = p->patient_ptr[i]; k < p->patient_ptr[i + 1]; ++k) era_pid[k] = i;
+  ytx.assign((size_t)J, 0.0);
+  parallel_ranges(J, [&](int64_t jlo, int64_t jhi) {
+    for (int64_t j = jlo; j < jhi; ++j) {
+      double s = 0.0;
+      for (int64_t e = p->col_ptr[j]; e < p->col_ptr[j + 1]; ++e) {
+        const int32_t r = p->row_idx[e];
+        const double om = weight ? (double)weight[era_pid[r]] : 1.0;
+        s += om * (double)p->count[r];
+      }
+      ytx[j] = s;
+    }
+  });
 }
 
 }  // namespace sccs

@@ -7,24 +7,35 @@
 // owner, so consecutive coordinates need no device-wide synchronisation
 // beyond the reduction of the two partial sums of Eqs. 7 and 9.
 //
-// Tiles.  The nonzeros of column j (compressed column storage, Section 2.4
-// "Representation in Memory") are cut into tiles of at most 64 entries -- one
-// wavefront -- that hold whole patient segments and never straddle an
-// ownership boundary.  A patient with more than 64 nonzeros in one column
-// gets a tile of its own (a "long" tile, walked in 64-wide chunks).  Tiles
-// cover [0, nnz) in order: tile t is [tile_start[t], tile_start[t+1]).
-// own[j*(G+1) + b] is the first tile of column j owned by workgroup b;
-// own[j*(G+1) + G] closes column j.
+// Column groups.  Consecutive columns that share no patient are independent
+// coordinates: the Newton step of one does not depend on the update of the
+// other (the update of column j changes only the state of column j's
+// patients), so a run of such columns can be visited with ONE device-wide
+// reduction carrying all their partial sums, with results identical to
+// visiting them one by one.  Columns are cut greedily, in order, into groups
+// of at most max_group pairwise patient-disjoint columns (gcol[g] is the
+// first column of group g).  max_group = 1 gives one column per group.
+//
+// Tiles.  The nonzeros of a group (compressed column storage, Section 2.4
+// "Representation in Memory") are reordered group by group, then by owning
+// workgroup, then column by column in CSC order, and cut into tiles of at
+// most tile_nnz entries -- one wavefront each -- that hold whole (column,
+// patient) segments and never straddle an ownership boundary.  A segment
+// longer than tile_nnz gets a tile of its own (a "long" tile, walked in
+// 64-wide chunks).  Tile t is [tile_start[t], tile_start[t+1]) of that
+// order.  own[g*(G+1) + b] is the first tile of group g owned by workgroup
+// b; own[g*(G+1) + G] closes group g.  rp[e] = (row, patient | c << 28)
+// with c the column's index within its group.
 #pragma once
 #include <cstdint>
 #include <string>
 #include <vector>
 
 #include "sccs.h"
+#include "sccs_limits.hpp"
 
 namespace sccs {
 
-constexpr int kTile = 64;
 
 struct Layout {
   int32_t N = 0, J = 0, G = 0, tile_nnz = kTile;
@@ -33,7 +44,9 @@ struct Layout {
   std::vector<int32_t> pb;          // [G+1] patient bounds per workgroup
   std::vector<uint32_t> rp;         // [2*nnz] (row, patient) per nonzero, CSC order
   std::vector<int32_t> tile_start;  // [T+1]
-  std::vector<int32_t> own;         // [J*(G+1)]
+  std::vector<int32_t> own;         // [n_groups*(G+1)]
+  int32_t n_groups = 0;
+  std::vector<int32_t> gcol;        // [n_groups+1] first column of each group
   std::vector<int32_t> pptr;        // [N+1] patient_ptr as int32
   std::vector<int32_t> era_ptr;     // [K+1] compressed row storage of X
   std::vector<int32_t> era_col;     // [nnz]
@@ -55,8 +68,13 @@ inline void layout_dims(const sccs_problem* p, int32_t G, int32_t tile_nnz, Layo
   L.tiles_cap = tile_bound(p->nnz, p->n_cols, G, tile_nnz) + 1;
 }
 
-// Build the layout for G workgroups and tiles of at most tile_nnz nonzeros
-// (except single-patient tiles).  The problem must have been validated.
-void build_layout(const sccs_problem* p, int32_t G, Layout& L, int32_t tile_nnz = kTile);
+// Build the layout for G workgroups, tiles of at most tile_nnz nonzeros
+// (except single-segment tiles) and column groups of at most max_group
+// columns.  The problem must have been validated.
+void build_layout(const sccs_problem* p, int32_t G, Layout& L, int32_t tile_nnz = kTile, int32_t max_group = 1);
+
+// Y'X_j with patient weights (NULL = 1), summed on the host; the terms are
+// integers, so the sum is exact in any order.
+void host_ytx(const sccs_problem* p, const int32_t* weight, std::vector<double>& ytx);
 
 }  // namespace sccs

@@ -45,7 +45,7 @@ class Problem_(ctypes.Structure):
 class Options_(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("n_workgroups", ctypes.c_int32),
                 ("refresh_period", ctypes.c_int32), ("tile_nnz", ctypes.c_int32),
-                ("stream", ctypes.c_void_p)]
+                ("max_group", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class FitOpts_(ctypes.Structure):
@@ -157,13 +157,14 @@ class ProblemArrays:
 
 
 def options(precision: int = PREC_FP64, n_workgroups: int = 0, refresh_period: int = -1,
-            stream: Optional[int] = None, tile_nnz: int = 0) -> Options_:
+            stream: Optional[int] = None, tile_nnz: int = 0, max_group: int = 0) -> Options_:
     o = Options_()
     lib().sccs_default_options(ctypes.byref(o))
     o.precision = precision
     o.n_workgroups = n_workgroups
     o.refresh_period = refresh_period
     o.tile_nnz = tile_nnz
+    o.max_group = max_group
     o.stream = stream
     return o
 
@@ -183,14 +184,15 @@ class Handle:
     alive by this object; the stream defaults to torch's current stream."""
 
     def __init__(self, prob, weight=None, precision: int = PREC_FP64, n_workgroups: int = 0,
-                 refresh_period: int = -1, stream=None, workspace: str = "torch", tile_nnz: int = 0):
+                 refresh_period: int = -1, stream=None, workspace: str = "torch", tile_nnz: int = 0,
+                 max_group: int = 0):
         import torch
         self.torch = torch
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
         P = ProblemArrays(prob, weight)
-        o = options(precision, n_workgroups, refresh_period, stream.cuda_stream, tile_nnz)
+        o = options(precision, n_workgroups, refresh_period, stream.cuda_stream, tile_nnz, max_group)
         n = ctypes.c_size_t()
         L = lib()
         st = L.sccs_query_workspace(ctypes.byref(P.s), ctypes.byref(o), ctypes.byref(n))

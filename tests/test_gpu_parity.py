@@ -39,8 +39,10 @@ def zipf_small(n_patients=20000, n_cols=300, seed=0, p0=0.1):
     return synth.zipf_problem("zipf_small", n_patients, n_cols, p0, seed_path=(8, seed))
 
 
-def run_gpu(sccs, prob, kind, var, sweeps, weight=None, precision=0, n_workgroups=0, beta0=None, tile_nnz=0):
-    with sccs.Handle(prob, weight=weight, precision=precision, n_workgroups=n_workgroups, tile_nnz=tile_nnz) as h:
+def run_gpu(sccs, prob, kind, var, sweeps, weight=None, precision=0, n_workgroups=0, beta0=None, tile_nnz=0,
+            max_group=0):
+    with sccs.Handle(prob, weight=weight, precision=precision, n_workgroups=n_workgroups, tile_nnz=tile_nnz,
+                     max_group=max_group) as h:
         h.set_prior(kind, var)
         if beta0 is not None:
             h.set_beta(beta0)
@@ -70,6 +72,20 @@ def test_grad_hess_at_warm_start_match_oracle(sccs, precision, tol):
             go, ho = oracle.grad_hess(prob, beta, j)
             assert abs(g - go) <= tol * max(1.0, abs(ho)), (j, g, go)
             assert abs(hh - ho) <= tol * max(1.0, abs(ho)), (j, hh, ho)
+
+
+def test_grad_hess_inside_column_groups(sccs):
+    """Columns at every position of multi-column groups (this problem has
+    groups of up to four pairwise patient-disjoint columns)."""
+    prob = zipf_small()
+    beta = synth.random_beta(prob.n_cols, 0.3, 5)
+    with sccs.Handle(prob) as h:
+        h.set_beta(beta)
+        for j in range(0, prob.n_cols, 3):
+            g, hh = h.grad_hess(j)
+            go, ho = oracle.grad_hess(prob, beta, j)
+            assert abs(g - go) <= 1e-11 * max(1.0, abs(ho)), (j, g, go)
+            assert abs(hh - ho) <= 1e-11 * max(1.0, abs(ho)), (j, hh, ho)
 
 
 @pytest.mark.parametrize("kind,var", [(1, 1.0), (2, 2.0), (0, 1.0), (2, 0.02)])
@@ -108,14 +124,15 @@ def test_abs_dxbeta_criterion(sccs):
         assert r["converged"] and abs(r["sweeps"] - ref["sweeps"]) <= 1
 
 
-@pytest.mark.parametrize("n_workgroups,tile_nnz", [(1, 0), (3, 0), (64, 0), (0, 0), (0, 16), (97, 32)])
-def test_zipf_laplace_20_sweeps(sccs, n_workgroups, tile_nnz):
+@pytest.mark.parametrize("n_workgroups,tile_nnz,max_group",
+                         [(1, 0, 0), (3, 0, 0), (64, 0, 0), (0, 0, 0), (0, 16, 0), (97, 32, 0), (0, 0, 1), (5, 0, 2)])
+def test_zipf_laplace_20_sweeps(sccs, n_workgroups, tile_nnz, max_group):
     """Mid-shaped (Zipf columns, 1+Poisson(9) eras) at 20k patients, Laplace
-    lambda = 1, 20 sweeps; several workgroup counts (ownership splits) and
-    tile sizes."""
+    lambda = 1, 20 sweeps; several workgroup counts (ownership splits), tile
+    sizes and column-group sizes (1 = one column per reduction)."""
     prob = zipf_small()
     ref = oracle.ccd(prob, 2, 2.0, 20)
-    beta, _ = run_gpu(sccs, prob, 2, 2.0, 20, n_workgroups=n_workgroups, tile_nnz=tile_nnz)
+    beta, _ = run_gpu(sccs, prob, 2, 2.0, 20, n_workgroups=n_workgroups, tile_nnz=tile_nnz, max_group=max_group)
     assert rel_inf(beta, ref["beta"]) <= FP64_TOL
     assert np.array_equal(beta == 0.0, ref["beta"] == 0.0)
 

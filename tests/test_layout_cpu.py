@@ -20,11 +20,12 @@ def probe(tmp_path_factory):
                     "-I", CSRC, os.path.join(ROOT, "tests", "layout_probe.cpp"),
                     os.path.join(CSRC, "sccs_layout.cpp"), "-o", out], check=True)
     lib = ctypes.CDLL(out)
-    lib.layout_probe.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int] + [ctypes.c_void_p] * 8
+    lib.layout_probe.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int] + [ctypes.c_void_p] * 10
+    lib.ytx_probe.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     return lib
 
 
-def run(probe, prob, G, tile_nnz):
+def run(probe, prob, G, tile_nnz, max_group=1):
     P = sccs.ProblemArrays(prob)
     K, N, J, nnz = prob.n_rows, prob.n_patients, prob.n_cols, prob.nnz
     pb = np.zeros(G + 1, np.int32)
@@ -32,13 +33,18 @@ def run(probe, prob, G, tile_nnz):
     own = np.zeros(J * (G + 1), np.int32)
     era_ptr = np.zeros(K + 1, np.int32)
     era_col = np.zeros(max(nnz, 1), np.int32)
-    nt, bound = ctypes.c_longlong(), ctypes.c_longlong()
+    gcol = np.zeros(J + 1, np.int32)
+    nt, bound, ng = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_int()
     ts = np.zeros(2 * nnz // tile_nnz + 2 * min(nnz, J * G) + 4, np.int32)
-    rc = probe.layout_probe(ctypes.addressof(P.s), G, tile_nnz, pb.ctypes.data, rp.ctypes.data, ts.ctypes.data,
-                            ctypes.byref(nt), own.ctypes.data, era_ptr.ctypes.data, era_col.ctypes.data,
-                            ctypes.byref(bound))
+    rc = probe.layout_probe(ctypes.addressof(P.s), G, tile_nnz, max_group, pb.ctypes.data, rp.ctypes.data,
+                            ts.ctypes.data, ctypes.byref(nt), own.ctypes.data, era_ptr.ctypes.data,
+                            era_col.ctypes.data, ctypes.byref(bound), gcol.ctypes.data, ctypes.byref(ng))
     assert rc == 0
-    return pb, rp.reshape(-1, 2)[:nnz], ts[:nt.value + 1], own.reshape(J, G + 1), era_ptr, era_col[:nnz], bound.value
+    n_groups = ng.value
+    if max_group == 1:
+        return pb, rp.reshape(-1, 2)[:nnz], ts[:nt.value + 1], own.reshape(J, G + 1), era_ptr, era_col[:nnz], bound.value
+    return (pb, rp.reshape(-1, 2)[:nnz], ts[:nt.value + 1], own[:n_groups * (G + 1)].reshape(n_groups, G + 1),
+            bound.value, gcol[:n_groups + 1])
 
 
 @pytest.mark.parametrize("G,tile_nnz", [(1, 64), (7, 64), (64, 32), (256, 16)])
@@ -91,3 +97,67 @@ def test_long_patient_segment_gets_own_tile(probe):
     pb, rp, ts, own, *_ = run(probe, prob, 1, 64)
     lens = np.diff(ts)
     assert lens[0] == 150 and np.all(lens[1:] <= 64)
+
+
+@pytest.mark.parametrize("G,tile_nnz,max_group", [(1, 64, 4), (7, 32, 4), (64, 16, 2), (256, 64, 4)])
+def test_grouped_layout(probe, G, tile_nnz, max_group):
+    """Column groups: greedy maximal runs of pairwise patient-disjoint
+    columns (at most max_group); the group order of the index pairs; tiles
+    within (group, workgroup) blocks holding whole (column, patient)
+    segments."""
+    prob = synth.zipf_problem("grp", 4000, 60, 0.02, seed_path=(11, 100 + G))
+    pb, rp, ts, own, bound, gcol = run(probe, prob, G, tile_nnz, max_group)
+    N, J, nnz = prob.n_patients, prob.n_cols, prob.nnz
+    era_pid = np.repeat(np.arange(N), np.diff(prob.patient_ptr))
+    pats = [set(era_pid[prob.column(j)].tolist()) for j in range(J)]
+    # groups: ordered cover of the columns, disjoint inside, maximal
+    assert gcol[0] == 0 and gcol[-1] == J and np.all(np.diff(gcol) >= 1) and np.all(np.diff(gcol) <= max_group)
+    for g in range(len(gcol) - 1):
+        seen = set()
+        for j in range(gcol[g], gcol[g + 1]):
+            assert not (seen & pats[j]), (g, j)
+            seen |= pats[j]
+        if gcol[g + 1] < J and gcol[g + 1] - gcol[g] < max_group:
+            assert seen & pats[gcol[g + 1]], "a group ended although the next column was disjoint"
+    assert len(gcol) - 1 < J, "the synthetic problem should have some disjoint neighbours"
+    # index pairs: group order, then workgroup, then column, then CSC order
+    owner = np.searchsorted(pb, np.arange(N), side="right") - 1
+    expect = []
+    for g in range(len(gcol) - 1):
+        for b in range(G):
+            for c, j in enumerate(range(gcol[g], gcol[g + 1])):
+                rows = prob.column(j)
+                rows = rows[owner[era_pid[rows]] == b]
+                expect.extend((int(r), int(era_pid[r]) | (c << 28)) for r in rows)
+    assert np.array_equal(rp, np.array(expect, dtype=np.uint32).reshape(-1, 2))
+    # tiles
+    assert ts[0] == 0 and ts[-1] == nnz and np.all(np.diff(ts) > 0) and len(ts) - 1 < bound
+    pos = 0
+    for g in range(len(gcol) - 1):
+        for b in range(G):
+            n = sum(int(np.sum(owner[era_pid[prob.column(j)]] == b)) for j in range(gcol[g], gcol[g + 1]))
+            t0, t1 = own[g, b], own[g, b + 1]
+            if n == 0:
+                assert t0 == t1
+                continue
+            assert ts[t0] == pos and ts[t1] == pos + n
+            for t in range(t0, t1):
+                e0, e1 = ts[t], ts[t + 1]
+                keys = rp[e0:e1, 1]
+                if e1 - e0 > tile_nnz:
+                    assert np.all(keys == keys[0])
+                if e0 > pos:
+                    assert rp[e0 - 1, 1] != rp[e0, 1]
+            pos += n
+
+
+def test_host_ytx(probe):
+    prob = synth.zipf_problem("ytx", 2000, 25, 0.1, seed_path=(11, 7))
+    w = (np.arange(prob.n_patients) % 3).astype(np.int32)
+    P = sccs.ProblemArrays(prob, w)
+    out = np.zeros(prob.n_cols)
+    probe.ytx_probe(ctypes.addressof(P.s), out.ctypes.data)
+    era_pid = np.repeat(np.arange(prob.n_patients), np.diff(prob.patient_ptr))
+    for j in range(prob.n_cols):
+        rows = prob.column(j)
+        assert out[j] == float(np.sum(w[era_pid[rows]] * prob.count[rows]))
