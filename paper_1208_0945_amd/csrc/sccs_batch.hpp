@@ -225,8 +225,8 @@ __device__ __forceinline__ void pairs_phase_a(const BatchArgs& A, const WaveMap&
   for (int q0 = 0; q0 < kFitsPerWave; q0 += kChunk) {
     if (pair_fit(wm, wave, q0, F) >= F) break;
     double wv[kChunk], den[kChunk], wn[kChunk];
-    bool head[kChunk];
-    int seg_end[kChunk];
+    bool lead[kChunk];
+    int seg_start[kChunk];
     uint32_t pid[kChunk];
 #pragma unroll
     for (int c = 0; c < kChunk; ++c) {
@@ -235,10 +235,10 @@ __device__ __forceinline__ void pairs_phase_a(const BatchArgs& A, const WaveMap&
       const uint2 rp = ixrp[q0 + c][lane];
       pid[c] = rp.y;
       wv[c] = 0.0;
-      head[c] = false;
-      seg_end[c] = lane;
+      lead[c] = false;
+      seg_start[c] = lane;
       if (f < F && t < t1 && len <= 64) {
-        seg_layout(rp.y, lane, len, head[c], seg_end[c]);
+        seg_layout(rp.y, lane, len, lead[c], seg_start[c]);
         if (lane < len) wv[c] = (double)((const WT*)A.fits[f].k.w)[rp.x];
       }
     }
@@ -247,7 +247,7 @@ __device__ __forceinline__ void pairs_phase_a(const BatchArgs& A, const WaveMap&
       const int f = pair_fit(wm, wave, q0 + c, F);
       den[c] = 1.0;
       wn[c] = 0.0;
-      if (head[c]) {
+      if (lead[c]) {
         const double2 pv = A.fits[f].k.pat[pid_of(pid[c])];
         den[c] = pv.x;
         wn[c] = pv.y;
@@ -256,9 +256,9 @@ __device__ __forceinline__ void pairs_phase_a(const BatchArgs& A, const WaveMap&
 #pragma unroll
     for (int c = 0; c < kChunk; ++c) {
       const int f = pair_fit(wm, wave, q0 + c, F);
-      const double num = seg_sum_v(wv[c], lane, seg_end[c]);
+      const double num = seg_sum_v(wv[c], lane, seg_start[c]);
       double Gl = 0.0, Hl = 0.0;
-      if (head[c]) accum_patient(num, make_double2(den[c], wn[c]), Gl, Hl);
+      if (lead[c]) accum_patient(num, make_double2(den[c], wn[c]), Gl, Hl);
       Gl = wave_sum(Gl);
       Hl = wave_sum(Hl);
       if (f < F && lane == 0) {
@@ -305,8 +305,8 @@ __device__ __forceinline__ void pairs_phase_b(const BatchArgs& A, const WaveMap&
     if (pair_fit(wm, wave, q0, F) >= F) break;
     WT wo[kChunk];
     double den[kChunk];
-    bool head[kChunk], live[kChunk];
-    int seg_end[kChunk];
+    bool lead[kChunk], live[kChunk];
+    int seg_start[kChunk];
 #pragma unroll
     for (int c = 0; c < kChunk; ++c) {
       const int f = pair_fit(wm, wave, q0 + c, F);
@@ -314,10 +314,10 @@ __device__ __forceinline__ void pairs_phase_b(const BatchArgs& A, const WaveMap&
       const uint2 rp = ixrp[q0 + c][lane];
       live[c] = f < F && !s_done[f] && dd[f][0] != 0.0 && t < t1 && len <= 64;
       wo[c] = (WT)0;
-      head[c] = false;
-      seg_end[c] = lane;
+      lead[c] = false;
+      seg_start[c] = lane;
       if (live[c]) {
-        seg_layout(rp.y, lane, len, head[c], seg_end[c]);
+        seg_layout(rp.y, lane, len, lead[c], seg_start[c]);
         if (lane < len) wo[c] = ((const WT*)A.fits[f].k.w)[rp.x];
       }
     }
@@ -325,7 +325,7 @@ __device__ __forceinline__ void pairs_phase_b(const BatchArgs& A, const WaveMap&
     for (int c = 0; c < kChunk; ++c) {
       const int f = pair_fit(wm, wave, q0 + c, F);
       den[c] = 0.0;
-      if (head[c]) den[c] = A.fits[f].k.pat[pid_of(ixrp[q0 + c][lane].y)].x;
+      if (lead[c]) den[c] = A.fits[f].k.pat[pid_of(ixrp[q0 + c][lane].y)].x;
     }
 #pragma unroll
     for (int c = 0; c < kChunk; ++c) {
@@ -335,11 +335,11 @@ __device__ __forceinline__ void pairs_phase_b(const BatchArgs& A, const WaveMap&
       const WT wnew = wo[c] * (WT)dd[f][1];
       if (lane < ixs[q0 + c][3]) ((WT*)A.fits[f].k.w)[rp.x] = wnew;
       if (sizeof(WT) == 8) {
-        const double num = seg_sum_v((double)wo[c], lane, seg_end[c]);
-        if (head[c]) A.fits[f].k.pat[pid_of(rp.y)].x = den[c] + num * dd[f][2];
+        const double num = seg_sum_v((double)wo[c], lane, seg_start[c]);
+        if (lead[c]) A.fits[f].k.pat[pid_of(rp.y)].x = den[c] + num * dd[f][2];
       } else {
-        const double sdiff = seg_sum_v((double)wnew - (double)wo[c], lane, seg_end[c]);
-        if (head[c]) A.fits[f].k.pat[pid_of(rp.y)].x = den[c] + sdiff;
+        const double sdiff = seg_sum_v((double)wnew - (double)wo[c], lane, seg_start[c]);
+        if (lead[c]) A.fits[f].k.pat[pid_of(rp.y)].x = den[c] + sdiff;
       }
     }
   }

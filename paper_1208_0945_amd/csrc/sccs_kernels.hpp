@@ -289,34 +289,56 @@ struct Prec<float> {
 
 // ------------------------------------------------------------ segmented sums
 
-// Segment layout of a tile: head lanes start a patient segment, seg_end is
-// the last lane of this lane's segment.  pid is sorted ascending over the
-// active lanes [0, len).  Shuffles only, no memory.
-__device__ __forceinline__ void seg_layout(uint32_t pid, int lane, int len, bool& head, int& seg_end) {
-  uint32_t pid_next = __shfl_down(pid, 1, 64);
-  uint32_t pid_prev = __shfl_up(pid, 1, 64);
-  bool act = lane < len;
-  bool tail = act && (lane == len - 1 || pid_next != pid);
-  head = act && (lane == 0 || pid_prev != pid);
-  uint64_t tails = __ballot(tail);
-  seg_end = act ? lane + (int)__builtin_ctzll(tails >> lane) : lane;
+// Segment layout of a tile.  The active lanes [0, len) hold (column,
+// patient) keys in segments of equal keys; the lead lane of a segment is its
+// last lane, seg_start the first lane of this lane's segment.  Neighbour keys
+// come from DPP wave shifts by one lane (no LDS).
+__device__ __forceinline__ void seg_layout(uint32_t key, int lane, int len, bool& lead, int& seg_start) {
+  const uint32_t key_next = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)key, 0x130, 0xf, 0xf, false);  // wave_shl:1
+  const uint32_t key_prev = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)key, 0x138, 0xf, 0xf, false);  // wave_shr:1
+  const bool act = lane < len;
+  lead = act && (lane == len - 1 || key_next != key);
+  const bool first = act && (lane == 0 || key_prev != key);
+  const uint64_t firsts = __ballot(first);
+  const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+  seg_start = act ? 63 - (int)__builtin_clzll(firsts & upto) : lane;
 }
 
-// Sum of v over this lane's segment (valid in head lanes): a suffix scan
-// restricted to the segment, fixed order.
-__device__ __forceinline__ double seg_sum_v(double v, int lane, int seg_end) {
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    double o = __shfl_down(v, d, 64);
-    if (lane + d <= seg_end) v += o;
-  }
+// Inclusive prefix sum of v within this lane's segment, so that the lead
+// lane holds the segment sum: a fixed-order scan with DPP row shifts by 1, 2,
+// 4 and 8 inside each 16-lane row, then the carries of row_bcast:15 (into
+// rows 1 and 3) and row_bcast:31 (into rows 2 and 3), each term added only
+// when its source lane lies in the same segment.
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, Ctrl, RowMask, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), Ctrl, RowMask, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double seg_sum_v(double v, int lane, int seg_start) {
+  const int r = lane & 15;
+  double o;
+  o = dpp_move<0x111, 0xf>(v);  // row_shr:1
+  if (r >= 1 && lane - 1 >= seg_start) v += o;
+  o = dpp_move<0x112, 0xf>(v);  // row_shr:2
+  if (r >= 2 && lane - 2 >= seg_start) v += o;
+  o = dpp_move<0x114, 0xf>(v);  // row_shr:4
+  if (r >= 4 && lane - 4 >= seg_start) v += o;
+  o = dpp_move<0x118, 0xf>(v);  // row_shr:8
+  if (r >= 8 && lane - 8 >= seg_start) v += o;
+  o = dpp_move<0x142, 0xa>(v);  // row_bcast:15: lane 15 -> row 1, lane 47 -> row 3
+  if ((lane & 16) && seg_start <= (lane & ~15) - 1) v += o;
+  o = dpp_move<0x143, 0xc>(v);  // row_bcast:31: lane 31 -> rows 2 and 3
+  if (lane >= 32 && seg_start <= 31) v += o;
   return v;
 }
 
-__device__ __forceinline__ double seg_sum(double v, uint32_t pid, int lane, int len, bool& head) {
-  int seg_end;
-  seg_layout(pid, lane, len, head, seg_end);
-  return seg_sum_v(v, lane, seg_end);
+__device__ __forceinline__ double seg_sum(double v, uint32_t key, int lane, int len, bool& lead) {
+  int seg_start;
+  seg_layout(key, lane, len, lead, seg_start);
+  return seg_sum_v(v, lane, seg_start);
 }
 
 // Contribution of one patient segment to G and H (the transform of Eq. 8
@@ -332,7 +354,7 @@ __device__ __forceinline__ void accum_patient(double num, double2 pv, double& Gl
 __device__ __forceinline__ uint32_t col_of(uint32_t key) { return key >> kGroupShift; }
 __device__ __forceinline__ uint32_t pid_of(uint32_t key) { return key & kPidMask; }
 
-// Per-lane accumulators of G and H for the NC columns of a group; a head
+// Per-lane accumulators of G and H for the NC columns of a group; a lead
 // lane adds its segment's terms to its own column's pair.
 template <int NC>
 struct Acc {
@@ -375,9 +397,9 @@ __device__ __forceinline__ void tile_a(const KArgs& a, int t, Acc<NC>& acc, unsi
     bool act = lane < len;
     uint2 rp = act ? a.rp[e0 + lane] : make_uint2(0u, 0xffffffffu);
     double wv = act ? (double)w[rp.x] : 0.0;
-    bool head;
-    double num = seg_sum(wv, rp.y, lane, len, head);
-    if (head) {
+    bool lead;
+    double num = seg_sum(wv, rp.y, lane, len, lead);
+    if (lead) {
       acc.add(col_of(rp.y), num, a.pat[pid_of(rp.y)]);
       if (kMark) atomicOr(&bits[(pid_of(rp.y) - p0) >> 5], 1u << ((pid_of(rp.y) - p0) & 31));
     }
@@ -413,13 +435,13 @@ __device__ __forceinline__ void tile_b(const KArgs& a, int t, Coef cf) {
     WT wo = upd ? w[rp.x] : (WT)0;
     WT wn = wo * (WT)ed;
     if (upd) w[rp.x] = wn;
-    bool head;
+    bool lead;
     if (sizeof(WT) == 8) {
-      double s = seg_sum((double)wo, rp.y, lane, len, head);
-      if (head && upd) a.pat[pid_of(rp.y)].x += s * em1;
+      double s = seg_sum((double)wo, rp.y, lane, len, lead);
+      if (lead && upd) a.pat[pid_of(rp.y)].x += s * em1;
     } else {
-      double s = seg_sum((double)wn - (double)wo, rp.y, lane, len, head);
-      if (head && upd) a.pat[pid_of(rp.y)].x += s;
+      double s = seg_sum((double)wn - (double)wo, rp.y, lane, len, lead);
+      if (lead && upd) a.pat[pid_of(rp.y)].x += s;
     }
   } else {
     const uint32_t key = a.rp[e0].y;
@@ -479,10 +501,10 @@ struct Pf {
 
 struct Cache {
   double wv;     // gathered weight
-  double num;    // segment sum (head lanes)
-  double den;    // den_i (head lanes)
-  double wn;     // omega_i n_i (head lanes)
-  bool head;
+  double num;    // segment sum (lead lanes)
+  double den;    // den_i (lead lanes)
+  double wn;     // omega_i n_i (lead lanes)
+  bool lead;
   bool valid;    // gathered (possibly speculatively) for this group
 };
 
@@ -511,24 +533,24 @@ template <typename WT>
 __device__ __forceinline__ void gather_first(const KArgs& a, const Pf& p, Cache& c) {
   const int lane = threadIdx.x & 63;
   c.valid = true;
-  c.head = false;
+  c.lead = false;
   c.wv = 0.0;
   c.num = 0.0;
   c.den = 1.0;
   c.wn = 0.0;
   if (p.t < p.t1 && p.len <= 64) {
     const WT* __restrict__ w = (const WT*)a.w;
-    bool head;
-    int seg_end;
-    seg_layout(p.rp.y, lane, p.len, head, seg_end);
+    bool lead;
+    int seg_start;
+    seg_layout(p.rp.y, lane, p.len, lead, seg_start);
     const bool act = lane < p.len;
     double wv = act ? (double)w[p.rp.x] : 0.0;
-    double2 pv = head ? a.pat[pid_of(p.rp.y)] : make_double2(1.0, 0.0);
-    c.num = seg_sum_v(wv, lane, seg_end);
+    double2 pv = lead ? a.pat[pid_of(p.rp.y)] : make_double2(1.0, 0.0);
+    c.num = seg_sum_v(wv, lane, seg_start);
     c.wv = wv;
     c.den = pv.x;
     c.wn = pv.y;
-    c.head = head;
+    c.lead = lead;
   }
 }
 
@@ -552,7 +574,7 @@ __device__ __forceinline__ void phase_a_cached(const KArgs& a, const Pf& p, cons
                                                unsigned* bits, int p0) {
   if (p.t < p.t1) {
     if (p.len <= 64) {
-      if (c.head) {
+      if (c.lead) {
         acc.add(col_of(p.rp.y), c.num, make_double2(c.den, c.wn));
         mark_patient(bits, pid_of(p.rp.y) - (unsigned)p0);
       }
@@ -577,13 +599,13 @@ __device__ __forceinline__ void phase_b_cached(const KArgs& a, const Pf& p, cons
       const WT wn = wo * (WT)ed;
       if (upd) w[p.rp.x] = wn;
       if (sizeof(WT) == 8) {
-        if (c.head && upd) a.pat[pid_of(p.rp.y)].x = c.den + c.num * em1;
+        if (c.lead && upd) a.pat[pid_of(p.rp.y)].x = c.den + c.num * em1;
       } else {
-        bool head;
-        int seg_end;
-        seg_layout(p.rp.y, lane, p.len, head, seg_end);
-        double s = seg_sum_v(upd ? (double)wn - (double)wo : 0.0, lane, seg_end);
-        if (head && upd) a.pat[pid_of(p.rp.y)].x = c.den + s;
+        bool lead;
+        int seg_start;
+        seg_layout(p.rp.y, lane, p.len, lead, seg_start);
+        double s = seg_sum_v(upd ? (double)wn - (double)wo : 0.0, lane, seg_start);
+        if (lead && upd) a.pat[pid_of(p.rp.y)].x = c.den + s;
       }
     } else {
       tile_b<WT>(a, p.t, cf);
