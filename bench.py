@@ -83,7 +83,6 @@ def profiled_traffic(kernel_ms):
     """HBM bytes per launch of the sweep kernel from the committed counter
     summary, if the kernel sources are unchanged since the counters were
     taken; otherwise None."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "k_ccd_mid_fp64_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -92,11 +91,21 @@ def profiled_traffic(kernel_ms):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    csrc = os.path.join(ROOT, "paper_1208_0945_amd", "csrc")
-    src = "".join(open(os.path.join(csrc, f)).read() for f in ("sccs_kernels.hpp", "sccs_device.hpp"))
-    if hashlib.sha256(src.encode()).hexdigest()[:16] != kv.get("kernel_source_sha"):
+    if kernel_source_sha() != kv.get("kernel_source_sha"):
         return None
     return float(kv["traffic_bytes_per_launch"])
+
+
+KERNEL_SOURCES = ("sccs_kernels.hpp", "sccs_device.hpp", "sccs_limits.hpp", "sccs_layout.cpp")
+
+
+def kernel_source_sha() -> str:
+    """sha256 (first 16 hex digits) of the sources that decide the sweep
+    kernel's memory traffic: device code, launch constants and the layout."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1208_0945_amd", "csrc")
+    src = "".join(open(os.path.join(csrc, f)).read() for f in KERNEL_SOURCES)
+    return hashlib.sha256(src.encode()).hexdigest()[:16]
 
 
 def cpu_baseline(prob, sweeps):
@@ -185,7 +194,7 @@ def cv_bench(sccs, synth, precision, max_sweeps, tol, n_folds=10, n_grid=16):
                        "max_sweeps_per_link": max_sweeps, "tol": tol}}
 
 
-def full_bench(sccs, synth, steps):
+def full_bench(sccs, synth, steps, refit=True):
     """Full-scale workload, precision form against the FP64 GPU path: 10M
     patients, ~100M eras, J = 4000 Zipf drugs (p_j = 0.482 rank^-1.1),
     Normal prior variance 0.5; `steps` sweeps each; then a seeded 1% patient
@@ -197,6 +206,7 @@ def full_bench(sccs, synth, steps):
     out = {"metric": "full-scale SCCS: sweeps/s, FP64 and mixed, and mixed error vs the FP64 oracle",
            "config": {"workload": "full SCCS: 10M patients, J=4000 Zipf(1.1) p0=0.482, Normal var 0.5",
                       "n_patients": prob.n_patients, "n_eras": prob.n_rows, "nnz": prob.nnz}}
+    c, p = column_stats(prob)
     betas = {}
     for prec, name in ((0, "fp64"), (1, "mixed")):
         t0 = time.perf_counter()
@@ -207,11 +217,19 @@ def full_bench(sccs, synth, steps):
             t0 = time.perf_counter()
             h.sweep(steps)
             wall = time.perf_counter() - t0
-            out[name] = {"sweeps_per_s": steps / wall, "kernel_ms_per_sweep": h.last_kernel_ms() / steps}
-            betas[name] = h.get_beta()[0]
+            ms = h.last_kernel_ms() / steps
+            beta = h.get_beta()[0]
+            # Normal prior: every coordinate moves
+            algo = bytes_per_sweep(c, p, np.ones(len(c), bool), prec)
+            out[name] = {"sweeps_per_s": steps / wall, "kernel_ms_per_sweep": ms,
+                         "algo_bytes_per_sweep": algo, "achieved_GBs": algo / (ms * 1e-3) / 1e9,
+                         "frac_of_8TBs": algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            betas[name] = beta
         print(f"[bench] {name}: {out[name]}", file=sys.stderr, flush=True)
     out["mixed_vs_fp64_gpu_rel_err"] = float(np.max(np.abs(betas["mixed"] - betas["fp64"])) /
                                             np.max(np.abs(betas["fp64"])))
+    if not refit:
+        return out
     sub = synth.subsample_patients(prob, 0.01)
     del prob
     ref = oracle.ccd(sub, oracle.PRIOR_NORMAL, 0.5, 500, oracle.CRIT_REL_LOGPOST, 1e-12)
@@ -242,9 +260,13 @@ def main():
     ap.add_argument("--tune", action="store_true", help="run the autotuner on the mid workload and print its table")
     ap.add_argument("--mixed-only", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--print-sha", action="store_true", help="print the sweep kernel's source hash and exit")
     ap.add_argument("--cv-max-sweeps", type=int, default=50)
     ap.add_argument("--cv-tol", type=float, default=1e-8)
     args = ap.parse_args()
+    if args.print_sha:
+        print(kernel_source_sha())
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(patient sharding is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
@@ -267,7 +289,7 @@ def main():
         print(json.dumps({"tune_best": best, "candidates": table}), flush=True)
         return
     if args.workload == "full":
-        print(json.dumps(full_bench(sccs, synth, args.steps)), flush=True)
+        print(json.dumps(full_bench(sccs, synth, args.steps, refit=not args.no_cpu)), flush=True)
         return
     if args.workload == "cv":
         print(json.dumps(cv_bench(sccs, synth, 1 if args.mixed_only else 0, args.cv_max_sweeps, args.cv_tol)),
