@@ -216,11 +216,27 @@ __device__ __forceinline__ void pair_index(const BatchArgs& A, const WaveMap& wm
 // gathered together from the staged indices, then any further tiles of the
 // pair's range (large columns) are walked one by one.  Partials go to
 // pp[f][slice].
+// Fits (bit f) whose range in this workgroup has more tiles than its first,
+// read by lane f from the owner's staged indices (whole fits per wave only).
+__device__ __forceinline__ uint64_t fits_with_more_tiles(const int (*const* all_ixs)[4], int F, const int* s_done) {
+  const int lane = threadIdx.x & 63;
+  bool more = false;
+  if (lane < F && !s_done[lane]) {
+    const int* ix = all_ixs[lane % kWaves][lane / kWaves];
+    more = ix[0] + 1 < ix[1];
+  }
+  return __ballot(more);
+}
+
 template <typename WT>
 __device__ __forceinline__ void pairs_phase_a(const BatchArgs& A, const WaveMap& wm, int wave, const int* s_done,
                                               const int (*ixs)[4], const uint2 (*ixrp)[64],
-                                              double (*pp)[kWaves][2]) {
-  const int lane = threadIdx.x & 63, F = A.F, slice = wm.slice(wave);
+                                              const int (*const* all_ixs)[4], double (*pp)[kWaves][2]) {
+  const int lane = threadIdx.x & 63, F = A.F;
+  // whole fits per wave: partials of fit f from wave w go to pp[f][w], and
+  // every wave clears its column first; else the slice's own slot
+  const int slice = wm.P == 1 ? wave : wm.slice(wave);
+  if (wm.P == 1 && lane < F) pp[lane][wave][0] = pp[lane][wave][1] = 0.0;
 #pragma unroll 1
   for (int q0 = 0; q0 < kFitsPerWave; q0 += kChunk) {
     if (pair_fit(wm, wave, q0, F) >= F) break;
@@ -267,6 +283,7 @@ __device__ __forceinline__ void pairs_phase_a(const BatchArgs& A, const WaveMap&
       }
     }
   }
+  // a long first tile: its owner
 #pragma unroll 1
   for (int q = 0; q < kFitsPerWave; ++q) {
     const int f = pair_fit(wm, wave, q, F);
@@ -277,7 +294,7 @@ __device__ __forceinline__ void pairs_phase_a(const BatchArgs& A, const WaveMap&
     acc.zero();
     bool any = false;
     if (t0 < t1 && len0 > 64) { tile_a<WT, 1, false>(A.fits[f].k, t0, acc); any = true; }
-    if (t0 + wm.P < t1) {
+    if (wm.P > 1 && t0 + wm.P < t1) {
       tiles_a<WT, 1, false>(A.fits[f].k, t0 + wm.P, t1, wm.P, acc);
       any = true;
     }
@@ -290,6 +307,26 @@ __device__ __forceinline__ void pairs_phase_a(const BatchArgs& A, const WaveMap&
       }
     }
   }
+  if (wm.P > 1) return;
+  // whole fits per wave: the tiles after the first of every fit are spread
+  // over all waves (tile t0 + 1 + ((w - f) mod kWaves) + k kWaves for wave w)
+  uint64_t more = fits_with_more_tiles(all_ixs, F, s_done);
+  while (more) {
+    const int f = __builtin_ctzll(more);
+    more &= more - 1;
+    const int* ix = all_ixs[f % kWaves][f / kWaves];
+    const int start = ix[0] + 1 + ((wave - f) & (kWaves - 1));
+    if (start >= ix[1]) continue;
+    Acc<1> acc;
+    acc.zero();
+    tiles_a<WT, 1, false>(A.fits[f].k, start, ix[1], kWaves, acc);
+    const double Gl = wave_sum(acc.g[0]);
+    const double Hl = wave_sum(acc.h[0]);
+    if (lane == 0) {
+      pp[f][wave][0] += Gl;
+      pp[f][wave][1] += Hl;
+    }
+  }
 }
 
 // Phase B over this wave's pairs with a nonzero step: the first tiles of a
@@ -298,6 +335,7 @@ __device__ __forceinline__ void pairs_phase_a(const BatchArgs& A, const WaveMap&
 template <typename WT>
 __device__ __forceinline__ void pairs_phase_b(const BatchArgs& A, const WaveMap& wm, int wave, const int* s_done,
                                               const int (*ixs)[4], const uint2 (*ixrp)[64],
+                                              const int (*const* all_ixs)[4],
                                               const double (*dd)[3]) {
   const int lane = threadIdx.x & 63, F = A.F;
 #pragma unroll 1
@@ -351,7 +389,18 @@ __device__ __forceinline__ void pairs_phase_b(const BatchArgs& A, const WaveMap&
     const int t0 = ixs[q][0], t1 = ixs[q][1], len0 = ixs[q][3];
     const Coef cf{&dd[f][1], &dd[f][2]};
     if (t0 < t1 && len0 > 64) tile_b<WT>(A.fits[f].k, t0, cf);
-    tiles_b<WT>(A.fits[f].k, t0 + wm.P, t1, wm.P, cf);
+    if (wm.P > 1) tiles_b<WT>(A.fits[f].k, t0 + wm.P, t1, wm.P, cf);
+  }
+  if (wm.P > 1) return;
+  // the tiles after the first of every fit, spread over all waves as in phase A
+  uint64_t more = fits_with_more_tiles(all_ixs, F, s_done);
+  while (more) {
+    const int f = __builtin_ctzll(more);
+    more &= more - 1;
+    if (dd[f][0] == 0.0) continue;
+    const int* ix = all_ixs[f % kWaves][f / kWaves];
+    const int start = ix[0] + 1 + ((wave - f) & (kWaves - 1));
+    if (start < ix[1]) tiles_b<WT>(A.fits[f].k, start, ix[1], kWaves, Coef{&dd[f][1], &dd[f][2]});
   }
 }
 
@@ -497,13 +546,17 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchArgs A) {
     double ytx_next = 0.0;
     for (int j = 0; j < J && ok; ++j) {
       const int cur = j & 1;
-      pairs_phase_a<WT>(A, wm, wave, s_done, s_ixs[cur][wave], s_ixrp[cur][wave], pp);
+      const int(*all_ixs[kWaves])[4];
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) all_ixs[w] = s_ixs[cur][w];
+      pairs_phase_a<WT>(A, wm, wave, s_done, s_ixs[cur][wave], s_ixrp[cur][wave], all_ixs, pp);
       // index data of the next coordinate (static), loaded before the reduction
       if (j + 1 < J) pair_index(A, wm, wave, j + 1, s_done, s_ixs[cur ^ 1][wave], s_ixrp[cur ^ 1][wave]);
       __syncthreads();
       if (tid < F) {
         double g = 0.0, h = 0.0;
-        for (int q = 0; q < wm.P; ++q) { g += pp[tid][q][0]; h += pp[tid][q][1]; }
+        const int nslots = wm.P == 1 ? kWaves : wm.P;
+        for (int q = 0; q < nslots; ++q) { g += pp[tid][q][0]; h += pp[tid][q][1]; }
         part[2 * tid] = g;
         part[2 * tid + 1] = h;
       }
@@ -549,7 +602,7 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchArgs A) {
       }
       __syncthreads();
       if (bad_any) { status = SCCS_ERR_NUMERIC; ok = false; break; }
-      pairs_phase_b<WT>(A, wm, wave, s_done, s_ixs[cur][wave], s_ixrp[cur][wave], dd);
+      pairs_phase_b<WT>(A, wm, wave, s_done, s_ixs[cur][wave], s_ixrp[cur][wave], all_ixs, dd);
       __syncthreads();
     }
     if (!ok) break;

@@ -50,6 +50,21 @@ def test_outcomes_fixed_sweeps_match_oracle(sccs, n_fits, n_workgroups):
             assert abs(res["logpost"] - ref["logpost"]) <= 1e-10 * abs(ref["logpost"])
 
 
+def test_sixty_four_fits_and_limit(sccs):
+    """The maximum batch (64 fits over 8 small problems, 8 fits per wave),
+    every fit against the oracle; a 65th fit is rejected."""
+    probs = outcomes(8, n_cols=24, lo=500, hi=4000, seed=5)
+    specs = [sccs.FitSpec(f % 8, [(sccs.PRIOR_NORMAL, 0.25 * (1 + f // 8))]) for f in range(64)]
+    with sccs.Batch(probs, specs) as b:
+        b.run(sccs.CRIT_FIXED, max_sweeps=3)
+        for f in range(64):
+            ref = oracle.ccd(probs[f % 8], oracle.PRIOR_NORMAL, 0.25 * (1 + f // 8), 3)
+            beta, _ = b.get(f)
+            assert rel_inf(beta, ref["beta"]) <= FP64_TOL, f
+    with pytest.raises(sccs.SccsError):
+        sccs.Batch(probs, specs + [specs[0]])
+
+
 def test_outcomes_to_convergence(sccs):
     probs = outcomes(6, seed=3)
     with sccs.Batch(probs, [sccs.FitSpec(f, [(sccs.PRIOR_NORMAL, 0.5)]) for f in range(6)]) as b:

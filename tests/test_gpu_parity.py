@@ -270,6 +270,37 @@ def test_errors_without_prior_and_bad_args(sccs):
             h.set_beta(np.full(prob.n_cols, np.nan))
 
 
+def test_maximum_columns_and_limits(sccs):
+    """J at the library's maximum (6144 columns: beta, trust and the sweep's
+    start copy of beta fill the LDS), against the oracle; one column more is
+    rejected at creation."""
+    prob = synth.zipf_problem("widest", 3000, 6144, 0.3, seed_path=(12, 1), n_effects=20)
+    ref = oracle.ccd(prob, 1, 0.5, 2)
+    beta, _ = run_gpu(sccs, prob, 1, 0.5, 2)
+    assert rel_inf(beta, ref["beta"]) <= FP64_TOL
+    wider = synth.zipf_problem("too_wide", 500, 6145, 0.3, seed_path=(12, 2), n_effects=5)
+    with pytest.raises(sccs.SccsError) as e:
+        sccs.Handle(wider)
+    assert e.value.status == sccs.ERR_INVALID_ARG
+
+
+def test_no_nonzeros_and_single_patient(sccs):
+    """Degenerate inputs: a problem whose columns are all empty (every step
+    is zero and beta stays 0, Normal or Laplace), and a single patient."""
+    base = synth.tiny(n_patients=50, n_cols=5)
+    empty = synth.Problem("empty", base.n_patients, base.patient_ptr, base.offset, base.count, 5,
+                          np.zeros(6, np.int64), np.zeros(0, np.int32), np.zeros(5))
+    for kind in (1, 2):
+        beta, _ = run_gpu(sccs, empty, kind, 1.0, 3)
+        assert np.all(beta == 0.0)
+    one = synth.Problem("one", 1, np.array([0, 4], np.int64), np.array([10, 20, 30, 40], np.int32),
+                        np.array([1, 0, 2, 1], np.int32), 2, np.array([0, 2, 3], np.int64),
+                        np.array([0, 2, 1], np.int32), np.zeros(2))
+    ref = oracle.ccd(one, 1, 1.0, 5)
+    beta, _ = run_gpu(sccs, one, 1, 1.0, 5)
+    assert rel_inf(beta, ref["beta"]) <= FP64_TOL
+
+
 def test_full_size_mid_parity(sccs):
     """Full mid workload (2M patients, ~20M eras, J = 2000, Laplace lambda = 1)
     in the benchmark's launch configuration: the first 3 sweeps against the
