@@ -350,6 +350,15 @@ __device__ __forceinline__ void accum_patient(double num, double2 pv, double& Gl
   Hl += tg * fmax(1.0 - r, 0.0);
 }
 
+// Index load through the vector memory path.  A wave-uniform address would
+// otherwise become a scalar load, and scalar loads share their completion
+// counter with LDS operations: every later LDS access of the wave would
+// wait for it.  A relaxed workgroup-scope atomic load is an ordinary cached
+// vector load.
+__device__ __forceinline__ int ld_idx(const int32_t* p) {
+  return __hip_atomic_load(const_cast<int32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // Column of a group (bits above the patient index of rp.y) and the patient.
 __device__ __forceinline__ uint32_t col_of(uint32_t key) { return key >> kGroupShift; }
 __device__ __forceinline__ uint32_t pid_of(uint32_t key) { return key & kPidMask; }
@@ -391,7 +400,7 @@ template <typename WT, int NC, bool kMark>
 __device__ __forceinline__ void tile_a(const KArgs& a, int t, Acc<NC>& acc, unsigned* bits = nullptr, int p0 = 0) {
   const int lane = threadIdx.x & 63;
   const WT* __restrict__ w = (const WT*)a.w;
-  const int e0 = a.tile_start[t], e1 = a.tile_start[t + 1];
+  const int e0 = ld_idx(a.tile_start + t), e1 = ld_idx(a.tile_start + t + 1);
   const int len = e1 - e0;
   if (len <= 64) {
     bool act = lane < len;
@@ -424,7 +433,7 @@ template <typename WT>
 __device__ __forceinline__ void tile_b(const KArgs& a, int t, Coef cf) {
   const int lane = threadIdx.x & 63;
   WT* __restrict__ w = (WT*)a.w;
-  const int e0 = a.tile_start[t], e1 = a.tile_start[t + 1];
+  const int e0 = ld_idx(a.tile_start + t), e1 = ld_idx(a.tile_start + t + 1);
   const int len = e1 - e0;
   if (len <= 64) {
     bool act = lane < len;
@@ -510,8 +519,8 @@ struct Cache {
 
 __device__ __forceinline__ void pf_range(const KArgs& a, int g, int& t0, int& t1) {
   const size_t base = (size_t)g * (a.G + 1) + blockIdx.x;
-  t0 = a.own[base];
-  t1 = a.own[base + 1];
+  t0 = ld_idx(a.own + base);
+  t1 = ld_idx(a.own + base + 1);
 }
 
 __device__ __forceinline__ void pf_tile(const KArgs& a, int t0, int t1, Pf& p) {
@@ -522,8 +531,8 @@ __device__ __forceinline__ void pf_tile(const KArgs& a, int t0, int t1, Pf& p) {
   p.len = 0;
   p.rp = make_uint2(0u, 0xffffffffu);
   if (p.t < t1) {
-    p.e0 = a.tile_start[p.t];
-    p.len = a.tile_start[p.t + 1] - p.e0;
+    p.e0 = ld_idx(a.tile_start + p.t);
+    p.len = ld_idx(a.tile_start + p.t + 1) - p.e0;
     if (p.len <= 64 && lane < p.len) p.rp = a.rp[p.e0 + lane];
   }
 }
@@ -753,7 +762,7 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
       const bool has_next = g + 1 < NG;
       int nt0 = 0, nt1 = 0;
       if (g + 2 < NG) pf_range(a, g + 2, nt0, nt1);
-      const int gc3 = g + 3 <= NG ? a.gcol[g + 3] : gc2;
+      const int gc3 = g + 3 <= NG ? ld_idx(a.gcol + g + 3) : gc2;
       const int j0n = gc1;
       const int mn = has_next ? gc2 - gc1 : 0;
       const double ytx_next = (wave == kPoller && lane < mn) ? a.ytx[j0n + lane] : 0.0;
