@@ -140,25 +140,144 @@ __device__ bool batch_allreduce(uint64_t* s1, uint64_t* s2, uint32_t seq, int G,
   return *flag != 0;
 }
 
-// Wave -> (fit, slice) assignment.  With F >= kWaves fits each wave takes
-// fits w, w + kWaves, ... whole; with fewer fits, P = kWaves / F waves share
-// a fit and take every P-th of its tiles.
+// Device-wide sum of the W = 2F words of every workgroup by ONE wave (the
+// poller) per workgroup; same tagged two-level scheme and slots as
+// batch_allreduce, with level 1 cut into slices of kSliceWords words so that
+// no lane keeps more than 8 polls in flight.  The leader of (member group g,
+// slice s) is workgroup (g + ng s) mod G; it sums its group's 32 members
+// over the slice (each lane four of them, then the four lanes of a word in
+// fixed order) and publishes the slice of the group total to every replica.
+// Every workgroup then polls the ng group totals of its replica and sums
+// them in group order into out[] (LDS).  part[w] is in lane w % 64 of the
+// wave at index w / 64.  Returns false (whole wave) on timeout/abort.
+constexpr int kSliceWords = 16;
+constexpr int kL2Per = kGroups * kBatchSlotWords / 64;   // level-2 polls per lane (16)
+
+// Poll words base[off[q]] (q < n for this lane, n <= NQ) until their tag
+// matches; decoded word q lands in dst[q * 64 + lane] (LDS).  All loads of a
+// round are issued before any is inspected.  Returns false (whole wave) on
+// timeout/abort.
+template <int NQ>
+__device__ __forceinline__ bool poll_words(const uint64_t* base, const int* off, int n, uint32_t tag, double* dst,
+                                           Ctrl* ctrl) {
+  const int lane = threadIdx.x & 63;
+  uint32_t need = (1u << n) - 1u;
+  long long spins = 0;
+  bool ok = true;
+  while (true) {
+    uint64_t x[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) x[q] = (need & (1u << q)) ? load_agent(base + off[q]) : 0ull;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      if ((need & (1u << q)) && (uint32_t)(x[q] >> 63) == tag) {
+        dst[q * 64 + lane] = tag_decode(x[q]);
+        need &= ~(1u << q);
+      }
+    if (__ballot(need != 0) == 0ull) break;
+    if (++spins > kSpinLimit) {
+      if (lane == 0) {
+        __hip_atomic_store(&ctrl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ctrl->status, (int)SCCS_ERR_SYNC, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      ok = false;
+      break;
+    }
+    if ((spins & 255) == 0 && load_agent_i(&ctrl->abort)) { ok = false; break; }
+    if (kPollSleep) __builtin_amdgcn_s_sleep(kPollSleep);
+  }
+  return __ballot(!ok) == 0ull;
+}
+
+// stage: LDS of at least 2 * kL2Per * 64 doubles.
+__device__ bool batch_reduce_poller(uint64_t* s1, uint64_t* s2, uint32_t seq, int G, int W, Ctrl* ctrl,
+                                    const double* part0, const double* part1, double* out, double* stage) {
+  const int lane = threadIdx.x & 63, b = blockIdx.x;
+  const uint32_t par = seq & 1u, tag = (seq >> 1) & 1u;
+  const int ng = G < kGroups ? G : kGroups;
+  const int S = (W + kSliceWords - 1) / kSliceWords;
+  uint64_t* L1 = s1 + (size_t)par * kMaxWorkgroups * kBatchSlotWords;
+  uint64_t* L2 = s2 + (size_t)par * kReplicas * kGroups * kBatchSlotWords;
+  double* st1 = stage;                   // [8][64] level-1 values
+  double* st2 = stage + kL2Per * 64;     // [kL2Per][64] level-2 values
+  if (lane < W) store_agent(L1 + (size_t)b * kBatchSlotWords + lane, tag_encode(*part0, tag));
+  if (lane + 64 < W) store_agent(L1 + (size_t)b * kBatchSlotWords + lane + 64, tag_encode(*part1, tag));
+  constexpr int NQ = 8;
+  int off[NQ];
+  // level 1: the (group, slice) pairs this workgroup leads
+  for (int pidx = b; pidx < ng * S; pidx += G) {
+    const int g = pidx % ng, sl = pidx / ng;
+    const int members = (G - g + ng - 1) / ng;
+    const int w = sl * kSliceWords + (lane & 15);
+    const int k0 = lane >> 4;
+    int n = 0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int k = k0 + 4 * q;
+      off[q] = (g + (k < members ? k : 0) * ng) * kBatchSlotWords + (w < W ? w : 0);
+      if (w < W && k < members) n = q + 1;
+    }
+    if (!poll_words<NQ>(L1, off, n, tag, st1, ctrl)) return false;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    double acc = 0.0;
+    for (int q = 0; q < n; ++q) acc += st1[q * 64 + lane];
+    acc += __shfl_xor(acc, 16, 64);
+    acc += __shfl_xor(acc, 32, 64);
+    if (lane < 16 && w < W)
+      for (int r = 0; r < kReplicas; ++r)
+        store_agent(L2 + ((size_t)r * kGroups + g) * kBatchSlotWords + w, tag_encode(acc, tag));
+  }
+  // level 2: the ng group totals of this workgroup's replica
+  const int r = b % kReplicas;
+  const int items = ng * W;
+  const uint64_t* L2r = L2 + (size_t)r * kGroups * kBatchSlotWords;
+  for (int q0 = 0; q0 < items; q0 += NQ * 64) {   // passes of NQ polls per lane
+    int n = 0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int i = q0 + lane + 64 * q;
+      off[q] = i < items ? (i / W) * kBatchSlotWords + i % W : 0;
+      if (i < items) n = q + 1;
+    }
+    if (!poll_words<NQ>(L2r, off, n, tag, st2 + q0, ctrl)) return false;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  // lane w sums word w (and w + 64) over the groups, in group order
+  for (int w = lane; w < W; w += 64) {
+    double t = 0.0;
+    for (int g = 0; g < ng; ++g) t += st2[g * W + w];   // item g * W + w sits at st2[(i % 64) + 64 (i / 64)] = st2[i]
+    out[w] = t;
+  }
+  return true;
+}
+
+// Waves 0..kBW-1 work on tiles; the last wave runs the device-wide reduction
+// and the Newton steps, so that the workers can load the next coordinate's
+// indices while it waits.
+constexpr int kBW = kWaves - 1;
+constexpr int kBPoller = kWaves - 1;
+
+// Worker wave -> (fit, slice) assignment.  With F >= kBW fits each worker
+// takes fits w, w + kBW, ... whole; with fewer fits, P = kBW / F workers
+// share a fit and take every P-th of its tiles.
 struct WaveMap {
   int P;
-  __device__ WaveMap(int F) : P(F >= kWaves ? 1 : kWaves / F) {}
-  __device__ int first_fit(int w, int F) const { return P == 1 ? w : (w < F * P ? w / P : F); }
-  __device__ int next_fit(int f) const { return P == 1 ? f + kWaves : 1 << 30; }
+  __device__ WaveMap(int F) : P(F >= kBW ? 1 : kBW / F) {}
   __device__ int slice(int w) const { return P == 1 ? 0 : w % P; }
 };
 
-constexpr int kFitsPerWave = kMaxFits / kWaves;
-constexpr int kChunk = 4;   // pairs whose loads a wave keeps in flight together
+constexpr int kFitsPerWave = (kMaxFits + kBW - 1) / kBW;   // 10
+constexpr int kChunk = 5;   // pairs whose loads a wave keeps in flight together
+static_assert(kFitsPerWave % kChunk == 0, "chunks tile the pairs of a wave");
 
-// Pair q of a wave: the fit it works on (F if none).  With P == 1 a wave
-// takes fits wave, wave + kWaves, ...; with P > 1 only pair 0 is used.
+// Offset of worker w among the workers that share fit f's extra tiles.
+__device__ __forceinline__ int rot(int w, int f) { return ((w - f) % kBW + kBW) % kBW; }
+
+// Pair q of a worker wave: the fit it works on (F if none).  With P == 1 a
+// worker takes fits wave, wave + kBW, ...; with P > 1 only pair 0 is used.
 // Pair fits increase with q, so the first pair with f >= F ends the list.
 __device__ __forceinline__ int pair_fit(const WaveMap& wm, int wave, int q, int F) {
-  if (wm.P == 1) return wave + q * kWaves;
+  if (wm.P == 1) return wave + q * kBW;
   return (q == 0 && wave < F * wm.P) ? wave / wm.P : F;
 }
 
@@ -222,7 +341,7 @@ __device__ __forceinline__ uint64_t fits_with_more_tiles(const int (*const* all_
   const int lane = threadIdx.x & 63;
   bool more = false;
   if (lane < F && !s_done[lane]) {
-    const int* ix = all_ixs[lane % kWaves][lane / kWaves];
+    const int* ix = all_ixs[lane % kBW][lane / kBW];
     more = ix[0] + 1 < ix[1];
   }
   return __ballot(more);
@@ -231,7 +350,7 @@ __device__ __forceinline__ uint64_t fits_with_more_tiles(const int (*const* all_
 template <typename WT>
 __device__ __forceinline__ void pairs_phase_a(const BatchArgs& A, const WaveMap& wm, int wave, const int* s_done,
                                               const int (*ixs)[4], const uint2 (*ixrp)[64],
-                                              const int (*const* all_ixs)[4], double (*pp)[kWaves][2]) {
+                                              const int (*const* all_ixs)[4], double (*pp)[kBW][2]) {
   const int lane = threadIdx.x & 63, F = A.F;
   // whole fits per wave: partials of fit f from wave w go to pp[f][w], and
   // every wave clears its column first; else the slice's own slot
@@ -309,17 +428,17 @@ __device__ __forceinline__ void pairs_phase_a(const BatchArgs& A, const WaveMap&
   }
   if (wm.P > 1) return;
   // whole fits per wave: the tiles after the first of every fit are spread
-  // over all waves (tile t0 + 1 + ((w - f) mod kWaves) + k kWaves for wave w)
+  // over all workers (tile t0 + 1 + ((w - f) mod kBW) + k kBW for worker w)
   uint64_t more = fits_with_more_tiles(all_ixs, F, s_done);
   while (more) {
     const int f = __builtin_ctzll(more);
     more &= more - 1;
-    const int* ix = all_ixs[f % kWaves][f / kWaves];
-    const int start = ix[0] + 1 + ((wave - f) & (kWaves - 1));
+    const int* ix = all_ixs[f % kBW][f / kBW];
+    const int start = ix[0] + 1 + rot(wave, f);
     if (start >= ix[1]) continue;
     Acc<1> acc;
     acc.zero();
-    tiles_a<WT, 1, false>(A.fits[f].k, start, ix[1], kWaves, acc);
+    tiles_a<WT, 1, false>(A.fits[f].k, start, ix[1], kBW, acc);
     const double Gl = wave_sum(acc.g[0]);
     const double Hl = wave_sum(acc.h[0]);
     if (lane == 0) {
@@ -398,24 +517,24 @@ __device__ __forceinline__ void pairs_phase_b(const BatchArgs& A, const WaveMap&
     const int f = __builtin_ctzll(more);
     more &= more - 1;
     if (dd[f][0] == 0.0) continue;
-    const int* ix = all_ixs[f % kWaves][f / kWaves];
-    const int start = ix[0] + 1 + ((wave - f) & (kWaves - 1));
-    if (start < ix[1]) tiles_b<WT>(A.fits[f].k, start, ix[1], kWaves, Coef{&dd[f][1], &dd[f][2]});
+    const int* ix = all_ixs[f % kBW][f / kBW];
+    const int start = ix[0] + 1 + rot(wave, f);
+    if (start < ix[1]) tiles_b<WT>(A.fits[f].k, start, ix[1], kBW, Coef{&dd[f][1], &dd[f][2]});
   }
 }
 
 template <typename WT>
 __global__ void __launch_bounds__(kBlock) k_batch(BatchArgs A) {
   __shared__ double stage[32 * kBatchSlotWords];
-  __shared__ double pp[kMaxFits][kWaves][2];      // per (fit, slice) partials
+  __shared__ double pp[kMaxFits][kBW][2];         // per (fit, worker or slice) partials
   __shared__ double part[kBatchSlotWords], tot[kBatchSlotWords];
   __shared__ double dd[kMaxFits][3];              // d, e^d, e^d - 1
   __shared__ double lp_prev[kMaxFits], s_var[kMaxFits], s_lam[kMaxFits], s_ivar[kMaxFits];
   __shared__ int s_link[kMaxFits], s_sw[kMaxFits], s_kind[kMaxFits], s_done[kMaxFits];
   __shared__ int flag, bad_any, n_active, since_refresh;
   __shared__ double red[kWaves][4];
-  __shared__ int s_ixs[2][kWaves][kFitsPerWave][4];        // indices of coordinates j and j + 1
-  __shared__ uint2 s_ixrp[2][kWaves][kFitsPerWave][64];
+  __shared__ int s_ixs[2][kBW][kFitsPerWave][4];        // indices of coordinates j and j + 1
+  __shared__ uint2 s_ixrp[2][kBW][kFitsPerWave][64];
 
   const int tid = threadIdx.x, b = blockIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -541,68 +660,79 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchArgs A) {
     }
     __syncthreads();
     if (n_active == 0) break;
-    pair_index(A, wm, wave, 0, s_done, s_ixs[0][wave], s_ixrp[0][wave]);
-    double2 bt_next = make_double2(0.0, 0.0);   // thread f < F: fit f's (beta_j, trust_j) for the next step
+    const bool worker = wave < kBW;
+    if (worker) pair_index(A, wm, wave, 0, s_done, s_ixs[0][wave], s_ixrp[0][wave]);
+    __syncthreads();   // every worker's staged indices, read across waves in phase A
+    // poller lane f < F: fit f's (beta_j, trust_j) and Y'X_j for the next step
+    double2 bt_next = make_double2(0.0, 0.0);
     double ytx_next = 0.0;
     for (int j = 0; j < J && ok; ++j) {
       const int cur = j & 1;
-      const int(*all_ixs[kWaves])[4];
+      const int(*all_ixs[kBW])[4];
 #pragma unroll
-      for (int w = 0; w < kWaves; ++w) all_ixs[w] = s_ixs[cur][w];
-      pairs_phase_a<WT>(A, wm, wave, s_done, s_ixs[cur][wave], s_ixrp[cur][wave], all_ixs, pp);
-      // index data of the next coordinate (static), loaded before the reduction
-      if (j + 1 < J) pair_index(A, wm, wave, j + 1, s_done, s_ixs[cur ^ 1][wave], s_ixrp[cur ^ 1][wave]);
+      for (int w = 0; w < kBW; ++w) all_ixs[w] = s_ixs[cur][w];
+      if (worker) pairs_phase_a<WT>(A, wm, wave, s_done, s_ixs[cur][wave], s_ixrp[cur][wave], all_ixs, pp);
       __syncthreads();
-      if (tid < F) {
-        double g = 0.0, h = 0.0;
-        const int nslots = wm.P == 1 ? kWaves : wm.P;
-        for (int q = 0; q < nslots; ++q) { g += pp[tid][q][0]; h += pp[tid][q][1]; }
-        part[2 * tid] = g;
-        part[2 * tid + 1] = h;
-      }
-      __syncthreads();
-      if (!batch_allreduce(A.s1, A.s2, seq++, G, 2 * F, A.ctrl, part, tot, stage, &flag)) { ok = false; break; }
-      // one Newton / trust-region step per fit (lanes of wave 0); (beta_j,
-      // trust_j) and Y'X_j come from the previous coordinate's prefetch
-      if (tid < F) {
-        const int f = tid;
-        double d = 0.0;
-        if (!s_done[f]) {
-          const BatchFit& bf = A.fits[f];
-          double2* bt = bf.bt + (size_t)b * J + j;
-          if (j == 0) {
-            bt_next = *bt;
-            ytx_next = bf.k.ytx[0];
-          }
-          const double2 v = bt_next;
-          double g = ytx_next - tot[2 * f], h = -tot[2 * f + 1];
-          if (j + 1 < J) {
-            // the next coordinate's copies: nothing writes them before its step
-            bt_next = bt[1];
-            ytx_next = bf.k.ytx[j + 1];
-          }
-          if (isfinite(g) && isfinite(h)) {
-            double dv = prior_step(s_kind[f], s_ivar[f], s_lam[f], v.x, g, h);
-            d = fmin(fmax(dv, -v.y), v.y);
-            double nb = v.x + d;
-            if (isfinite(nb)) {
-              *bt = make_double2(nb, fmax(2.0 * fabs(d), 0.5 * v.y));
+      if (worker) {
+        // index data of the next coordinate (static), in the shadow of the reduction
+        if (j + 1 < J) pair_index(A, wm, wave, j + 1, s_done, s_ixs[cur ^ 1][wave], s_ixrp[cur ^ 1][wave]);
+      } else {
+        // the poller: each fit's two words summed over its partial slots in
+        // fixed order, the device-wide reduction, then one Newton /
+        // trust-region step per fit (lane f); (beta_j, trust_j) and Y'X_j
+        // come from the previous coordinate's prefetch
+        const int lane = tid & 63;
+        const int nslots = wm.P == 1 ? kBW : wm.P;
+        double p0 = 0.0, p1 = 0.0;
+        if (lane < 2 * F)
+          for (int q = 0; q < nslots; ++q) p0 += pp[lane >> 1][q][lane & 1];
+        if (lane + 64 < 2 * F)
+          for (int q = 0; q < nslots; ++q) p1 += pp[(lane + 64) >> 1][q][lane & 1];
+        const bool okr = batch_reduce_poller(A.s1, A.s2, seq, G, 2 * F, A.ctrl, &p0, &p1, tot, stage);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        if (lane < F) {
+          const int f = lane;
+          double d = 0.0;
+          if (!s_done[f] && okr) {
+            const BatchFit& bf = A.fits[f];
+            double2* bt = bf.bt + (size_t)b * J + j;
+            if (j == 0) {
+              bt_next = *bt;
+              ytx_next = bf.k.ytx[0];
+            }
+            const double2 v = bt_next;
+            double g = ytx_next - tot[2 * f], h = -tot[2 * f + 1];
+            if (j + 1 < J) {
+              // the next coordinate's copies: nothing writes them before its step
+              bt_next = bt[1];
+              ytx_next = bf.k.ytx[j + 1];
+            }
+            if (isfinite(g) && isfinite(h)) {
+              double dv = prior_step(s_kind[f], s_ivar[f], s_lam[f], v.x, g, h);
+              d = fmin(fmax(dv, -v.y), v.y);
+              double nb = v.x + d;
+              if (isfinite(nb)) {
+                *bt = make_double2(nb, fmax(2.0 * fabs(d), 0.5 * v.y));
+              } else {
+                d = 0.0;
+                atomicOr(&bad_any, 1);
+              }
             } else {
-              d = 0.0;
               atomicOr(&bad_any, 1);
             }
-          } else {
-            atomicOr(&bad_any, 1);
           }
+          const double em1 = expm1(d);
+          dd[f][0] = d;
+          dd[f][1] = 1.0 + em1;
+          dd[f][2] = em1;
         }
-        const double em1 = expm1(d);
-        dd[f][0] = d;
-        dd[f][1] = 1.0 + em1;
-        dd[f][2] = em1;
+        if (lane == 0) flag = okr ? 1 : 0;
       }
+      ++seq;
       __syncthreads();
+      if (!flag) { ok = false; break; }
       if (bad_any) { status = SCCS_ERR_NUMERIC; ok = false; break; }
-      pairs_phase_b<WT>(A, wm, wave, s_done, s_ixs[cur][wave], s_ixrp[cur][wave], all_ixs, dd);
+      if (worker) pairs_phase_b<WT>(A, wm, wave, s_done, s_ixs[cur][wave], s_ixrp[cur][wave], all_ixs, dd);
       __syncthreads();
     }
     if (!ok) break;
