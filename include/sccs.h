@@ -107,6 +107,12 @@ typedef struct sccs_options {
                               those of visiting them one by one, up to summation order);
                               0 = 4, else 1..4 (1 = one column per reduction).  The batched
                               form always visits one column at a time. */
+  int32_t merge_passes;    /* single fit: 1 = let the next group share the current group's
+                              reduction (up to max_group columns) when every column that links
+                              them through a shared patient took a zero step in its previous
+                              visit; the prediction is checked after the step and, where it
+                              fails, the second group is visited again on its own, so g_j, h_j
+                              and beta are those of the plain cyclic order; 0 = off.  Default 1. */
   void* stream;            /* hipStream_t */
 } sccs_options;
 
@@ -125,7 +131,7 @@ typedef struct sccs_fit_result {
 } sccs_fit_result;
 
 /* Options with defaults: FP64, one workgroup per CU, default refresh, 64-nonzero tiles,
- * groups of up to 4 columns, NULL stream. */
+ * groups of up to 4 columns, merged passes on, NULL stream. */
 void sccs_default_options(sccs_options* opts);
 
 /* Device bytes sccs_create needs for this problem and these options.
@@ -179,6 +185,13 @@ sccs_status sccs_objective(sccs_handle* h, double* loglik, double* logpost);
  * milliseconds (HIP events on the handle's stream around the persistent
  * kernel alone).  Synchronises. */
 sccs_status sccs_last_kernel_ms(sccs_handle* h, double* ms);
+
+/* Schedule statistics of the most recent sccs_sweep / sccs_fit launch:
+ * passes = device-wide coordinate reductions run (one per column group, or
+ * per two groups merged as options.merge_passes describes), rejects =
+ * merged passes whose second group had to be visited again.  Valid after
+ * the call has returned; ERR_STATE before any sweep. */
+sccs_status sccs_pass_stats(sccs_handle* h, int32_t* passes, int32_t* rejects);
 
 /* Autotuner: times candidate schedules -- workgroup counts (all compute
  * units, 3/4, 1/2, 1/4 of them) x tile sizes (16, 32, 64 nonzeros) -- on

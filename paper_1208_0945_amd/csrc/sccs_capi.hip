@@ -32,6 +32,7 @@ struct sccs_handle {
   int32_t refresh_period = 0;
   size_t lds_bytes = 0;
   int32_t nbits = 0;
+  int32_t mv_words = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool timed = false;
   KArgs args{};
@@ -63,6 +64,8 @@ struct Carver {
 struct Plan {
   uint2* rp;
   int32_t *tile_start, *own, *gcol, *pb, *pptr, *era_ptr, *era_col, *offset, *count, *weight;
+  uint32_t* gdesc;
+  uint64_t* moved;
   int64_t* col_ptr;
   void* w;
   double2* pat;
@@ -77,6 +80,8 @@ size_t carve(void* base, const Layout& L, int prec, bool has_weight, Plan& P) {
   P.tile_start = c.take<int32_t>((size_t)L.tiles_cap);
   P.own = c.take<int32_t>((size_t)L.J * (L.G + 1));
   P.gcol = c.take<int32_t>((size_t)L.J + 1);
+  P.gdesc = c.take<uint32_t>((size_t)L.J);
+  P.moved = c.take<uint64_t>(((size_t)L.J + 63) / 64);
   P.pb = c.take<int32_t>((size_t)L.G + 1);
   P.pptr = c.take<int32_t>((size_t)L.N + 1);
   P.era_ptr = c.take<int32_t>((size_t)L.K + 1);
@@ -119,6 +124,10 @@ sccs_status check_options(const sccs_options* o, std::string& err) {
   }
   if (o->max_group < 0 || o->max_group > kMaxGroup) {
     err = "options.max_group must be 0 (4) or in [1, 4]";
+    return SCCS_ERR_INVALID_ARG;
+  }
+  if (o->merge_passes != 0 && o->merge_passes != 1) {
+    err = "options.merge_passes must be 0 or 1";
     return SCCS_ERR_INVALID_ARG;
   }
   return SCCS_OK;
@@ -220,6 +229,16 @@ sccs_status refresh_all(sccs_handle* h) {
   return SCCS_OK;
 }
 
+// Forget which columns took zero steps (a new beta makes the prediction of
+// merged passes stale; it is only a prediction either way, and a new prior
+// keeps it: the steps of a warm-started chain change gradually).
+sccs_status reset_moved(sccs_handle* h) {
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(256), 0, h->stream, (uint64_t*)h->args.moved,
+                     (size_t)h->mv_words / 2, ~0ull);
+  HIPCHK(h, hipGetLastError());
+  return SCCS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -232,6 +251,7 @@ void sccs_default_options(sccs_options* o) {
   o->refresh_period = -1;
   o->tile_nnz = 0;
   o->max_group = 0;
+  o->merge_passes = 1;
   o->stream = nullptr;
 }
 
@@ -307,7 +327,9 @@ sccs_status sccs_create(const sccs_problem* prob, const sccs_options* opts_in, v
     for (int32_t b = 0; b < G; ++b) maxrange = std::max(maxrange, L.pb[b + 1] - L.pb[b]);
     h->nbits = (maxrange + 31) / 32;
   }
-  h->lds_bytes = (size_t)3 * L.J * sizeof(double) + (size_t)2 * h->nbits * sizeof(uint32_t);
+  h->mv_words = 2 * ((L.J + 63) / 64);
+  h->lds_bytes = (size_t)3 * L.J * sizeof(double) + (size_t)2 * h->nbits * sizeof(uint32_t) +
+                 (size_t)h->mv_words * sizeof(uint32_t);
   if (h->lds_bytes > 150 * 1024) {
     delete h;
     g_create_error = "too many columns or patients per workgroup for the LDS budget";
@@ -353,6 +375,7 @@ sccs_status sccs_create(const sccs_problem* prob, const sccs_options* opts_in, v
   };
   bool ok = cp(P.rp, L.rp.data(), L.rp.size() * 4) && cp(P.tile_start, L.tile_start.data(), L.tile_start.size() * 4) &&
             cp(P.own, L.own.data(), L.own.size() * 4) && cp(P.gcol, L.gcol.data(), L.gcol.size() * 4) &&
+            cp(P.gdesc, L.gdesc.data(), L.gdesc.size() * 4) &&
             cp(P.pb, L.pb.data(), L.pb.size() * 4) && cp(P.ytx, ytx.data(), ytx.size() * 8) &&
             cp(P.pptr, L.pptr.data(), L.pptr.size() * 4) && cp(P.era_ptr, L.era_ptr.data(), L.era_ptr.size() * 4) &&
             cp(P.era_col, L.era_col.data(), L.era_col.size() * 4) &&
@@ -372,6 +395,8 @@ sccs_status sccs_create(const sccs_problem* prob, const sccs_options* opts_in, v
     hipLaunchKernelGGL(k_fill_u64, dim3(16), dim3(256), 0, s, P.oslots, n1, kSign);
     hipLaunchKernelGGL(k_fill_u64, dim3(4), dim3(256), 0, s, P.oslots2, n2, kSign);
   }
+  // no column has a known zero step yet: no pass is merged in the first sweep
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(256), 0, s, P.moved, ((size_t)L.J + 63) / 64, ~0ull);
   int gp = (L.N + 255) / 256;
   if (gp > 4096) gp = 4096;
   hipLaunchKernelGGL(k_setup_patients, dim3(gp), dim3(256), 0, s, P.pptr, P.count, P.weight, P.pat, L.N);
@@ -384,6 +409,7 @@ sccs_status sccs_create(const sccs_problem* prob, const sccs_options* opts_in, v
   a.ytx = P.ytx; a.beta = P.beta; a.trust = P.trust; a.slots = P.slots; a.slots2 = P.slots2;
   a.oslots = P.oslots; a.oslots2 = P.oslots2;
   a.ctrl = P.ctrl; a.N = L.N; a.J = L.J; a.G = G; a.nbits = h->nbits;
+  a.gdesc = P.gdesc; a.moved = (uint32_t*)P.moved; a.mv_words = h->mv_words; a.merge = opts.merge_passes;
   h->d_col_ptr = P.col_ptr; h->d_count = P.count; h->d_weight = P.weight;
   h->gcol = L.gcol;
   if (refresh_all(h) != SCCS_OK) return bail(h->err, SCCS_ERR_HIP);
@@ -434,6 +460,8 @@ sccs_status sccs_set_beta(sccs_handle* h, const double* beta, const double* trus
   HIPCHK(h, hipMemcpyAsync(h->args.beta, beta, (size_t)h->J * 8, hipMemcpyHostToDevice, h->stream));
   HIPCHK(h, hipMemcpyAsync(h->args.trust, trust, (size_t)h->J * 8, hipMemcpyHostToDevice, h->stream));
   if (refresh_all(h) != SCCS_OK) return SCCS_ERR_HIP;
+  st = reset_moved(h);
+  if (st) return st;
   HIPCHK(h, hipStreamSynchronize(h->stream));
   return SCCS_OK;
 }
@@ -511,6 +539,15 @@ sccs_status sccs_objective(sccs_handle* h, double* loglik, double* logpost) {
   if (st) return st;
   *loglik = h->h_ctrl->loglik;
   *logpost = h->h_ctrl->logpost;
+  return SCCS_OK;
+}
+
+sccs_status sccs_pass_stats(sccs_handle* h, int32_t* passes, int32_t* rejects) {
+  if (!h || !passes || !rejects) return SCCS_ERR_INVALID_ARG;
+  if (!h->timed) { h->err = "no kernel launched yet"; return SCCS_ERR_STATE; }
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  *passes = h->h_ctrl->passes;
+  *rejects = h->h_ctrl->rejects;
   return SCCS_OK;
 }
 

@@ -43,6 +43,8 @@ struct Ctrl {
   double loglik, logpost;
   double g, h;         // diagnostic output
   uint32_t gseq[kMaxGroup];  // single fit: sequence number of each reduction class
+  int32_t passes;      // single fit, last launch: device-wide reductions of coordinates
+  int32_t rejects;     //   merged passes whose second group was visited again
 };
 
 struct KArgs {
@@ -50,6 +52,8 @@ struct KArgs {
   const int32_t* tile_start;  // [T+1]
   const int32_t* own;         // [n_groups*(G+1)]
   const int32_t* gcol;        // [n_groups+1] first column of each group
+  const uint32_t* gdesc;      // [n_groups] pass descriptors (sccs_layout.hpp)
+  uint32_t* moved;            // [mv_words] bit j: column j's last step was nonzero
   const int32_t* pb;          // [G+1]
   const int32_t* pptr;        // [N+1]
   const int32_t* era_ptr;     // [K+1]
@@ -78,6 +82,8 @@ struct KArgs {
   int32_t diag_j;
   int32_t diag_g, diag_c;     // group of diag_j and its column within the group
   int32_t nbits;              // words of each per-workgroup patient bitmap (LDS)
+  int32_t mv_words;           // 32-bit words of the moved-column bitmap (LDS copy of moved)
+  int32_t merge;              // merge the next group into a pass when predicted independent
 };
 
 enum { kModeSweep = 0, kModeGradHess = 1, kModeObjective = 2 };

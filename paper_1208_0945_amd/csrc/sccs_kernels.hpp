@@ -358,6 +358,9 @@ __device__ __forceinline__ void accum_patient(double num, double2 pv, double& Gl
 __device__ __forceinline__ int ld_idx(const int32_t* p) {
   return __hip_atomic_load(const_cast<int32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
+__device__ __forceinline__ uint32_t ld_idx(const uint32_t* p) {
+  return __hip_atomic_load(const_cast<uint32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
 
 // Column of a group (bits above the patient index of rp.y) and the patient.
 __device__ __forceinline__ uint32_t col_of(uint32_t key) { return key >> kGroupShift; }
@@ -397,7 +400,8 @@ struct Coef {
 // segment, accumulate the segment's terms of G and H; optionally mark the
 // tile's patients in the workgroup's bitmap.
 template <typename WT, int NC, bool kMark>
-__device__ __forceinline__ void tile_a(const KArgs& a, int t, Acc<NC>& acc, unsigned* bits = nullptr, int p0 = 0) {
+__device__ __forceinline__ void tile_a(const KArgs& a, int t, Acc<NC>& acc, unsigned* bits = nullptr, int p0 = 0,
+                                       uint32_t coff = 0) {
   const int lane = threadIdx.x & 63;
   const WT* __restrict__ w = (const WT*)a.w;
   const int e0 = ld_idx(a.tile_start + t), e1 = ld_idx(a.tile_start + t + 1);
@@ -409,7 +413,7 @@ __device__ __forceinline__ void tile_a(const KArgs& a, int t, Acc<NC>& acc, unsi
     bool lead;
     double num = seg_sum(wv, rp.y, lane, len, lead);
     if (lead) {
-      acc.add(col_of(rp.y), num, a.pat[pid_of(rp.y)]);
+      acc.add(col_of(rp.y) + coff, num, a.pat[pid_of(rp.y)]);
       if (kMark) atomicOr(&bits[(pid_of(rp.y) - p0) >> 5], 1u << ((pid_of(rp.y) - p0) & 31));
     }
   } else {
@@ -419,7 +423,7 @@ __device__ __forceinline__ void tile_a(const KArgs& a, int t, Acc<NC>& acc, unsi
     s = wave_sum(s);
     if (lane == 0) {
       const uint32_t key = a.rp[e0].y;
-      acc.add(col_of(key), s, a.pat[pid_of(key)]);
+      acc.add(col_of(key) + coff, s, a.pat[pid_of(key)]);
       if (kMark) atomicOr(&bits[(pid_of(key) - p0) >> 5], 1u << ((pid_of(key) - p0) & 31));
     }
   }
@@ -474,8 +478,8 @@ __device__ __forceinline__ void tile_b(const KArgs& a, int t, Coef cf) {
 
 template <typename WT, int NC, bool kMark>
 __device__ __forceinline__ void tiles_a(const KArgs& a, int t, int t1, int stride, Acc<NC>& acc,
-                                        unsigned* bits = nullptr, int p0 = 0) {
-  for (; t < t1; t += stride) tile_a<WT, NC, kMark>(a, t, acc, bits, p0);
+                                        unsigned* bits = nullptr, int p0 = 0, uint32_t coff = 0) {
+  for (; t < t1; t += stride) tile_a<WT, NC, kMark>(a, t, acc, bits, p0, coff);
 }
 
 template <typename WT>
@@ -580,18 +584,18 @@ __device__ __forceinline__ bool first_tile_stale(const Pf& p, const unsigned* bi
 // (validated by the caller) plus its remaining tiles.
 template <typename WT>
 __device__ __forceinline__ void phase_a_cached(const KArgs& a, const Pf& p, const Cache& c, Acc<kMaxGroup>& acc,
-                                               unsigned* bits, int p0) {
+                                               unsigned* bits, int p0, uint32_t coff) {
   if (p.t < p.t1) {
     if (p.len <= 64) {
       if (c.lead) {
-        acc.add(col_of(p.rp.y), c.num, make_double2(c.den, c.wn));
+        acc.add(col_of(p.rp.y) + coff, c.num, make_double2(c.den, c.wn));
         mark_patient(bits, pid_of(p.rp.y) - (unsigned)p0);
       }
     } else {
-      tile_a<WT, kMaxGroup, true>(a, p.t, acc, bits, p0);
+      tile_a<WT, kMaxGroup, true>(a, p.t, acc, bits, p0, coff);
     }
   }
-  tiles_a<WT, kMaxGroup, true>(a, p.t + kWorkers, p.t1, kWorkers, acc, bits, p0);
+  tiles_a<WT, kMaxGroup, true>(a, p.t + kWorkers, p.t1, kWorkers, acc, bits, p0, coff);
 }
 
 template <typename WT>
@@ -621,6 +625,75 @@ __device__ __forceinline__ void phase_b_cached(const KArgs& a, const Pf& p, cons
     }
   }
   tiles_b<WT>(a, p.t + kWorkers, p.t1, kWorkers, cf);
+}
+
+// ---- passes
+//
+// A pass is one device-wide reduction: a column group, or two consecutive
+// groups when the second is predicted independent of the first.  Group
+// g + 1 depends on group g only through the columns of g that share a
+// patient with it (bit c of the descriptor's mask), and only if one of them
+// takes a nonzero step: until it does, the state of the shared patients is
+// untouched.  Under the Laplace prior many coordinates stay at zero sweep
+// after sweep, so the prediction is "those columns did not move in their
+// last visit" (bit j of a per-column bitmap, identical in every workgroup
+// because every workgroup takes the same steps).  After the reduction the
+// prediction is checked against the steps actually taken; when it fails the
+// second group's sums are dropped and that group is visited again, alone, in
+// the next pass.  Either way every column's g_j and h_j are those of the
+// sequential order, and each column's partial sums are accumulated in the
+// same order as without merging (the other group adds exact zeros).
+
+__device__ __forceinline__ int desc_j0(uint32_t d) { return (int)(d & ((1u << kDescColBits) - 1u)); }
+__device__ __forceinline__ int desc_m(uint32_t d) { return (int)((d >> 13) & 7u); }
+__device__ __forceinline__ int desc_mnext(uint32_t d) { return (int)((d >> 16) & 7u); }
+__device__ __forceinline__ uint32_t desc_cmask(uint32_t d) { return (d >> 19) & 15u; }
+
+// Bits [j0, j0 + m) of an LDS bitmap (m <= 4; the bitmap covers j0 + m).
+__device__ __forceinline__ uint32_t get_bits(const uint32_t* bm, int j0, int m) {
+  const int w = j0 >> 5, sh = j0 & 31;
+  uint64_t v = bm[w];
+  if (sh + m > 32) v |= (uint64_t)bm[w + 1] << 32;
+  return (uint32_t)(v >> sh) & ((1u << m) - 1u);
+}
+
+// Set bits [j0, j0 + m) of an LDS bitmap to the low m bits of val (one lane).
+__device__ __forceinline__ void set_bits(uint32_t* bm, int j0, int m, uint32_t val) {
+  const int w = j0 >> 5, sh = j0 & 31;
+  const uint32_t mask = (1u << m) - 1u;
+  val &= mask;
+  bm[w] = (bm[w] & ~(mask << sh)) | (val << sh);
+  if (sh + m > 32) {
+    const int r = 32 - sh;
+    bm[w + 1] = (bm[w + 1] & ~(mask >> r)) | (val >> r);
+  }
+}
+
+// Groups in the pass that starts with descriptor d: 2 when the next group
+// fits in the reduction and every column linking the two is predicted to
+// stay put, else 1.  Uniform (LDS reads of identical values).
+__device__ __forceinline__ int plan_pass(uint32_t d, const uint32_t* mv, int merge) {
+  const int m = desc_m(d);
+  if (!merge || m + desc_mnext(d) > kMaxGroup) return 1;   // also when d is the last group (width 7)
+  const uint32_t linked = desc_cmask(d) & get_bits(mv, desc_j0(d), m);
+  return __builtin_amdgcn_readfirstlane(linked ? 1 : 2);
+}
+
+struct Pass {
+  int s, n;      // first group, number of groups (0: past the last group)
+  uint32_t d;    // descriptor of group s
+  Pf p[2];       // the wave's first tile of each group
+};
+
+// Tile indices of every group of pass p, loaded in sequence (pipeline start).
+__device__ __forceinline__ void load_pass(const KArgs& a, Pass& p) {
+  int t0, t1;
+  pf_range(a, p.s, t0, t1);
+  pf_tile(a, t0, t1, p.p[0]);
+  if (p.n == 2) {
+    pf_range(a, p.s + 1, t0, t1);
+    pf_tile(a, t0, t1, p.p[1]);
+  }
 }
 
 // Exact recomputation of w = L x exp(X beta) and den = M w for patients
@@ -732,47 +805,75 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
   double L = 0.0, P = 0.0;
   const int wave = tid >> 6, lane = tid & 63;
   const bool worker = wave < kWorkers;
-  unsigned* bits0 = (unsigned*)(lds_dyn + 3 * a.J);   // patients of even groups
-  unsigned* bits1 = bits0 + a.nbits;                  // patients of odd groups
+  unsigned* bits0 = (unsigned*)(lds_dyn + 3 * a.J);   // patients of even passes
+  unsigned* bits1 = bits0 + a.nbits;                  // patients of odd passes
+  uint32_t* s_mv = bits1 + a.nbits;                   // moved-column bits (identical in every workgroup)
+  for (int i = tid; i < a.mv_words; i += kBlock) s_mv[i] = a.moved[i];
+  int n_passes = 0, n_rejects = 0;
   const Coef cf{s_ed, s_em1};
+  __syncthreads();
   while (ok && sweep < a.n_sweeps) {
     if (a.criterion == SCCS_CRIT_ABS_DXBETA)
       for (int j = tid; j < a.J; j += kBlock) sprev[j] = sbeta[j];
     for (int i = tid; i < 2 * a.nbits; i += kBlock) bits0[i] = 0u;
-    // pipeline start: indices of groups 0 and 1; nothing speculated
-    Pf pf_cur, pf_next;
-    {
-      int t0, t1;
-      pf_range(a, 0, t0, t1);
-      pf_tile(a, t0, t1, pf_cur);
-      pf_range(a, NG > 1 ? 1 : 0, t0, t1);
-      pf_tile(a, t0, t1, pf_next);
-    }
-    Cache c_cur, c_next;
-    c_cur.valid = false;
-    // group bounds gcol[g], gcol[g+1], gcol[g+2] roll through registers, each
-    // loaded two groups before it is needed
-    int j0 = a.gcol[0], gc1 = a.gcol[1], gc2 = NG > 1 ? a.gcol[2] : gc1;
-    int m = gc1 - j0;
-    double ytx_cur = (wave == kPoller && lane < m) ? a.ytx[j0 + lane] : 0.0;
     __syncthreads();
-    for (int g = 0; g < NG; ++g) {
-      unsigned* bits_cur = (g & 1) ? bits1 : bits0;
-      unsigned* bits_prev = (g & 1) ? bits0 : bits1;
-      const bool has_next = g + 1 < NG;
-      int nt0 = 0, nt1 = 0;
-      if (g + 2 < NG) pf_range(a, g + 2, nt0, nt1);
-      const int gc3 = g + 3 <= NG ? ld_idx(a.gcol + g + 3) : gc2;
-      const int j0n = gc1;
-      const int mn = has_next ? gc2 - gc1 : 0;
-      const double ytx_next = (wave == kPoller && lane < mn) ? a.ytx[j0n + lane] : 0.0;
+    // pipeline start: the first two passes' indices; nothing speculated
+    Pass cur, nxt;
+    cur.s = 0;
+    cur.d = __builtin_amdgcn_readfirstlane(ld_idx(a.gdesc));
+    cur.n = plan_pass(cur.d, s_mv, a.merge);
+    load_pass(a, cur);
+    nxt.s = cur.s + cur.n;
+    nxt.n = 0;
+    nxt.d = 0u;
+    if (nxt.s < NG) {
+      nxt.d = __builtin_amdgcn_readfirstlane(ld_idx(a.gdesc + nxt.s));
+      nxt.n = plan_pass(nxt.d, s_mv, a.merge);
+      load_pass(a, nxt);
+    } else {
+      nxt.s = NG;
+    }
+    uint32_t d_nn = 0u;   // descriptor of the pass after nxt
+    if (nxt.n > 0 && nxt.s + nxt.n < NG) d_nn = ld_idx(a.gdesc + nxt.s + nxt.n);
+    Cache c_cur[2], c_nxt[2];
+    c_cur[0].valid = c_cur[1].valid = false;
+    c_nxt[0].valid = c_nxt[1].valid = false;
+    int par = 0;
+    int mv_cols = 0;        // poller: columns whose moved bits this pass sets
+    uint32_t mv_val = 0u;
+    while (cur.s < NG) {
+      unsigned* bits_cur = par ? bits1 : bits0;
+      unsigned* bits_prev = par ? bits0 : bits1;
+      // the pass after next: the tile ranges of the two groups it may hold
+      // are loaded now; it is planned later, in the shadow of the reduction
+      // (its descriptor was loaded one pass ago; reading it here would wait
+      // for the previous pass's stores as well)
+      Pass nn;
+      nn.s = nxt.s + nxt.n;
+      nn.n = 0;
+      nn.d = 0u;
+      const bool nn_live = nxt.n > 0 && nn.s < NG;
+      int nr0[2] = {0, 0}, nr1[2] = {0, 0};
+      uint32_t d_nnn = 0u;
+      if (nn_live) {
+        pf_range(a, nn.s, nr0[0], nr1[0]);
+        if (nn.s + 1 < NG) pf_range(a, nn.s + 1, nr0[1], nr1[1]);
+      }
+      const int j0 = desc_j0(cur.d);
+      const int ma = desc_m(cur.d);                              // columns of the pass's first group
+      const int m = ma + (cur.n == 2 ? desc_mnext(cur.d) : 0);   // columns of the pass
+      const double ytx_cur = (wave == kPoller && lane < m) ? a.ytx[j0 + lane] : 0.0;
 
-      // phase A: validate the speculative first tile, then accumulate
+      // phase A: validate the speculative first tiles, then accumulate
       Acc<kMaxGroup> acc;
       acc.zero();
       if (worker) {
-        if (!c_cur.valid || (g > 0 && first_tile_stale(pf_cur, bits_prev, p0))) gather_first<WT>(a, pf_cur, c_cur);
-        phase_a_cached<WT>(a, pf_cur, c_cur, acc, bits_cur, p0);
+        if (!c_cur[0].valid || first_tile_stale(cur.p[0], bits_prev, p0)) gather_first<WT>(a, cur.p[0], c_cur[0]);
+        phase_a_cached<WT>(a, cur.p[0], c_cur[0], acc, bits_cur, p0, 0u);
+        if (cur.n == 2) {
+          if (!c_cur[1].valid || first_tile_stale(cur.p[1], bits_prev, p0)) gather_first<WT>(a, cur.p[1], c_cur[1]);
+          phase_a_cached<WT>(a, cur.p[1], c_cur[1], acc, bits_cur, p0, (uint32_t)ma);
+        }
       }
       double loc[2 * kMaxGroup], part[2 * kMaxGroup];
 #pragma unroll
@@ -781,27 +882,29 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
         loc[2 * i + 1] = acc.h[i];
         part[2 * i] = part[2 * i + 1] = 0.0;
       }
-      switch (m) {   // sum only the words of the group's columns (m is uniform)
+      switch (m) {   // sum only the words of the pass's columns (m is uniform)
         case 1: block_sum_to<2>(loc, part, redg, kPoller); break;
 #if SCCS_MAX_GROUP >= 2
         case 2: block_sum_to<4>(loc, part, redg, kPoller); break;
 #endif
         default: block_sum_to<2 * kMaxGroup>(loc, part, redg, kPoller); break;
       }
-      Pf pf_next2;
-      pf_next2.t = pf_next2.t1 = 0;
-      c_next.valid = false;
       if (worker) {
-        // in the shadow of the reduction: clear the bitmap of group g+1,
-        // gather group g+1 speculatively, load indices of group g+2
-        unsigned* bits_next = bits_prev;
-        for (int i = tid; i < a.nbits; i += kWorkers * 64) bits_next[i] = 0u;
-        if (has_next) gather_first<WT>(a, pf_next, c_next);
-        if (g + 2 < NG) pf_tile(a, nt0, nt1, pf_next2);
+        // in the shadow of the reduction: clear the other bitmap, gather the
+        // next pass speculatively, load the tile indices of the pass after it
+        for (int i = tid; i < a.nbits; i += kWorkers * 64) bits_prev[i] = 0u;
+        if (nxt.n > 0) gather_first<WT>(a, nxt.p[0], c_nxt[0]);
+        if (nxt.n == 2) gather_first<WT>(a, nxt.p[1], c_nxt[1]);
+        if (nn_live) {
+          nn.d = __builtin_amdgcn_readfirstlane(d_nn);
+          nn.n = plan_pass(nn.d, s_mv, a.merge);
+          if (nn.s + nn.n < NG) d_nnn = ld_idx(a.gdesc + nn.s + nn.n);
+          pf_tile(a, nr0[0], nr1[0], nn.p[0]);
+          if (nn.n == 2) pf_tile(a, nr0[1], nr1[1], nn.p[1]);
+        }
       } else {
-        // device-wide reduction of the group's 2m partials, then one
-        // Newton / trust-region step (Eq. 4) per column, lane c for column
-        // j0 + c (the columns are independent)
+        // device-wide reduction of the pass's 2m partials, then one Newton /
+        // trust-region step (Eq. 4) per column, lane c for column j0 + c
         double tot[2 * kMaxGroup];
         const int cls = m - 1;
         uint32_t sq = gseq[0];
@@ -831,34 +934,49 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
             Gc = tot[2 * i];
             Hc = tot[2 * i + 1];
           }
-        double d = 0.0;
+        double d = 0.0, bj = 0.0, tr = 0.0;
         int bad = 0;
         if (lane < m) {
           const double gg = ytx_cur - Gc, hh = -Hc;
           bad = !(isfinite(gg) && isfinite(hh));
           if (okr && !bad) {
-            const int j = j0 + lane;
-            const double bj = sbeta[j], tr = strust[j];
+            bj = sbeta[j0 + lane];
+            tr = strust[j0 + lane];
             const double dv = prior_step(a.prior_kind, a.inv_var, a.lambda, bj, gg, hh);
             d = fmin(fmax(dv, -tr), tr);
-            strust[j] = fmax(2.0 * fabs(d), 0.5 * tr);
-            const double nb = bj + d;
-            if (!isfinite(nb)) { bad = 1; d = 0.0; }
-            else sbeta[j] = nb;
           }
+        }
+        // a merged pass keeps its second group only if no column of the first
+        // group that shares a patient with it moved; else that group is
+        // visited again, alone, in the next pass (its sums are discarded)
+        const uint32_t cmask = desc_cmask(cur.d);
+        const bool rej = cur.n == 2 && __ballot(lane < ma && d != 0.0 && ((cmask >> lane) & 1u)) != 0ull;
+        const int mc = rej ? ma : m;   // columns whose step is taken
+        if (lane >= mc) {
+          d = 0.0;
+          bad = 0;
+        }
+        if (lane < mc && okr && !bad) {
+          strust[j0 + lane] = fmax(2.0 * fabs(d), 0.5 * tr);
+          const double nb = bj + d;
+          if (!isfinite(nb)) { bad = 1; d = 0.0; }
+          else sbeta[j0 + lane] = nb;
         }
         if (lane < kMaxGroup) {
           const double em1 = expm1(d);
           s_ed[lane] = 1.0 + em1;
           s_em1[lane] = em1;
         }
-        const bool any_step = __ballot(d != 0.0) != 0ull;
+        const uint64_t moved = __ballot(lane < mc && d != 0.0);
         const bool any_bad = __ballot(bad != 0) != 0ull;
         if (lane == 0) {
           bci[0] = okr ? 1 : 0;
           bci[1] = any_bad ? 1 : 0;
-          bci[2] = any_step ? 1 : 0;
+          bci[2] = moved != 0ull ? 1 : 0;
+          bci[3] = rej ? 1 : 0;
         }
+        mv_cols = okr ? mc : 0;
+        mv_val = (uint32_t)moved;
       }
       __syncthreads();
 #pragma unroll
@@ -866,16 +984,44 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
         if (m - 1 == c) ++gseq[c];
       if (!bci[0]) { ok = false; break; }
       if (bci[1]) { status = SCCS_ERR_NUMERIC; ok = false; break; }
-      if (worker && bci[2]) phase_b_cached<WT>(a, pf_cur, c_cur, cf);
+      const bool rejected = bci[3] != 0;
+      if (worker) {
+        if (bci[2]) {
+          phase_b_cached<WT>(a, cur.p[0], c_cur[0], cf);
+          // a rejected second group is left untouched
+          if (cur.n == 2 && !rejected) phase_b_cached<WT>(a, cur.p[1], c_cur[1], Coef{s_ed + ma, s_em1 + ma});
+        }
+      } else {
+        // while the workers update: record which columns moved (no pass
+        // reads these bits before the next sweep), and plan the pass after
+        // next as the workers did (same bits, same answer)
+        if (lane == 0 && mv_cols > 0) set_bits(s_mv, j0, mv_cols, mv_val);
+        if (nn_live) {
+          nn.d = __builtin_amdgcn_readfirstlane(d_nn);
+          nn.n = plan_pass(nn.d, s_mv, a.merge);
+          if (nn.s + nn.n < NG) d_nnn = ld_idx(a.gdesc + nn.s + nn.n);
+        }
+      }
       __syncthreads();
-      pf_cur = pf_next;
-      pf_next = pf_next2;
-      c_cur = c_next;
-      ytx_cur = ytx_next;
-      j0 = j0n;
-      m = mn;
-      gc1 = gc2;
-      gc2 = gc3;
+      ++n_passes;
+      par ^= 1;
+      if (rejected) {
+        // the second group alone, from fresh data; nxt and the passes after
+        // it stay as planned (their speculative gathers are repeated)
+        ++n_rejects;
+        cur.s += 1;
+        cur.n = 1;
+        cur.d = (uint32_t)(j0 + ma) | ((uint32_t)desc_mnext(cur.d) << 13) | (7u << 16);
+        cur.p[0] = cur.p[1];
+        c_cur[0].valid = false;
+      } else {
+        cur = nxt;
+        c_cur[0] = c_nxt[0];
+        c_cur[1] = c_nxt[1];
+        nxt = nn;
+        d_nn = d_nnn;
+        if (nxt.n == 0) nxt.s = NG;
+      }
     }
     if (!ok) break;
     ++sweep;
@@ -907,7 +1053,10 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
       a.beta[j] = sbeta[j];
       a.trust[j] = strust[j];
     }
+    for (int i = tid; i < a.mv_words; i += kBlock) a.moved[i] = s_mv[i];
     if (tid == 0) {
+      a.ctrl->passes = n_passes;
+      a.ctrl->rejects = n_rejects;
       a.ctrl->sweeps = sweep;
       a.ctrl->converged = converged;
       a.ctrl->loglik = L;

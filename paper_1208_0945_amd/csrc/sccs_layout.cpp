@@ -160,6 +160,28 @@ void build_layout(const sccs_problem* p, int32_t G, Layout& L, int32_t tile_nnz,
   const int32_t NG = (int32_t)L.gcol.size() - 1;
   L.n_groups = NG;
 
+  // pass descriptors: which columns of group g share a patient with g + 1
+  L.gdesc.assign((size_t)NG, 0u);
+  if (J < kDescMaxCols) {
+    std::vector<int32_t> stamp((size_t)N, -1);
+    for (int32_t g = 0; g < NG; ++g) {
+      const uint32_t j0 = (uint32_t)L.gcol[g], m = (uint32_t)(L.gcol[g + 1] - L.gcol[g]);
+      uint32_t mnext = 7u, cmask = 0u;
+      if (g + 1 < NG) {
+        mnext = (uint32_t)(L.gcol[g + 2] - L.gcol[g + 1]);
+        for (int32_t j = L.gcol[g + 1]; j < L.gcol[g + 2]; ++j)
+          for (int64_t e = p->col_ptr[j]; e < p->col_ptr[j + 1]; ++e) stamp[era_pid[p->row_idx[e]]] = g + 1;
+        for (uint32_t c = 0; c < m; ++c) {
+          const int32_t j = (int32_t)(j0 + c);
+          bool hit = false;
+          for (int64_t e = p->col_ptr[j]; e < p->col_ptr[j + 1] && !hit; ++e) hit = stamp[era_pid[p->row_idx[e]]] == g + 1;
+          if (hit) cmask |= 1u << c;
+        }
+      }
+      L.gdesc[g] = j0 | (m << 13) | (mnext << 16) | (cmask << 19);
+    }
+  }
+
   // cwb[j*(G+1) + b]: first CSC position of column j at or after workgroup b's eras
   std::vector<int64_t> cwb((size_t)J * (G + 1));
   parallel_ranges(J, [&](int64_t jlo, int64_t jhi) {

@@ -26,6 +26,13 @@
 // order.  own[g*(G+1) + b] is the first tile of group g owned by workgroup
 // b; own[g*(G+1) + G] closes group g.  rp[e] = (row, patient | c << 28)
 // with c the column's index within its group.
+//
+// Pass descriptors.  gdesc[g] packs what the sweep needs to decide, at run
+// time, whether group g+1 can share group g's reduction (see
+// sccs_kernels.hpp): g's first column (bits 0-12), its width (bits 13-15),
+// the width of group g+1 (bits 16-18; 7 when g is the last group) and a mask
+// (bits 19-22) whose bit c is set when column c of g shares a patient with
+// group g+1.
 #pragma once
 #include <cstdint>
 #include <string>
@@ -47,6 +54,7 @@ struct Layout {
   std::vector<int32_t> own;         // [n_groups*(G+1)]
   int32_t n_groups = 0;
   std::vector<int32_t> gcol;        // [n_groups+1] first column of each group
+  std::vector<uint32_t> gdesc;      // [n_groups] pass descriptors
   std::vector<int32_t> pptr;        // [N+1] patient_ptr as int32
   std::vector<int32_t> era_ptr;     // [K+1] compressed row storage of X
   std::vector<int32_t> era_col;     // [nnz]

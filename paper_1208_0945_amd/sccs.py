@@ -23,7 +23,7 @@ CRIT_FIXED, CRIT_REL_LOGPOST, CRIT_ABS_DXBETA = 0, 1, 2
 
 EXPORTS = ("sccs_default_options", "sccs_query_workspace", "sccs_create", "sccs_destroy",
            "sccs_set_prior", "sccs_set_beta", "sccs_get_beta", "sccs_sweep", "sccs_fit",
-           "sccs_grad_hess", "sccs_objective", "sccs_last_kernel_ms", "sccs_last_error",
+           "sccs_grad_hess", "sccs_objective", "sccs_last_kernel_ms", "sccs_pass_stats", "sccs_last_error",
            "sccs_batch_query_workspace", "sccs_batch_create", "sccs_batch_run", "sccs_batch_get",
            "sccs_batch_heldout", "sccs_batch_last_kernel_ms", "sccs_batch_destroy", "sccs_batch_last_error", "sccs_tune")
 
@@ -45,7 +45,8 @@ class Problem_(ctypes.Structure):
 class Options_(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("n_workgroups", ctypes.c_int32),
                 ("refresh_period", ctypes.c_int32), ("tile_nnz", ctypes.c_int32),
-                ("max_group", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("max_group", ctypes.c_int32), ("merge_passes", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
 
 
 class FitOpts_(ctypes.Structure):
@@ -112,6 +113,8 @@ def lib() -> ctypes.CDLL:
         L.sccs_grad_hess.argtypes = [H, ctypes.c_int32, dp, dp]
         L.sccs_objective.argtypes = [H, dp, dp]
         L.sccs_last_kernel_ms.argtypes = [H, dp]
+        ip = ctypes.POINTER(ctypes.c_int32)
+        L.sccs_pass_stats.argtypes = [H, ip, ip]
         L.sccs_last_error.argtypes = [H]
         L.sccs_last_error.restype = ctypes.c_char_p
         L.sccs_batch_query_workspace.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
@@ -157,7 +160,8 @@ class ProblemArrays:
 
 
 def options(precision: int = PREC_FP64, n_workgroups: int = 0, refresh_period: int = -1,
-            stream: Optional[int] = None, tile_nnz: int = 0, max_group: int = 0) -> Options_:
+            stream: Optional[int] = None, tile_nnz: int = 0, max_group: int = 0,
+            merge_passes: int = 1) -> Options_:
     o = Options_()
     lib().sccs_default_options(ctypes.byref(o))
     o.precision = precision
@@ -165,6 +169,7 @@ def options(precision: int = PREC_FP64, n_workgroups: int = 0, refresh_period: i
     o.refresh_period = refresh_period
     o.tile_nnz = tile_nnz
     o.max_group = max_group
+    o.merge_passes = merge_passes
     o.stream = stream
     return o
 
@@ -185,14 +190,15 @@ class Handle:
 
     def __init__(self, prob, weight=None, precision: int = PREC_FP64, n_workgroups: int = 0,
                  refresh_period: int = -1, stream=None, workspace: str = "torch", tile_nnz: int = 0,
-                 max_group: int = 0):
+                 max_group: int = 0, merge_passes: int = 1):
         import torch
         self.torch = torch
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
         P = ProblemArrays(prob, weight)
-        o = options(precision, n_workgroups, refresh_period, stream.cuda_stream, tile_nnz, max_group)
+        o = options(precision, n_workgroups, refresh_period, stream.cuda_stream, tile_nnz, max_group,
+                    merge_passes)
         n = ctypes.c_size_t()
         L = lib()
         st = L.sccs_query_workspace(ctypes.byref(P.s), ctypes.byref(o), ctypes.byref(n))
@@ -279,6 +285,12 @@ class Handle:
         ms = ctypes.c_double()
         self._check(lib().sccs_last_kernel_ms(self.h, ctypes.byref(ms)))
         return ms.value
+
+    def pass_stats(self) -> Tuple[int, int]:
+        """(device-wide reductions, rejected merges) of the last sweep/fit launch."""
+        p, r = ctypes.c_int32(), ctypes.c_int32()
+        self._check(lib().sccs_pass_stats(self.h, ctypes.byref(p), ctypes.byref(r)))
+        return p.value, r.value
 
 
 def tune(prob, prior_kind: int, variance: float, n_sweeps: int = 2, precision: int = PREC_FP64, weight=None):

@@ -219,7 +219,7 @@ def paper_shaped(n_patients: int = 3_600_000, n_cols: int = 1428, seed: int = 0)
     popularity: eras 1 + Poisson(19.83) per patient (~20.8 on average, so
     K ~ 75M), p_j = 0.1 rank^-1.1, 50 true effects ~N(0, 0.7).  The real
     claims data are not available; only the sizes are the paper's."""
-    return zipf_problem("paper", n_patients, n_cols, 0.1, seed_path=(8, seed), era_mean=19.83)
+    return zipf_problem("paper", n_patients, n_cols, 0.1, seed_path=(9, seed), era_mean=19.83)
 
 
 def outcome_sizes(n_fits: int = 64, lo: float = 1e4, hi: float = 2e6, seed: int = 0) -> np.ndarray:

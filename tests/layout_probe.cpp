@@ -6,7 +6,7 @@
 
 extern "C" int layout_probe(const sccs_problem* p, int G, int tile_nnz, int max_group, int* pb, unsigned* rp,
                             int* tile_start, long long* n_tiles, int* own, int* era_ptr, int* era_col,
-                            long long* bound, int* gcol, int* n_groups) {
+                            long long* bound, int* gcol, int* n_groups, unsigned* gdesc) {
   std::string err;
   if (sccs::validate_problem(p, err) != SCCS_OK) return -1;
   sccs::Layout L;
@@ -21,6 +21,7 @@ extern "C" int layout_probe(const sccs_problem* p, int G, int tile_nnz, int max_
   std::memcpy(era_ptr, L.era_ptr.data(), L.era_ptr.size() * 4);
   std::memcpy(era_col, L.era_col.data(), L.era_col.size() * 4);
   std::memcpy(gcol, L.gcol.data(), L.gcol.size() * 4);
+  if (gdesc) std::memcpy(gdesc, L.gdesc.data(), L.gdesc.size() * 4);
   return 0;
 }
 

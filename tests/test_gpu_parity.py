@@ -137,6 +137,39 @@ def test_zipf_laplace_20_sweeps(sccs, n_workgroups, tile_nnz, max_group):
     assert np.array_equal(beta == 0.0, ref["beta"] == 0.0)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_merged_passes_match_plain_order(sccs, precision):
+    """Merged passes (two column groups in one reduction when the columns
+    linking them are predicted to stay put) against one pass per group: the
+    same beta bit for bit after every sweep, also after a prior change that
+    makes predicted-quiet columns move (merges rejected and the second group
+    visited again); merges and rejections both occur; FP64 beta equals the
+    oracle's for the same prior chain."""
+    prob = zipf_small()
+    chain = [(0.05, 12), (5.0, 8)]
+    betas, stats = {}, {}
+    for merge in (0, 1):
+        with sccs.Handle(prob, precision=precision, merge_passes=merge) as h:
+            seq, st = [], []
+            for var, n in chain:
+                h.set_prior(2, var)
+                for _ in range(n):
+                    h.sweep(1)
+                    seq.append(h.get_beta()[0])
+                    st.append(h.pass_stats())
+            betas[merge], stats[merge] = seq, st
+    for k, (b0, b1) in enumerate(zip(betas[0], betas[1])):
+        assert np.array_equal(b0, b1), f"sweep {k}"
+    print("passes/rejects per sweep, merged:", stats[1], "plain:", stats[0][0])
+    assert len({p for p, _ in stats[0]}) == 1 and all(r == 0 for _, r in stats[0])
+    assert sum(p for p, _ in stats[1]) < sum(p for p, _ in stats[0])
+    assert sum(r for _, r in stats[1]) > 0
+    if precision == 0:
+        r1 = oracle.ccd(prob, 2, 0.05, 12)
+        r2 = oracle.ccd(prob, 2, 5.0, 8, beta0=r1["beta"], trust0=r1["trust"])
+        assert rel_inf(betas[1][-1], r2["beta"]) <= FP64_TOL
+
+
 def ragged_problem():
     """Patients from 1 to 300 eras; a column covering every era of the long
     patients (segments longer than one wavefront), an empty column, a single

@@ -20,12 +20,12 @@ def probe(tmp_path_factory):
                     "-I", CSRC, os.path.join(ROOT, "tests", "layout_probe.cpp"),
                     os.path.join(CSRC, "sccs_layout.cpp"), "-o", out], check=True)
     lib = ctypes.CDLL(out)
-    lib.layout_probe.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int] + [ctypes.c_void_p] * 10
+    lib.layout_probe.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int] + [ctypes.c_void_p] * 11
     lib.ytx_probe.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     return lib
 
 
-def run(probe, prob, G, tile_nnz, max_group=1):
+def run(probe, prob, G, tile_nnz, max_group=1, gdesc=None):
     P = sccs.ProblemArrays(prob)
     K, N, J, nnz = prob.n_rows, prob.n_patients, prob.n_cols, prob.nnz
     pb = np.zeros(G + 1, np.int32)
@@ -38,7 +38,8 @@ def run(probe, prob, G, tile_nnz, max_group=1):
     ts = np.zeros(2 * nnz // tile_nnz + 2 * min(nnz, J * G) + 4, np.int32)
     rc = probe.layout_probe(ctypes.addressof(P.s), G, tile_nnz, max_group, pb.ctypes.data, rp.ctypes.data,
                             ts.ctypes.data, ctypes.byref(nt), own.ctypes.data, era_ptr.ctypes.data,
-                            era_col.ctypes.data, ctypes.byref(bound), gcol.ctypes.data, ctypes.byref(ng))
+                            era_col.ctypes.data, ctypes.byref(bound), gcol.ctypes.data, ctypes.byref(ng),
+                            None if gdesc is None else gdesc.ctypes.data)
     assert rc == 0
     n_groups = ng.value
     if max_group == 1:
@@ -161,3 +162,34 @@ def test_host_ytx(probe):
     for j in range(prob.n_cols):
         rows = prob.column(j)
         assert out[j] == float(np.sum(w[era_pid[rows]] * prob.count[rows]))
+
+
+@pytest.mark.parametrize("max_group", [1, 2, 4])
+def test_pass_descriptors(probe, max_group):
+    """Pass descriptors: first column and width of each group, width of the
+    next group (7 after the last), and the mask of the group's columns that
+    share a patient with the next group -- against sets of patients."""
+    prob = synth.zipf_problem("desc", 3000, 70, 0.03, seed_path=(11, 200 + max_group))
+    J = prob.n_cols
+    gdesc = np.zeros(J, np.uint32)
+    pb, rp, ts, own, *rest = run(probe, prob, 16, 64, max_group, gdesc=gdesc)
+    gcol = np.arange(J + 1) if max_group == 1 else rest[-1]
+    NG = len(gcol) - 1
+    era_pid = np.repeat(np.arange(prob.n_patients), np.diff(prob.patient_ptr))
+    pats = [set(era_pid[prob.column(j)].tolist()) for j in range(J)]
+    n_linked = 0
+    for g in range(NG):
+        d = int(gdesc[g])
+        assert d & 0x1FFF == gcol[g]
+        assert (d >> 13) & 7 == gcol[g + 1] - gcol[g]
+        if g + 1 < NG:
+            assert (d >> 16) & 7 == gcol[g + 2] - gcol[g + 1]
+            nxt = set().union(*(pats[j] for j in range(gcol[g + 1], gcol[g + 2])))
+            mask = sum(1 << c for c, j in enumerate(range(gcol[g], gcol[g + 1])) if pats[j] & nxt)
+        else:
+            assert (d >> 16) & 7 == 7
+            mask = 0
+        assert (d >> 19) & 15 == mask, g
+        assert d >> 23 == 0
+        n_linked += mask != 0
+    assert 0 < n_linked < NG, "both linked and independent neighbours should occur"
