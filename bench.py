@@ -65,10 +65,12 @@ def run_form(sccs, prob, precision, steps, warmup, c, p):
     torch.cuda.synchronize()
     kernel_ms = []
     algo_bytes = []
+    passes = []
     t0 = time.perf_counter()
     for _ in range(steps):
         h.sweep(1)
         kernel_ms.append(h.last_kernel_ms())
+        passes.append(h.pass_stats())
         beta, _ = h.get_beta()
         algo_bytes.append(bytes_per_sweep(c, p, beta != beta_prev, precision))
         beta_prev = beta
@@ -76,7 +78,7 @@ def run_form(sccs, prob, precision, steps, warmup, c, p):
     wall = time.perf_counter() - t0
     beta, _ = h.get_beta()
     h.close()
-    return {"wall_s": wall, "kernel_ms": kernel_ms, "bytes": algo_bytes, "beta": beta}
+    return {"wall_s": wall, "kernel_ms": kernel_ms, "bytes": algo_bytes, "beta": beta, "passes": passes}
 
 
 def profiled_traffic(kernel_ms):
@@ -369,6 +371,11 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(ms),
                      "kernel": "k_ccd<double>", "kernel_ms_mean": ms,
                      "algo_bytes_per_launch": float(np.mean(fp["bytes"]))},
+        # device-wide reductions per sweep (column groups, two merged into one
+        # pass when predicted independent) and merges undone per sweep
+        "schedule": {"passes_per_sweep_mean": float(np.mean([q for q, _ in fp["passes"]])),
+                     "passes_last_sweep": int(fp["passes"][-1][0]),
+                     "rejected_merges_per_sweep_mean": float(np.mean([r for _, r in fp["passes"]]))},
     }
     if not args.no_mixed:
         mx = run_form(sccs, prob, 1, args.steps, args.warmup, c, p)

@@ -42,6 +42,10 @@ struct sccs_handle {
   int32_t* d_weight = nullptr;
   std::vector<int32_t> gcol;  // host copy of the column groups
   Ctrl* h_ctrl = nullptr;  // pinned host mirror of the control block
+  uint32_t gseq0[kMaxGroup] = {};  // reduction sequence numbers before the last sweep launch
+  int last_mode = -1;              // kind of the last launch
+  int32_t passes = 0, rejects = 0; // schedule statistics of the last sweep launch
+  bool swept = false;
 };
 
 static thread_local std::string g_create_error;
@@ -147,9 +151,14 @@ sccs_status pick_workgroups(const sccs_options* o, int32_t& G, std::string& err)
   return SCCS_OK;
 }
 
-const void* ccd_kernel(int prec, int mode) {
-  if (mode == kModeSweep)
-    return prec == SCCS_PREC_FP64 ? (const void*)k_ccd<double> : (const void*)k_ccd<float>;
+// The sweep kernel with merged passes is used where zero steps occur (the
+// Laplace prior); otherwise the one-pass-per-group form, which carries less
+// state per pass.
+const void* ccd_kernel(int prec, int mode, bool merge = false) {
+  if (mode == kModeSweep) {
+    if (merge) return prec == SCCS_PREC_FP64 ? (const void*)k_ccd<double, true> : (const void*)k_ccd<float, true>;
+    return prec == SCCS_PREC_FP64 ? (const void*)k_ccd<double, false> : (const void*)k_ccd<float, false>;
+  }
   return prec == SCCS_PREC_FP64 ? (const void*)k_diag<double> : (const void*)k_diag<float>;
 }
 
@@ -174,6 +183,14 @@ sccs_status usable(sccs_handle* h) {
 sccs_status read_ctrl(sccs_handle* h) {
   HIPCHK(h, hipMemcpyAsync(h->h_ctrl, h->args.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (h->last_mode == kModeSweep) {
+    // one reduction per pass, each on the sequence of its width class
+    uint32_t n = 0;
+    for (int c = 0; c < kMaxGroup; ++c) n += h->h_ctrl->gseq[c] - h->gseq0[c];
+    h->passes = (int32_t)n;
+    h->rejects = h->h_ctrl->rejects;
+    h->swept = true;
+  }
   if (h->h_ctrl->status == SCCS_ERR_SYNC) {
     h->failed = true;
     h->err = "device-wide reduction timed out (workgroups not co-resident?)";
@@ -208,7 +225,11 @@ sccs_status launch(sccs_handle* h, int mode, int n_sweeps, int criterion, double
   void* params[] = {&a};
   HIPCHK(h, hipMemsetAsync(&h->args.ctrl->status, 0, sizeof(int32_t), h->stream));
   HIPCHK(h, hipEventRecord(h->ev0, h->stream));
-  HIPCHK(h, hipLaunchCooperativeKernel(ccd_kernel(h->prec, mode), dim3(h->G), dim3(kBlock), params,
+  const bool merge = a.merge && a.prior_kind == SCCS_PRIOR_LAPLACE;
+  if (mode == kModeSweep)   // the mirror holds the state after the previous launch
+    for (int c = 0; c < kMaxGroup; ++c) h->gseq0[c] = h->h_ctrl->gseq[c];
+  h->last_mode = mode;
+  HIPCHK(h, hipLaunchCooperativeKernel(ccd_kernel(h->prec, mode, merge), dim3(h->G), dim3(kBlock), params,
                                         (unsigned)h->lds_bytes, h->stream));
   HIPCHK(h, hipEventRecord(h->ev1, h->stream));
   h->timed = true;
@@ -358,13 +379,13 @@ sccs_status sccs_create(const sccs_problem* prob, const sccs_options* opts_in, v
     return bail("hipEventCreate failed", SCCS_ERR_HIP);
   if (hipHostMalloc((void**)&h->h_ctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess)
     return bail("hipHostMalloc failed", SCCS_ERR_HIP);
+  std::memset(h->h_ctrl, 0, sizeof(Ctrl));   // mirrors the zeroed device block
 
   // occupancy: every workgroup must be resident at once
-  for (int mode : {kModeSweep, kModeObjective}) {
+  for (const void* k : {ccd_kernel(h->prec, kModeSweep, false), ccd_kernel(h->prec, kModeSweep, true),
+                         ccd_kernel(h->prec, kModeObjective)}) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ccd_kernel(h->prec, mode), kBlock, h->lds_bytes) !=
-            hipSuccess ||
-        per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kBlock, h->lds_bytes) != hipSuccess || per_cu < 1)
       return bail("the persistent kernel cannot be resident (registers or LDS)", SCCS_ERR_HIP);
   }
 
@@ -544,10 +565,9 @@ sccs_status sccs_objective(sccs_handle* h, double* loglik, double* logpost) {
 
 sccs_status sccs_pass_stats(sccs_handle* h, int32_t* passes, int32_t* rejects) {
   if (!h || !passes || !rejects) return SCCS_ERR_INVALID_ARG;
-  if (!h->timed) { h->err = "no kernel launched yet"; return SCCS_ERR_STATE; }
-  HIPCHK(h, hipStreamSynchronize(h->stream));
-  *passes = h->h_ctrl->passes;
-  *rejects = h->h_ctrl->rejects;
+  if (!h->swept) { h->err = "no sweep run yet"; return SCCS_ERR_STATE; }
+  *passes = h->passes;
+  *rejects = h->rejects;
   return SCCS_OK;
 }
 

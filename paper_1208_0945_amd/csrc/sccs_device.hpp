@@ -43,8 +43,8 @@ struct Ctrl {
   double loglik, logpost;
   double g, h;         // diagnostic output
   uint32_t gseq[kMaxGroup];  // single fit: sequence number of each reduction class
-  int32_t passes;      // single fit, last launch: device-wide reductions of coordinates
-  int32_t rejects;     //   merged passes whose second group was visited again
+  int32_t rejects;     // single fit, last launch: merged passes whose second group was visited again
+  int32_t pad2;
 };
 
 struct KArgs {

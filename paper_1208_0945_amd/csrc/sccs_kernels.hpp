@@ -766,7 +766,7 @@ __device__ __forceinline__ bool objective(const KArgs& a, const double* sbeta, c
 
 // ------------------------------------------------------------ persistent kernel
 
-template <typename WT>
+template <typename WT, bool kMerge>
 __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
   extern __shared__ double lds_dyn[];
   double* sbeta = lds_dyn;              // [J]
@@ -803,224 +803,374 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
   }
   int sweep = 0, converged = 0;
   double L = 0.0, P = 0.0;
-  const int wave = tid >> 6, lane = tid & 63;
+  // merged passes: the wave index in a scalar register, so that the
+  // worker/poller branches are uniform and so is the pass state they assign
+  // (the one-pass-per-group loop measured faster without)
+  const int wave = kMerge ? __builtin_amdgcn_readfirstlane(tid >> 6) : tid >> 6, lane = tid & 63;
   const bool worker = wave < kWorkers;
   unsigned* bits0 = (unsigned*)(lds_dyn + 3 * a.J);   // patients of even passes
   unsigned* bits1 = bits0 + a.nbits;                  // patients of odd passes
   uint32_t* s_mv = bits1 + a.nbits;                   // moved-column bits (identical in every workgroup)
   for (int i = tid; i < a.mv_words; i += kBlock) s_mv[i] = a.moved[i];
-  int n_passes = 0, n_rejects = 0;
+  __shared__ uint32_t s_nn[2];   // merged passes: the pass after next (groups, descriptor), for the poller
+  __shared__ int s_nrej;         // merged passes: rejected merges in this launch
+  if (tid == 0) s_nrej = 0;
   const Coef cf{s_ed, s_em1};
   __syncthreads();
   while (ok && sweep < a.n_sweeps) {
     if (a.criterion == SCCS_CRIT_ABS_DXBETA)
       for (int j = tid; j < a.J; j += kBlock) sprev[j] = sbeta[j];
     for (int i = tid; i < 2 * a.nbits; i += kBlock) bits0[i] = 0u;
-    __syncthreads();
-    // pipeline start: the first two passes' indices; nothing speculated
-    Pass cur, nxt;
-    cur.s = 0;
-    cur.d = __builtin_amdgcn_readfirstlane(ld_idx(a.gdesc));
-    cur.n = plan_pass(cur.d, s_mv, a.merge);
-    load_pass(a, cur);
-    nxt.s = cur.s + cur.n;
-    nxt.n = 0;
-    nxt.d = 0u;
-    if (nxt.s < NG) {
-      nxt.d = __builtin_amdgcn_readfirstlane(ld_idx(a.gdesc + nxt.s));
-      nxt.n = plan_pass(nxt.d, s_mv, a.merge);
-      load_pass(a, nxt);
+    if constexpr (kMerge) {
+      __syncthreads();
+      // pipeline start: the first two passes' indices; nothing speculated
+      Pass cur, nxt;
+      cur.s = 0;
+      cur.d = __builtin_amdgcn_readfirstlane(ld_idx(a.gdesc));
+      cur.n = plan_pass(cur.d, s_mv, a.merge);
+      load_pass(a, cur);
+      nxt.s = cur.s + cur.n;
+      nxt.n = 0;
+      nxt.d = 0u;
+      if (nxt.s < NG) {
+        nxt.d = __builtin_amdgcn_readfirstlane(ld_idx(a.gdesc + nxt.s));
+        nxt.n = plan_pass(nxt.d, s_mv, a.merge);
+        load_pass(a, nxt);
+      } else {
+        nxt.s = NG;
+      }
+      uint32_t d_nn = 0u;   // descriptor of the pass after nxt
+      if (nxt.n > 0 && nxt.s + nxt.n < NG) d_nn = ld_idx(a.gdesc + nxt.s + nxt.n);
+      Cache c_cur[2], c_nxt[2];
+      c_cur[0].valid = c_cur[1].valid = false;
+      c_nxt[0].valid = c_nxt[1].valid = false;
+      int par = 0;
+      int mv_cols = 0;        // poller: columns whose moved bits this pass sets
+      uint32_t mv_val = 0u;
+      while (cur.s < NG) {
+        unsigned* bits_cur = par ? bits1 : bits0;
+        unsigned* bits_prev = par ? bits0 : bits1;
+        // the pass after next: the tile ranges of the two groups it may hold
+        // are loaded now; it is planned later, in the shadow of the reduction
+        // (its descriptor was loaded one pass ago; reading it here would wait
+        // for the previous pass's stores as well)
+        Pass nn;
+        nn.s = nxt.s + nxt.n;
+        nn.n = 0;
+        nn.d = 0u;
+        const bool nn_live = nxt.n > 0 && nn.s < NG;
+        int nr0 = 0, nr1 = 0;
+        uint32_t d_nnn = 0u;
+        if (nn_live && worker) {
+          pf_range(a, nn.s, nr0, nr1);
+        }
+        const int j0 = desc_j0(cur.d);
+        const int ma = desc_m(cur.d);                              // columns of the pass's first group
+        const int m = ma + (cur.n == 2 ? desc_mnext(cur.d) : 0);   // columns of the pass
+        const double ytx_cur = (wave == kPoller && lane < m) ? a.ytx[j0 + lane] : 0.0;
+
+        // phase A: validate the speculative first tiles, then accumulate
+        Acc<kMaxGroup> acc;
+        acc.zero();
+        if (worker) {
+          if (!c_cur[0].valid || first_tile_stale(cur.p[0], bits_prev, p0)) gather_first<WT>(a, cur.p[0], c_cur[0]);
+          phase_a_cached<WT>(a, cur.p[0], c_cur[0], acc, bits_cur, p0, 0u);
+          if (cur.n == 2) {
+            if (!c_cur[1].valid || first_tile_stale(cur.p[1], bits_prev, p0)) gather_first<WT>(a, cur.p[1], c_cur[1]);
+            phase_a_cached<WT>(a, cur.p[1], c_cur[1], acc, bits_cur, p0, (uint32_t)ma);
+          }
+        }
+        double loc[2 * kMaxGroup], part[2 * kMaxGroup];
+  #pragma unroll
+        for (int i = 0; i < kMaxGroup; ++i) {
+          loc[2 * i] = acc.g[i];
+          loc[2 * i + 1] = acc.h[i];
+          part[2 * i] = part[2 * i + 1] = 0.0;
+        }
+        switch (m) {   // sum only the words of the pass's columns (m is uniform)
+          case 1: block_sum_to<2>(loc, part, redg, kPoller); break;
+  #if SCCS_MAX_GROUP >= 2
+          case 2: block_sum_to<4>(loc, part, redg, kPoller); break;
+  #endif
+          default: block_sum_to<2 * kMaxGroup>(loc, part, redg, kPoller); break;
+        }
+        if (worker) {
+          // in the shadow of the reduction: clear the other bitmap, gather the
+          // next pass speculatively, load the tile indices of the pass after it
+          for (int i = tid; i < a.nbits; i += kWorkers * 64) bits_prev[i] = 0u;
+          if (nxt.n > 0) gather_first<WT>(a, nxt.p[0], c_nxt[0]);
+          if (nxt.n == 2) gather_first<WT>(a, nxt.p[1], c_nxt[1]);
+          if (nn_live) {
+            nn.d = __builtin_amdgcn_readfirstlane(d_nn);
+            nn.n = plan_pass(nn.d, s_mv, a.merge);
+            if (nn.s + nn.n < NG) d_nnn = ld_idx(a.gdesc + nn.s + nn.n);
+            pf_tile(a, nr0, nr1, nn.p[0]);
+            if (nn.n == 2) {   // the second group's range only now (merged passes are the fewer)
+              int t0, t1;
+              pf_range(a, nn.s + 1, t0, t1);
+              pf_tile(a, t0, t1, nn.p[1]);
+            }
+          }
+          if (tid == 0) {
+            s_nn[0] = (uint32_t)nn.n;
+            s_nn[1] = nn.d;
+          }
+        } else {
+          // device-wide reduction of the pass's 2m partials, then one Newton /
+          // trust-region step (Eq. 4) per column, lane c for column j0 + c
+          double tot[2 * kMaxGroup];
+          const int cls = m - 1;
+          uint32_t sq = gseq[0];
+  #pragma unroll
+          for (int c = 1; c < kMaxGroup; ++c)
+            if (cls == c) sq = gseq[c];
+          uint64_t* s1 = a.slots + cls * kSlots1PerClass;
+          uint64_t* s2 = a.slots2 + cls * kSlots2PerClass;
+  #pragma unroll
+          for (int i = 0; i < 2 * kMaxGroup; ++i) tot[i] = 0.0;
+          bool okr;
+          switch (m) {   // one width per slot class, fixed at compile time
+            case 1: okr = allreduce2_wave<2>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
+  #if SCCS_MAX_GROUP >= 2
+            case 2: okr = allreduce2_wave<4>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
+  #endif
+  #if SCCS_MAX_GROUP >= 3
+            case 3: okr = allreduce2_wave<6>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
+  #endif
+            default: okr = allreduce2_wave<2 * kMaxGroup>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
+          }
+
+          double Gc = 0.0, Hc = 0.0;
+  #pragma unroll
+          for (int i = 0; i < kMaxGroup; ++i)
+            if (lane == i) {
+              Gc = tot[2 * i];
+              Hc = tot[2 * i + 1];
+            }
+          double d = 0.0, bj = 0.0, tr = 0.0;
+          int bad = 0;
+          if (lane < m) {
+            const double gg = ytx_cur - Gc, hh = -Hc;
+            bad = !(isfinite(gg) && isfinite(hh));
+            if (okr && !bad) {
+              bj = sbeta[j0 + lane];
+              tr = strust[j0 + lane];
+              const double dv = prior_step(a.prior_kind, a.inv_var, a.lambda, bj, gg, hh);
+              d = fmin(fmax(dv, -tr), tr);
+            }
+          }
+          // a merged pass keeps its second group only if no column of the first
+          // group that shares a patient with it moved; else that group is
+          // visited again, alone, in the next pass (its sums are discarded)
+          const uint32_t cmask = desc_cmask(cur.d);
+          const bool rej = cur.n == 2 && __ballot(lane < ma && d != 0.0 && ((cmask >> lane) & 1u)) != 0ull;
+          const int mc = rej ? ma : m;   // columns whose step is taken
+          if (lane >= mc) {
+            d = 0.0;
+            bad = 0;
+          }
+          if (lane < mc && okr && !bad) {
+            strust[j0 + lane] = fmax(2.0 * fabs(d), 0.5 * tr);
+            const double nb = bj + d;
+            if (!isfinite(nb)) { bad = 1; d = 0.0; }
+            else sbeta[j0 + lane] = nb;
+          }
+          if (lane < kMaxGroup) {
+            const double em1 = expm1(d);
+            s_ed[lane] = 1.0 + em1;
+            s_em1[lane] = em1;
+          }
+          const uint64_t moved = __ballot(lane < mc && d != 0.0);
+          const bool any_bad = __ballot(bad != 0) != 0ull;
+          if (lane == 0) {
+            bci[0] = okr ? 1 : 0;
+            bci[1] = any_bad ? 1 : 0;
+            bci[2] = moved != 0ull ? 1 : 0;
+            bci[3] = rej ? 1 : 0;
+          }
+          mv_cols = okr ? mc : 0;
+          mv_val = (uint32_t)moved;
+          if (rej && lane == 0) ++s_nrej;
+        }
+        __syncthreads();
+  #pragma unroll
+        for (int c = 0; c < kMaxGroup; ++c)
+          if (m - 1 == c) ++gseq[c];
+        if (!bci[0]) { ok = false; break; }
+        if (bci[1]) { status = SCCS_ERR_NUMERIC; ok = false; break; }
+        const bool rejected = __builtin_amdgcn_readfirstlane(bci[3]) != 0;
+        if (worker) {
+          if (bci[2]) {
+            phase_b_cached<WT>(a, cur.p[0], c_cur[0], cf);
+            // a rejected second group is left untouched
+            if (cur.n == 2 && !rejected) phase_b_cached<WT>(a, cur.p[1], c_cur[1], Coef{s_ed + ma, s_em1 + ma});
+          }
+        } else {
+          // while the workers update: record which columns moved (no pass
+          // reads these bits before the next sweep); take the plan of the
+          // pass after next from the workers
+          if (lane == 0 && mv_cols > 0) set_bits(s_mv, j0, mv_cols, mv_val);
+          nn.n = (int)__builtin_amdgcn_readfirstlane(s_nn[0]);
+          nn.d = __builtin_amdgcn_readfirstlane(s_nn[1]);
+        }
+        __syncthreads();
+        par ^= 1;
+        if (rejected) {
+          // the second group alone, from fresh data; nxt and the passes after
+          // it stay as planned (their speculative gathers are repeated)
+          cur.s += 1;
+          cur.n = 1;
+          cur.d = (uint32_t)(j0 + ma) | ((uint32_t)desc_mnext(cur.d) << 13) | (7u << 16);
+          cur.p[0] = cur.p[1];
+          c_cur[0].valid = false;
+        } else {
+          cur = nxt;
+          c_cur[0] = c_nxt[0];
+          c_cur[1] = c_nxt[1];
+          nxt = nn;
+          d_nn = d_nnn;
+          if (nxt.n == 0) nxt.s = NG;
+        }
+      }
     } else {
-      nxt.s = NG;
-    }
-    uint32_t d_nn = 0u;   // descriptor of the pass after nxt
-    if (nxt.n > 0 && nxt.s + nxt.n < NG) d_nn = ld_idx(a.gdesc + nxt.s + nxt.n);
-    Cache c_cur[2], c_nxt[2];
-    c_cur[0].valid = c_cur[1].valid = false;
-    c_nxt[0].valid = c_nxt[1].valid = false;
-    int par = 0;
-    int mv_cols = 0;        // poller: columns whose moved bits this pass sets
-    uint32_t mv_val = 0u;
-    while (cur.s < NG) {
-      unsigned* bits_cur = par ? bits1 : bits0;
-      unsigned* bits_prev = par ? bits0 : bits1;
-      // the pass after next: the tile ranges of the two groups it may hold
-      // are loaded now; it is planned later, in the shadow of the reduction
-      // (its descriptor was loaded one pass ago; reading it here would wait
-      // for the previous pass's stores as well)
-      Pass nn;
-      nn.s = nxt.s + nxt.n;
-      nn.n = 0;
-      nn.d = 0u;
-      const bool nn_live = nxt.n > 0 && nn.s < NG;
-      int nr0[2] = {0, 0}, nr1[2] = {0, 0};
-      uint32_t d_nnn = 0u;
-      if (nn_live) {
-        pf_range(a, nn.s, nr0[0], nr1[0]);
-        if (nn.s + 1 < NG) pf_range(a, nn.s + 1, nr0[1], nr1[1]);
+      // one pass per column group (no zero steps to exploit, or merging off)
+      // pipeline start: indices of groups 0 and 1; nothing speculated
+      Pf pf_cur, pf_next;
+      {
+        int t0, t1;
+        pf_range(a, 0, t0, t1);
+        pf_tile(a, t0, t1, pf_cur);
+        pf_range(a, NG > 1 ? 1 : 0, t0, t1);
+        pf_tile(a, t0, t1, pf_next);
       }
-      const int j0 = desc_j0(cur.d);
-      const int ma = desc_m(cur.d);                              // columns of the pass's first group
-      const int m = ma + (cur.n == 2 ? desc_mnext(cur.d) : 0);   // columns of the pass
-      const double ytx_cur = (wave == kPoller && lane < m) ? a.ytx[j0 + lane] : 0.0;
-
-      // phase A: validate the speculative first tiles, then accumulate
-      Acc<kMaxGroup> acc;
-      acc.zero();
-      if (worker) {
-        if (!c_cur[0].valid || first_tile_stale(cur.p[0], bits_prev, p0)) gather_first<WT>(a, cur.p[0], c_cur[0]);
-        phase_a_cached<WT>(a, cur.p[0], c_cur[0], acc, bits_cur, p0, 0u);
-        if (cur.n == 2) {
-          if (!c_cur[1].valid || first_tile_stale(cur.p[1], bits_prev, p0)) gather_first<WT>(a, cur.p[1], c_cur[1]);
-          phase_a_cached<WT>(a, cur.p[1], c_cur[1], acc, bits_cur, p0, (uint32_t)ma);
-        }
-      }
-      double loc[2 * kMaxGroup], part[2 * kMaxGroup];
-#pragma unroll
-      for (int i = 0; i < kMaxGroup; ++i) {
-        loc[2 * i] = acc.g[i];
-        loc[2 * i + 1] = acc.h[i];
-        part[2 * i] = part[2 * i + 1] = 0.0;
-      }
-      switch (m) {   // sum only the words of the pass's columns (m is uniform)
-        case 1: block_sum_to<2>(loc, part, redg, kPoller); break;
-#if SCCS_MAX_GROUP >= 2
-        case 2: block_sum_to<4>(loc, part, redg, kPoller); break;
-#endif
-        default: block_sum_to<2 * kMaxGroup>(loc, part, redg, kPoller); break;
-      }
-      if (worker) {
-        // in the shadow of the reduction: clear the other bitmap, gather the
-        // next pass speculatively, load the tile indices of the pass after it
-        for (int i = tid; i < a.nbits; i += kWorkers * 64) bits_prev[i] = 0u;
-        if (nxt.n > 0) gather_first<WT>(a, nxt.p[0], c_nxt[0]);
-        if (nxt.n == 2) gather_first<WT>(a, nxt.p[1], c_nxt[1]);
-        if (nn_live) {
-          nn.d = __builtin_amdgcn_readfirstlane(d_nn);
-          nn.n = plan_pass(nn.d, s_mv, a.merge);
-          if (nn.s + nn.n < NG) d_nnn = ld_idx(a.gdesc + nn.s + nn.n);
-          pf_tile(a, nr0[0], nr1[0], nn.p[0]);
-          if (nn.n == 2) pf_tile(a, nr0[1], nr1[1], nn.p[1]);
-        }
-      } else {
-        // device-wide reduction of the pass's 2m partials, then one Newton /
-        // trust-region step (Eq. 4) per column, lane c for column j0 + c
-        double tot[2 * kMaxGroup];
-        const int cls = m - 1;
-        uint32_t sq = gseq[0];
-#pragma unroll
-        for (int c = 1; c < kMaxGroup; ++c)
-          if (cls == c) sq = gseq[c];
-        uint64_t* s1 = a.slots + cls * kSlots1PerClass;
-        uint64_t* s2 = a.slots2 + cls * kSlots2PerClass;
-#pragma unroll
-        for (int i = 0; i < 2 * kMaxGroup; ++i) tot[i] = 0.0;
-        bool okr;
-        switch (m) {   // one width per slot class, fixed at compile time
-          case 1: okr = allreduce2_wave<2>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
-#if SCCS_MAX_GROUP >= 2
-          case 2: okr = allreduce2_wave<4>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
-#endif
-#if SCCS_MAX_GROUP >= 3
-          case 3: okr = allreduce2_wave<6>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
-#endif
-          default: okr = allreduce2_wave<2 * kMaxGroup>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
-        }
-
-        double Gc = 0.0, Hc = 0.0;
-#pragma unroll
-        for (int i = 0; i < kMaxGroup; ++i)
-          if (lane == i) {
-            Gc = tot[2 * i];
-            Hc = tot[2 * i + 1];
-          }
-        double d = 0.0, bj = 0.0, tr = 0.0;
-        int bad = 0;
-        if (lane < m) {
-          const double gg = ytx_cur - Gc, hh = -Hc;
-          bad = !(isfinite(gg) && isfinite(hh));
-          if (okr && !bad) {
-            bj = sbeta[j0 + lane];
-            tr = strust[j0 + lane];
-            const double dv = prior_step(a.prior_kind, a.inv_var, a.lambda, bj, gg, hh);
-            d = fmin(fmax(dv, -tr), tr);
-          }
-        }
-        // a merged pass keeps its second group only if no column of the first
-        // group that shares a patient with it moved; else that group is
-        // visited again, alone, in the next pass (its sums are discarded)
-        const uint32_t cmask = desc_cmask(cur.d);
-        const bool rej = cur.n == 2 && __ballot(lane < ma && d != 0.0 && ((cmask >> lane) & 1u)) != 0ull;
-        const int mc = rej ? ma : m;   // columns whose step is taken
-        if (lane >= mc) {
-          d = 0.0;
-          bad = 0;
-        }
-        if (lane < mc && okr && !bad) {
-          strust[j0 + lane] = fmax(2.0 * fabs(d), 0.5 * tr);
-          const double nb = bj + d;
-          if (!isfinite(nb)) { bad = 1; d = 0.0; }
-          else sbeta[j0 + lane] = nb;
-        }
-        if (lane < kMaxGroup) {
-          const double em1 = expm1(d);
-          s_ed[lane] = 1.0 + em1;
-          s_em1[lane] = em1;
-        }
-        const uint64_t moved = __ballot(lane < mc && d != 0.0);
-        const bool any_bad = __ballot(bad != 0) != 0ull;
-        if (lane == 0) {
-          bci[0] = okr ? 1 : 0;
-          bci[1] = any_bad ? 1 : 0;
-          bci[2] = moved != 0ull ? 1 : 0;
-          bci[3] = rej ? 1 : 0;
-        }
-        mv_cols = okr ? mc : 0;
-        mv_val = (uint32_t)moved;
-      }
+      Cache c_cur, c_next;
+      c_cur.valid = false;
+      // group bounds gcol[g], gcol[g+1], gcol[g+2] roll through registers, each
+      // loaded two groups before it is needed
+      int j0 = a.gcol[0], gc1 = a.gcol[1], gc2 = NG > 1 ? a.gcol[2] : gc1;
+      int m = gc1 - j0;
+      double ytx_cur = (wave == kPoller && lane < m) ? a.ytx[j0 + lane] : 0.0;
       __syncthreads();
-#pragma unroll
-      for (int c = 0; c < kMaxGroup; ++c)
-        if (m - 1 == c) ++gseq[c];
-      if (!bci[0]) { ok = false; break; }
-      if (bci[1]) { status = SCCS_ERR_NUMERIC; ok = false; break; }
-      const bool rejected = bci[3] != 0;
-      if (worker) {
-        if (bci[2]) {
-          phase_b_cached<WT>(a, cur.p[0], c_cur[0], cf);
-          // a rejected second group is left untouched
-          if (cur.n == 2 && !rejected) phase_b_cached<WT>(a, cur.p[1], c_cur[1], Coef{s_ed + ma, s_em1 + ma});
+      for (int g = 0; g < NG; ++g) {
+        unsigned* bits_cur = (g & 1) ? bits1 : bits0;
+        unsigned* bits_prev = (g & 1) ? bits0 : bits1;
+        const bool has_next = g + 1 < NG;
+        int nt0 = 0, nt1 = 0;
+        if (g + 2 < NG) pf_range(a, g + 2, nt0, nt1);
+        const int gc3 = g + 3 <= NG ? ld_idx(a.gcol + g + 3) : gc2;
+        const int j0n = gc1;
+        const int mn = has_next ? gc2 - gc1 : 0;
+        const double ytx_next = (wave == kPoller && lane < mn) ? a.ytx[j0n + lane] : 0.0;
+
+        // phase A: validate the speculative first tile, then accumulate
+        Acc<kMaxGroup> acc;
+        acc.zero();
+        if (worker) {
+          if (!c_cur.valid || (g > 0 && first_tile_stale(pf_cur, bits_prev, p0))) gather_first<WT>(a, pf_cur, c_cur);
+          phase_a_cached<WT>(a, pf_cur, c_cur, acc, bits_cur, p0, 0u);
         }
-      } else {
-        // while the workers update: record which columns moved (no pass
-        // reads these bits before the next sweep), and plan the pass after
-        // next as the workers did (same bits, same answer)
-        if (lane == 0 && mv_cols > 0) set_bits(s_mv, j0, mv_cols, mv_val);
-        if (nn_live) {
-          nn.d = __builtin_amdgcn_readfirstlane(d_nn);
-          nn.n = plan_pass(nn.d, s_mv, a.merge);
-          if (nn.s + nn.n < NG) d_nnn = ld_idx(a.gdesc + nn.s + nn.n);
+        double loc[2 * kMaxGroup], part[2 * kMaxGroup];
+  #pragma unroll
+        for (int i = 0; i < kMaxGroup; ++i) {
+          loc[2 * i] = acc.g[i];
+          loc[2 * i + 1] = acc.h[i];
+          part[2 * i] = part[2 * i + 1] = 0.0;
         }
-      }
-      __syncthreads();
-      ++n_passes;
-      par ^= 1;
-      if (rejected) {
-        // the second group alone, from fresh data; nxt and the passes after
-        // it stay as planned (their speculative gathers are repeated)
-        ++n_rejects;
-        cur.s += 1;
-        cur.n = 1;
-        cur.d = (uint32_t)(j0 + ma) | ((uint32_t)desc_mnext(cur.d) << 13) | (7u << 16);
-        cur.p[0] = cur.p[1];
-        c_cur[0].valid = false;
-      } else {
-        cur = nxt;
-        c_cur[0] = c_nxt[0];
-        c_cur[1] = c_nxt[1];
-        nxt = nn;
-        d_nn = d_nnn;
-        if (nxt.n == 0) nxt.s = NG;
+        switch (m) {   // sum only the words of the group's columns (m is uniform)
+          case 1: block_sum_to<2>(loc, part, redg, kPoller); break;
+  #if SCCS_MAX_GROUP >= 2
+          case 2: block_sum_to<4>(loc, part, redg, kPoller); break;
+  #endif
+          default: block_sum_to<2 * kMaxGroup>(loc, part, redg, kPoller); break;
+        }
+        Pf pf_next2;
+        pf_next2.t = pf_next2.t1 = 0;
+        c_next.valid = false;
+        if (worker) {
+          // in the shadow of the reduction: clear the bitmap of group g+1,
+          // gather group g+1 speculatively, load indices of group g+2
+          unsigned* bits_next = bits_prev;
+          for (int i = tid; i < a.nbits; i += kWorkers * 64) bits_next[i] = 0u;
+          if (has_next) gather_first<WT>(a, pf_next, c_next);
+          if (g + 2 < NG) pf_tile(a, nt0, nt1, pf_next2);
+        } else {
+          // device-wide reduction of the group's 2m partials, then one
+          // Newton / trust-region step (Eq. 4) per column, lane c for column
+          // j0 + c (the columns are independent)
+          double tot[2 * kMaxGroup];
+          const int cls = m - 1;
+          uint32_t sq = gseq[0];
+  #pragma unroll
+          for (int c = 1; c < kMaxGroup; ++c)
+            if (cls == c) sq = gseq[c];
+          uint64_t* s1 = a.slots + cls * kSlots1PerClass;
+          uint64_t* s2 = a.slots2 + cls * kSlots2PerClass;
+  #pragma unroll
+          for (int i = 0; i < 2 * kMaxGroup; ++i) tot[i] = 0.0;
+          bool okr;
+          switch (m) {   // one width per slot class, fixed at compile time
+            case 1: okr = allreduce2_wave<2>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
+  #if SCCS_MAX_GROUP >= 2
+            case 2: okr = allreduce2_wave<4>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
+  #endif
+  #if SCCS_MAX_GROUP >= 3
+            case 3: okr = allreduce2_wave<6>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
+  #endif
+            default: okr = allreduce2_wave<2 * kMaxGroup>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
+          }
+
+          double Gc = 0.0, Hc = 0.0;
+  #pragma unroll
+          for (int i = 0; i < kMaxGroup; ++i)
+            if (lane == i) {
+              Gc = tot[2 * i];
+              Hc = tot[2 * i + 1];
+            }
+          double d = 0.0;
+          int bad = 0;
+          if (lane < m) {
+            const double gg = ytx_cur - Gc, hh = -Hc;
+            bad = !(isfinite(gg) && isfinite(hh));
+            if (okr && !bad) {
+              const int j = j0 + lane;
+              const double bj = sbeta[j], tr = strust[j];
+              const double dv = prior_step(a.prior_kind, a.inv_var, a.lambda, bj, gg, hh);
+              d = fmin(fmax(dv, -tr), tr);
+              strust[j] = fmax(2.0 * fabs(d), 0.5 * tr);
+              const double nb = bj + d;
+              if (!isfinite(nb)) { bad = 1; d = 0.0; }
+              else sbeta[j] = nb;
+            }
+          }
+          if (lane < kMaxGroup) {
+            const double em1 = expm1(d);
+            s_ed[lane] = 1.0 + em1;
+            s_em1[lane] = em1;
+          }
+          const bool any_step = __ballot(d != 0.0) != 0ull;
+          const bool any_bad = __ballot(bad != 0) != 0ull;
+          if (lane == 0) {
+            bci[0] = okr ? 1 : 0;
+            bci[1] = any_bad ? 1 : 0;
+            bci[2] = any_step ? 1 : 0;
+          }
+        }
+        __syncthreads();
+  #pragma unroll
+        for (int c = 0; c < kMaxGroup; ++c)
+          if (m - 1 == c) ++gseq[c];
+        if (!bci[0]) { ok = false; break; }
+        if (bci[1]) { status = SCCS_ERR_NUMERIC; ok = false; break; }
+        if (worker && bci[2]) phase_b_cached<WT>(a, pf_cur, c_cur, cf);
+        __syncthreads();
+        pf_cur = pf_next;
+        pf_next = pf_next2;
+        c_cur = c_next;
+        ytx_cur = ytx_next;
+        j0 = j0n;
+        m = mn;
+        gc1 = gc2;
+        gc2 = gc3;
       }
     }
     if (!ok) break;
@@ -1055,8 +1205,7 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
     }
     for (int i = tid; i < a.mv_words; i += kBlock) a.moved[i] = s_mv[i];
     if (tid == 0) {
-      a.ctrl->passes = n_passes;
-      a.ctrl->rejects = n_rejects;
+      a.ctrl->rejects = s_nrej;
       a.ctrl->sweeps = sweep;
       a.ctrl->converged = converged;
       a.ctrl->loglik = L;
@@ -1170,8 +1319,10 @@ __global__ void k_refresh_bt(KArgs a, const double2* bt) {
   refresh_range<WT>(a, (const double*)bt, 0, a.N, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, 2);
 }
 
-template __global__ void k_ccd<double>(KArgs);
-template __global__ void k_ccd<float>(KArgs);
+template __global__ void k_ccd<double, false>(KArgs);
+template __global__ void k_ccd<double, true>(KArgs);
+template __global__ void k_ccd<float, false>(KArgs);
+template __global__ void k_ccd<float, true>(KArgs);
 template __global__ void k_diag<double>(KArgs);
 template __global__ void k_diag<float>(KArgs);
 template __global__ void k_refresh<double>(KArgs);
