@@ -372,10 +372,12 @@ def main():
                      "kernel": "k_ccd<double>", "kernel_ms_mean": ms,
                      "algo_bytes_per_launch": float(np.mean(fp["bytes"]))},
         # device-wide reductions per sweep (column groups, two merged into one
-        # pass when predicted independent) and merges undone per sweep
-        "schedule": {"passes_per_sweep_mean": float(np.mean([q for q, _ in fp["passes"]])),
+        # pass when predicted independent), merges undone per sweep, and the
+        # share of coordinates whose step was exactly zero
+        "schedule": {"passes_per_sweep_mean": float(np.mean([q[0] for q in fp["passes"]])),
                      "passes_last_sweep": int(fp["passes"][-1][0]),
-                     "rejected_merges_per_sweep_mean": float(np.mean([r for _, r in fp["passes"]]))},
+                     "rejected_merges_per_sweep_mean": float(np.mean([q[1] for q in fp["passes"]])),
+                     "zero_step_share_mean": float(np.mean([q[2] for q in fp["passes"]])) / prob.n_cols},
     }
     if not args.no_mixed:
         mx = run_form(sccs, prob, 1, args.steps, args.warmup, c, p)

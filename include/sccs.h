@@ -112,7 +112,9 @@ typedef struct sccs_options {
                               them through a shared patient took a zero step in its previous
                               visit; the prediction is checked after the step and, where it
                               fails, the second group is visited again on its own, so g_j, h_j
-                              and beta are those of the plain cyclic order; 0 = off.  Default 1. */
+                              and beta are those of the plain cyclic order (bit for bit);
+                              used for launches that follow one where most steps were zero
+                              (see sccs_pass_stats); 0 = off.  Default 1. */
   void* stream;            /* hipStream_t */
 } sccs_options;
 
@@ -189,9 +191,12 @@ sccs_status sccs_last_kernel_ms(sccs_handle* h, double* ms);
 /* Schedule statistics of the most recent sccs_sweep / sccs_fit launch:
  * passes = device-wide coordinate reductions run (one per column group, or
  * per two groups merged as options.merge_passes describes), rejects =
- * merged passes whose second group had to be visited again.  Valid after
- * the call has returned; ERR_STATE before any sweep. */
-sccs_status sccs_pass_stats(sccs_handle* h, int32_t* passes, int32_t* rejects);
+ * merged passes whose second group had to be visited again, zero_steps =
+ * coordinate visits whose step was exactly zero.  Merged passes are used
+ * for a launch when at least half of the previous launch's visits took
+ * zero steps (until that share falls below 35 %).  ERR_STATE before any
+ * sweep. */
+sccs_status sccs_pass_stats(sccs_handle* h, int32_t* passes, int32_t* rejects, int32_t* zero_steps);
 
 /* Autotuner: times candidate schedules -- workgroup counts (all compute
  * units, 3/4, 1/2, 1/4 of them) x tile sizes (16, 32, 64 nonzeros) -- on

@@ -44,8 +44,9 @@ struct sccs_handle {
   Ctrl* h_ctrl = nullptr;  // pinned host mirror of the control block
   uint32_t gseq0[kMaxGroup] = {};  // reduction sequence numbers before the last sweep launch
   int last_mode = -1;              // kind of the last launch
-  int32_t passes = 0, rejects = 0; // schedule statistics of the last sweep launch
+  int32_t passes = 0, rejects = 0, zero_steps = 0;  // schedule statistics of the last sweep launch
   bool swept = false;
+  bool use_merge = false;          // the next sweep launch takes the merged-pass form
 };
 
 static thread_local std::string g_create_error;
@@ -151,9 +152,8 @@ sccs_status pick_workgroups(const sccs_options* o, int32_t& G, std::string& err)
   return SCCS_OK;
 }
 
-// The sweep kernel with merged passes is used where zero steps occur (the
-// Laplace prior); otherwise the one-pass-per-group form, which carries less
-// state per pass.
+// The sweep kernel in its merged-pass form, or in the one-pass-per-group
+// form, which carries less state per pass.
 const void* ccd_kernel(int prec, int mode, bool merge = false) {
   if (mode == kModeSweep) {
     if (merge) return prec == SCCS_PREC_FP64 ? (const void*)k_ccd<double, true> : (const void*)k_ccd<float, true>;
@@ -189,7 +189,17 @@ sccs_status read_ctrl(sccs_handle* h) {
     for (int c = 0; c < kMaxGroup; ++c) n += h->h_ctrl->gseq[c] - h->gseq0[c];
     h->passes = (int32_t)n;
     h->rejects = h->h_ctrl->rejects;
+    h->zero_steps = h->h_ctrl->zero_steps;
     h->swept = true;
+    // Merged passes pay off once many coordinates take exactly zero steps
+    // (coordinates held at zero by the Laplace prior, and converged ones,
+    // whose FP64 step rounds to zero); they cost a little more per pass
+    // otherwise.  The next launch follows this launch's share, with
+    // hysteresis.
+    const double visits = (double)h->J * (h->h_ctrl->sweeps > 0 ? h->h_ctrl->sweeps : 1);
+    const double zf = h->zero_steps / visits;
+    if (!h->use_merge && zf >= 0.5) h->use_merge = true;
+    else if (h->use_merge && zf < 0.35) h->use_merge = false;
   }
   if (h->h_ctrl->status == SCCS_ERR_SYNC) {
     h->failed = true;
@@ -225,7 +235,7 @@ sccs_status launch(sccs_handle* h, int mode, int n_sweeps, int criterion, double
   void* params[] = {&a};
   HIPCHK(h, hipMemsetAsync(&h->args.ctrl->status, 0, sizeof(int32_t), h->stream));
   HIPCHK(h, hipEventRecord(h->ev0, h->stream));
-  const bool merge = a.merge && a.prior_kind == SCCS_PRIOR_LAPLACE;
+  const bool merge = a.merge && h->use_merge;
   if (mode == kModeSweep)   // the mirror holds the state after the previous launch
     for (int c = 0; c < kMaxGroup; ++c) h->gseq0[c] = h->h_ctrl->gseq[c];
   h->last_mode = mode;
@@ -481,6 +491,7 @@ sccs_status sccs_set_beta(sccs_handle* h, const double* beta, const double* trus
   HIPCHK(h, hipMemcpyAsync(h->args.beta, beta, (size_t)h->J * 8, hipMemcpyHostToDevice, h->stream));
   HIPCHK(h, hipMemcpyAsync(h->args.trust, trust, (size_t)h->J * 8, hipMemcpyHostToDevice, h->stream));
   if (refresh_all(h) != SCCS_OK) return SCCS_ERR_HIP;
+  h->use_merge = false;
   st = reset_moved(h);
   if (st) return st;
   HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -563,11 +574,12 @@ sccs_status sccs_objective(sccs_handle* h, double* loglik, double* logpost) {
   return SCCS_OK;
 }
 
-sccs_status sccs_pass_stats(sccs_handle* h, int32_t* passes, int32_t* rejects) {
-  if (!h || !passes || !rejects) return SCCS_ERR_INVALID_ARG;
+sccs_status sccs_pass_stats(sccs_handle* h, int32_t* passes, int32_t* rejects, int32_t* zero_steps) {
+  if (!h || !passes || !rejects || !zero_steps) return SCCS_ERR_INVALID_ARG;
   if (!h->swept) { h->err = "no sweep run yet"; return SCCS_ERR_STATE; }
   *passes = h->passes;
   *rejects = h->rejects;
+  *zero_steps = h->zero_steps;
   return SCCS_OK;
 }
 

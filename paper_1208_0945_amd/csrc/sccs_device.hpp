@@ -44,7 +44,7 @@ struct Ctrl {
   double g, h;         // diagnostic output
   uint32_t gseq[kMaxGroup];  // single fit: sequence number of each reduction class
   int32_t rejects;     // single fit, last launch: merged passes whose second group was visited again
-  int32_t pad2;
+  int32_t zero_steps;  //   coordinate visits whose step was exactly zero
 };
 
 struct KArgs {

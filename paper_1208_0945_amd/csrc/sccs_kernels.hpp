@@ -813,8 +813,9 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
   uint32_t* s_mv = bits1 + a.nbits;                   // moved-column bits (identical in every workgroup)
   for (int i = tid; i < a.mv_words; i += kBlock) s_mv[i] = a.moved[i];
   __shared__ uint32_t s_nn[2];   // merged passes: the pass after next (groups, descriptor), for the poller
-  __shared__ int s_nrej;         // merged passes: rejected merges in this launch
-  if (tid == 0) s_nrej = 0;
+  // poller lane 0: rejected merges and coordinate visits with an exactly
+  // zero step in this launch
+  int n_rej = 0, n_zero = 0;
   const Coef cf{s_ed, s_em1};
   __syncthreads();
   while (ok && sweep < a.n_sweeps) {
@@ -881,7 +882,7 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
           }
         }
         double loc[2 * kMaxGroup], part[2 * kMaxGroup];
-  #pragma unroll
+#pragma unroll
         for (int i = 0; i < kMaxGroup; ++i) {
           loc[2 * i] = acc.g[i];
           loc[2 * i + 1] = acc.h[i];
@@ -921,12 +922,12 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
           double tot[2 * kMaxGroup];
           const int cls = m - 1;
           uint32_t sq = gseq[0];
-  #pragma unroll
+#pragma unroll
           for (int c = 1; c < kMaxGroup; ++c)
             if (cls == c) sq = gseq[c];
           uint64_t* s1 = a.slots + cls * kSlots1PerClass;
           uint64_t* s2 = a.slots2 + cls * kSlots2PerClass;
-  #pragma unroll
+#pragma unroll
           for (int i = 0; i < 2 * kMaxGroup; ++i) tot[i] = 0.0;
           bool okr;
           switch (m) {   // one width per slot class, fixed at compile time
@@ -941,7 +942,7 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
           }
 
           double Gc = 0.0, Hc = 0.0;
-  #pragma unroll
+#pragma unroll
           for (int i = 0; i < kMaxGroup; ++i)
             if (lane == i) {
               Gc = tot[2 * i];
@@ -990,10 +991,11 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
           }
           mv_cols = okr ? mc : 0;
           mv_val = (uint32_t)moved;
-          if (rej && lane == 0) ++s_nrej;
+          n_rej += rej ? 1 : 0;
+          n_zero += mv_cols - __popcll(moved);
         }
         __syncthreads();
-  #pragma unroll
+#pragma unroll
         for (int c = 0; c < kMaxGroup; ++c)
           if (m - 1 == c) ++gseq[c];
         if (!bci[0]) { ok = false; break; }
@@ -1033,7 +1035,9 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
         }
       }
     } else {
-      // one pass per column group (no zero steps to exploit, or merging off)
+      // one pass per column group (few zero steps to exploit, or merging
+      // off); the moved bits are left as they are (the first merged sweep
+      // brings them up to date)
       // pipeline start: indices of groups 0 and 1; nothing speculated
       Pf pf_cur, pf_next;
       {
@@ -1070,7 +1074,7 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
           phase_a_cached<WT>(a, pf_cur, c_cur, acc, bits_cur, p0, 0u);
         }
         double loc[2 * kMaxGroup], part[2 * kMaxGroup];
-  #pragma unroll
+#pragma unroll
         for (int i = 0; i < kMaxGroup; ++i) {
           loc[2 * i] = acc.g[i];
           loc[2 * i + 1] = acc.h[i];
@@ -1100,12 +1104,12 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
           double tot[2 * kMaxGroup];
           const int cls = m - 1;
           uint32_t sq = gseq[0];
-  #pragma unroll
+#pragma unroll
           for (int c = 1; c < kMaxGroup; ++c)
             if (cls == c) sq = gseq[c];
           uint64_t* s1 = a.slots + cls * kSlots1PerClass;
           uint64_t* s2 = a.slots2 + cls * kSlots2PerClass;
-  #pragma unroll
+#pragma unroll
           for (int i = 0; i < 2 * kMaxGroup; ++i) tot[i] = 0.0;
           bool okr;
           switch (m) {   // one width per slot class, fixed at compile time
@@ -1120,7 +1124,7 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
           }
 
           double Gc = 0.0, Hc = 0.0;
-  #pragma unroll
+#pragma unroll
           for (int i = 0; i < kMaxGroup; ++i)
             if (lane == i) {
               Gc = tot[2 * i];
@@ -1147,16 +1151,17 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
             s_ed[lane] = 1.0 + em1;
             s_em1[lane] = em1;
           }
-          const bool any_step = __ballot(d != 0.0) != 0ull;
+          const uint64_t moved = __ballot(lane < m && d != 0.0);
           const bool any_bad = __ballot(bad != 0) != 0ull;
           if (lane == 0) {
             bci[0] = okr ? 1 : 0;
             bci[1] = any_bad ? 1 : 0;
-            bci[2] = any_step ? 1 : 0;
+            bci[2] = moved != 0ull ? 1 : 0;
           }
+          n_zero += okr ? m - __popcll(moved) : 0;
         }
         __syncthreads();
-  #pragma unroll
+#pragma unroll
         for (int c = 0; c < kMaxGroup; ++c)
           if (m - 1 == c) ++gseq[c];
         if (!bci[0]) { ok = false; break; }
@@ -1204,8 +1209,12 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
       a.trust[j] = strust[j];
     }
     for (int i = tid; i < a.mv_words; i += kBlock) a.moved[i] = s_mv[i];
+    if (tid == kPoller * 64) {
+      a.ctrl->rejects = n_rej;
+      a.ctrl->zero_steps = n_zero;
+    }
     if (tid == 0) {
-      a.ctrl->rejects = s_nrej;
+
       a.ctrl->sweeps = sweep;
       a.ctrl->converged = converged;
       a.ctrl->loglik = L;

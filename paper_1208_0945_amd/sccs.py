@@ -114,7 +114,7 @@ def lib() -> ctypes.CDLL:
         L.sccs_objective.argtypes = [H, dp, dp]
         L.sccs_last_kernel_ms.argtypes = [H, dp]
         ip = ctypes.POINTER(ctypes.c_int32)
-        L.sccs_pass_stats.argtypes = [H, ip, ip]
+        L.sccs_pass_stats.argtypes = [H, ip, ip, ip]
         L.sccs_last_error.argtypes = [H]
         L.sccs_last_error.restype = ctypes.c_char_p
         L.sccs_batch_query_workspace.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
@@ -286,11 +286,12 @@ class Handle:
         self._check(lib().sccs_last_kernel_ms(self.h, ctypes.byref(ms)))
         return ms.value
 
-    def pass_stats(self) -> Tuple[int, int]:
-        """(device-wide reductions, rejected merges) of the last sweep/fit launch."""
-        p, r = ctypes.c_int32(), ctypes.c_int32()
-        self._check(lib().sccs_pass_stats(self.h, ctypes.byref(p), ctypes.byref(r)))
-        return p.value, r.value
+    def pass_stats(self) -> Tuple[int, int, int]:
+        """(device-wide reductions, rejected merges, zero-step visits) of the
+        last sweep/fit launch."""
+        p, r, z = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(lib().sccs_pass_stats(self.h, ctypes.byref(p), ctypes.byref(r), ctypes.byref(z)))
+        return p.value, r.value, z.value
 
 
 def tune(prob, prior_kind: int, variance: float, n_sweeps: int = 2, precision: int = PREC_FP64, weight=None):
