@@ -369,7 +369,7 @@ def main():
                    "nnz": prob.nnz, "prior": "laplace", "variance": 2.0, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(ms),
-                     "kernel": "k_ccd<double>", "kernel_ms_mean": ms,
+                     "kernel": "k_ccd<double, *> (one-pass-per-group and merged-pass forms)", "kernel_ms_mean": ms,
                      "algo_bytes_per_launch": float(np.mean(fp["bytes"]))},
         # device-wide reductions per sweep (column groups, two merged into one
         # pass when predicted independent), merges undone per sweep, and the
