@@ -51,6 +51,19 @@ def run_gpu(sccs, prob, kind, var, sweeps, weight=None, precision=0, n_workgroup
         return h.get_beta()
 
 
+def run_gpu_launches(sccs, prob, kind, var, warm, n_single, **kw):
+    """warm sweeps in one launch, then n_single one-sweep launches (so that
+    the merged-pass form can take over); returns beta and pass counts."""
+    with sccs.Handle(prob, **kw) as h:
+        h.set_prior(kind, var)
+        h.sweep(warm)
+        passes = []
+        for _ in range(n_single):
+            h.sweep(1)
+            passes.append(h.pass_stats()[0])
+        return h.get_beta()[0], passes
+
+
 def test_first_coordinates_at_zero_match_oracle(sccs):
     prob = synth.tiny()
     with sccs.Handle(prob) as h:
@@ -137,6 +150,28 @@ def test_zipf_laplace_20_sweeps(sccs, n_workgroups, tile_nnz, max_group):
     assert np.array_equal(beta == 0.0, ref["beta"] == 0.0)
 
 
+@pytest.mark.parametrize("n_workgroups,tile_nnz,max_group",
+                         [(1, 0, 0), (3, 0, 0), (64, 0, 0), (0, 0, 0), (0, 16, 0), (97, 32, 0), (0, 0, 1), (5, 0, 2)])
+def test_zipf_laplace_merged_form(sccs, n_workgroups, tile_nnz, max_group):
+    """The same shapes with single-sweep launches after a warm-up launch, so
+    that the merged-pass form takes over once most steps are zero (Laplace
+    lambda = 2): beta after 40 sweeps against the oracle's."""
+    prob = zipf_small()
+    ref = oracle.ccd(prob, 2, 0.5, 40)
+    with sccs.Handle(prob, n_workgroups=n_workgroups, tile_nnz=tile_nnz, max_group=max_group) as h:
+        h.set_prior(2, 0.5)
+        h.sweep(10)
+        passes = [h.pass_stats()[0]]
+        for _ in range(30):
+            h.sweep(1)
+            passes.append(h.pass_stats()[0])
+        beta, _ = h.get_beta()
+    print("passes per launch:", passes)
+    assert min(passes[1:]) < passes[0] // 10, "the merged form should have taken over"
+    assert rel_inf(beta, ref["beta"]) <= FP64_TOL
+    assert np.array_equal(beta == 0.0, ref["beta"] == 0.0)
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_merged_passes_match_plain_order(sccs, precision):
     """Merged passes (two column groups in one reduction when the columns
@@ -210,6 +245,12 @@ def test_ragged_and_long_segments(sccs, kind, var, n_workgroups):
     beta, _ = run_gpu(sccs, prob, kind, var, 10, n_workgroups=n_workgroups)
     assert rel_inf(beta, ref["beta"]) <= FP64_TOL
     assert beta[1] == 0.0  # empty column never moves
+    # the same with one-sweep launches from sweep 5 on (merged passes once
+    # most steps are zero)
+    ref = oracle.ccd(prob, kind, var, 30)
+    beta, passes = run_gpu_launches(sccs, prob, kind, var, 5, 25, n_workgroups=n_workgroups)
+    assert rel_inf(beta, ref["beta"]) <= FP64_TOL
+    assert beta[1] == 0.0
 
 
 @pytest.mark.parametrize("mode", ["cv", "bootstrap"])
@@ -332,11 +373,16 @@ def test_no_nonzeros_and_single_patient(sccs):
     for kind in (1, 2):
         beta, _ = run_gpu(sccs, empty, kind, 1.0, 3)
         assert np.all(beta == 0.0)
+        beta, _ = run_gpu_launches(sccs, empty, kind, 1.0, 1, 3)   # all steps zero: merged form
+        assert np.all(beta == 0.0)
     one = synth.Problem("one", 1, np.array([0, 4], np.int64), np.array([10, 20, 30, 40], np.int32),
                         np.array([1, 0, 2, 1], np.int32), 2, np.array([0, 2, 3], np.int64),
                         np.array([0, 2, 1], np.int32), np.zeros(2))
     ref = oracle.ccd(one, 1, 1.0, 5)
     beta, _ = run_gpu(sccs, one, 1, 1.0, 5)
+    assert rel_inf(beta, ref["beta"]) <= FP64_TOL
+    ref = oracle.ccd(one, 2, 1.0, 60)
+    beta, _ = run_gpu_launches(sccs, one, 2, 1.0, 20, 40)
     assert rel_inf(beta, ref["beta"]) <= FP64_TOL
 
 
