@@ -106,7 +106,8 @@ typedef struct sccs_options {
                               reduction, up to max_group columns at a time (results equal
                               those of visiting them one by one, up to summation order);
                               0 = 4, else 1..4 (1 = one column per reduction).  The batched
-                              form always visits one column at a time. */
+                              form groups columns only when all its fits share one problem,
+                              with at most 64 / n_fits columns per group. */
   int32_t merge_passes;    /* single fit: 1 = let the next group share the current group's
                               reduction (up to max_group columns) when every column that links
                               them through a shared patient took a zero step in its previous

@@ -2,11 +2,15 @@
 // folds) advanced in lockstep by one cooperative persistent launch.
 //
 // All fits share the coordinate order j = 0..J-1 and the workgroup count G;
-// workgroup b owns patient range b of every fit's problem.  Per coordinate,
-// every workgroup computes its partial (G_f, H_f) for each active fit, ONE
-// device-wide reduction carries all 2F partials (so its latency is paid once
-// for all fits), then each fit takes its own Newton / trust-region step
-// (Eq. 4) and its own sparse update.  Each fit walks a chain of priors in
+// workgroup b owns patient range b of every fit's problem.  When all fits
+// share one problem (cross-validation folds, bootstrap replicates) they also
+// share its column groups (consecutive, pairwise patient-disjoint columns,
+// up to m columns with F m <= 64); otherwise every group is one column.  Per
+// group, every workgroup computes its partials (G_fc, H_fc) for each active
+// fit and column, ONE device-wide reduction carries all 2 F m partials (so
+// its latency is paid once for all fits and columns), then each (fit,
+// column) takes its own Newton / trust-region step (Eq. 4) and its own
+// sparse update.  Each fit walks a chain of priors in
 // order -- the warm starts along the prior-variance path used for
 // cross-validation (Section 2.5) -- with its trust region reset at the start
 // of every link; a link ends when its stopping rule holds or after
@@ -21,7 +25,15 @@
 namespace sccs {
 
 constexpr int kMaxFits = 64;
-constexpr int kBatchSlotWords = 2 * kMaxFits;   // 2F words per workgroup slot
+constexpr int kBatchSlotWords = 2 * kMaxFits;   // 2 F m words per workgroup slot (F m <= 64)
+// Slots of one class (group width m), both parities: level 1 and level 2.
+constexpr size_t kBatchSlots1 = (size_t)2 * kMaxWorkgroups * kBatchSlotWords;
+constexpr size_t kBatchSlots2 = (size_t)2 * kReplicas * kGroups * kBatchSlotWords;
+
+// Fit of poller lane f m + c (m = 1..4, no general division).
+__device__ __forceinline__ int fit_of(int lane, int m) {
+  return m == 1 ? lane : m == 2 ? lane >> 1 : m == 4 ? lane >> 2 : lane / 3;
+}
 
 struct LinkResult {
   int32_t sweeps;
@@ -47,8 +59,10 @@ struct BatchFit {
 
 struct BatchArgs {
   const BatchFit* fits;
-  uint64_t* s1;              // [2][256][kBatchSlotWords]
-  uint64_t* s2;              // [2][kReplicas][8][kBatchSlotWords]
+  uint64_t* s1;              // [kMaxGroup classes][2][256][kBatchSlotWords]
+  uint64_t* s2;              // [kMaxGroup classes][2][kReplicas][8][kBatchSlotWords]
+  const int32_t* gcol;       // [n_groups + 1] column groups, shared by all fits (one problem, or width 1)
+  int32_t n_groups;
   Ctrl* ctrl;
   int32_t F, G, J;
   int32_t max_sweeps;        // per link
@@ -331,10 +345,6 @@ __device__ __forceinline__ void pair_index(const BatchArgs& A, const WaveMap& wm
   }
 }
 
-// Phase A over this wave's pairs: the first tiles of a chunk of pairs are
-// gathered together from the staged indices, then any further tiles of the
-// pair's range (large columns) are walked one by one.  Partials go to
-// pp[f][slice].
 // Fits (bit f) whose range in this workgroup has more tiles than its first,
 // read by lane f from the owner's staged indices (whole fits per wave only).
 __device__ __forceinline__ uint64_t fits_with_more_tiles(const int (*const* all_ixs)[4], int F, const int* s_done) {
@@ -347,15 +357,46 @@ __device__ __forceinline__ uint64_t fits_with_more_tiles(const int (*const* all_
   return __ballot(more);
 }
 
-template <typename WT>
-__device__ __forceinline__ void pairs_phase_a(const BatchArgs& A, const WaveMap& wm, int wave, const int* s_done,
+// Wave sums of the first m columns' (G, H) of acc, added (add) or stored
+// into row[2 (f m + c) + {0, 1}] by lane 0.  Column widths are unrolled
+// with compile-time indices.  NC: columns per group at most (1 or
+// kMaxGroup; the kernel is instantiated for both).
+template <int NC>
+__device__ __forceinline__ void put_pair_sums(const Acc<NC>& acc, int m, int f, double* row, bool add) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    if (c < m) {
+      const double Gs = wave_sum(acc.g[c]);
+      const double Hs = wave_sum(acc.h[c]);
+      if (lane == 0) {
+        double* r = row + 2 * (f * m + c);
+        if (add) {
+          r[0] += Gs;
+          r[1] += Hs;
+        } else {
+          r[0] = Gs;
+          r[1] = Hs;
+        }
+      }
+    }
+  }
+}
+
+// Phase A over this wave's pairs for column group (j0 .. j0+m-1): the first
+// tiles of a chunk of pairs are gathered together from the staged indices,
+// then any further tiles of the pair's range (large columns) are walked one
+// by one.  Partials of fit f, column c go to words 2 (f m + c) of the
+// wave's row pp[wave] (whole fits per wave) or of its slice's row.
+template <typename WT, int NC>
+__device__ __forceinline__ void pairs_phase_a(const BatchArgs& A, const WaveMap& wm, int wave, int m, const int* s_done,
                                               const int (*ixs)[4], const uint2 (*ixrp)[64],
-                                              const int (*const* all_ixs)[4], double (*pp)[kBW][2]) {
+                                              const int (*const* all_ixs)[4], double (*pp)[kBatchSlotWords]) {
   const int lane = threadIdx.x & 63, F = A.F;
-  // whole fits per wave: partials of fit f from wave w go to pp[f][w], and
-  // every wave clears its column first; else the slice's own slot
   const int slice = wm.P == 1 ? wave : wm.slice(wave);
-  if (wm.P == 1 && lane < F) pp[lane][wave][0] = pp[lane][wave][1] = 0.0;
+  double* row = pp[slice];
+  if (wm.P == 1)
+    for (int w = lane; w < 2 * F * m; w += 64) row[w] = 0.0;
 #pragma unroll 1
   for (int q0 = 0; q0 < kFitsPerWave; q0 += kChunk) {
     if (pair_fit(wm, wave, q0, F) >= F) break;
@@ -392,14 +433,10 @@ __device__ __forceinline__ void pairs_phase_a(const BatchArgs& A, const WaveMap&
     for (int c = 0; c < kChunk; ++c) {
       const int f = pair_fit(wm, wave, q0 + c, F);
       const double num = seg_sum_v(wv[c], lane, seg_start[c]);
-      double Gl = 0.0, Hl = 0.0;
-      if (lead[c]) accum_patient(num, make_double2(den[c], wn[c]), Gl, Hl);
-      Gl = wave_sum(Gl);
-      Hl = wave_sum(Hl);
-      if (f < F && lane == 0) {
-        pp[f][slice][0] = Gl;
-        pp[f][slice][1] = Hl;
-      }
+      Acc<NC> acc;
+      acc.zero();
+      if (lead[c]) acc.add(col_of(pid[c]), num, make_double2(den[c], wn[c]));
+      if (f < F) put_pair_sums<NC>(acc, m, f, row, false);
     }
   }
   // a long first tile: its owner
@@ -409,22 +446,15 @@ __device__ __forceinline__ void pairs_phase_a(const BatchArgs& A, const WaveMap&
     if (f >= F) break;
     if (s_done[f]) continue;
     const int t0 = ixs[q][0], t1 = ixs[q][1], len0 = ixs[q][3];
-    Acc<1> acc;
+    Acc<NC> acc;
     acc.zero();
     bool any = false;
-    if (t0 < t1 && len0 > 64) { tile_a<WT, 1, false>(A.fits[f].k, t0, acc); any = true; }
+    if (t0 < t1 && len0 > 64) { tile_a<WT, NC, false>(A.fits[f].k, t0, acc); any = true; }
     if (wm.P > 1 && t0 + wm.P < t1) {
-      tiles_a<WT, 1, false>(A.fits[f].k, t0 + wm.P, t1, wm.P, acc);
+      tiles_a<WT, NC, false>(A.fits[f].k, t0 + wm.P, t1, wm.P, acc);
       any = true;
     }
-    if (any) {
-      const double Gl = wave_sum(acc.g[0]);
-      const double Hl = wave_sum(acc.h[0]);
-      if (lane == 0) {
-        pp[f][slice][0] += Gl;
-        pp[f][slice][1] += Hl;
-      }
-    }
+    if (any) put_pair_sums<NC>(acc, m, f, row, true);
   }
   if (wm.P > 1) return;
   // whole fits per wave: the tiles after the first of every fit are spread
@@ -436,67 +466,73 @@ __device__ __forceinline__ void pairs_phase_a(const BatchArgs& A, const WaveMap&
     const int* ix = all_ixs[f % kBW][f / kBW];
     const int start = ix[0] + 1 + rot(wave, f);
     if (start >= ix[1]) continue;
-    Acc<1> acc;
+    Acc<NC> acc;
     acc.zero();
-    tiles_a<WT, 1, false>(A.fits[f].k, start, ix[1], kBW, acc);
-    const double Gl = wave_sum(acc.g[0]);
-    const double Hl = wave_sum(acc.h[0]);
-    if (lane == 0) {
-      pp[f][wave][0] += Gl;
-      pp[f][wave][1] += Hl;
-    }
+    tiles_a<WT, NC, false>(A.fits[f].k, start, ix[1], kBW, acc);
+    put_pair_sums<NC>(acc, m, f, row, true);
   }
 }
 
-// Phase B over this wave's pairs with a nonzero step: the first tiles of a
-// chunk are re-gathered together (the lines are still in L2 from phase A)
-// and updated as tile_b does; further tiles follow one by one.
-template <typename WT>
-__device__ __forceinline__ void pairs_phase_b(const BatchArgs& A, const WaveMap& wm, int wave, const int* s_done,
+// Phase B over this wave's pairs of fits with a nonzero step: the first
+// tiles of a chunk are re-gathered together (the lines are still in L2 from
+// phase A) and updated as tile_b does, column by column (s_ed / s_em1 at
+// f m + c); further tiles follow one by one.
+template <typename WT, int NC>
+__device__ __forceinline__ void pairs_phase_b(const BatchArgs& A, const WaveMap& wm, int wave, int m, const int* s_done,
                                               const int (*ixs)[4], const uint2 (*ixrp)[64],
-                                              const int (*const* all_ixs)[4],
-                                              const double (*dd)[3]) {
+                                              const int (*const* all_ixs)[4], const int* s_fstep,
+                                              const double* s_ed, const double* s_em1) {
   const int lane = threadIdx.x & 63, F = A.F;
 #pragma unroll 1
   for (int q0 = 0; q0 < kFitsPerWave; q0 += kChunk) {
     if (pair_fit(wm, wave, q0, F) >= F) break;
     WT wo[kChunk];
-    double den[kChunk];
-    bool lead[kChunk], live[kChunk];
+    double den[kChunk], ed[kChunk], em1[kChunk];
+    bool lead[kChunk], live[kChunk], upd[kChunk];
     int seg_start[kChunk];
 #pragma unroll
     for (int c = 0; c < kChunk; ++c) {
       const int f = pair_fit(wm, wave, q0 + c, F);
       const int t = ixs[q0 + c][0], t1 = ixs[q0 + c][1], len = ixs[q0 + c][3];
       const uint2 rp = ixrp[q0 + c][lane];
-      live[c] = f < F && !s_done[f] && dd[f][0] != 0.0 && t < t1 && len <= 64;
+      live[c] = f < F && !s_done[f] && s_fstep[f] && t < t1 && len <= 64;
       wo[c] = (WT)0;
       lead[c] = false;
+      upd[c] = false;
       seg_start[c] = lane;
+      ed[c] = 1.0;
+      em1[c] = 0.0;
       if (live[c]) {
         seg_layout(rp.y, lane, len, lead[c], seg_start[c]);
-        if (lane < len) wo[c] = ((const WT*)A.fits[f].k.w)[rp.x];
+        if (lane < len) {
+          const int k = f * m + (NC == 1 ? 0 : (int)col_of(rp.y));
+          ed[c] = s_ed[k];
+          em1[c] = s_em1[k];
+          upd[c] = em1[c] != 0.0;
+          if (upd[c]) wo[c] = ((const WT*)A.fits[f].k.w)[rp.x];
+        }
       }
     }
 #pragma unroll
     for (int c = 0; c < kChunk; ++c) {
       const int f = pair_fit(wm, wave, q0 + c, F);
       den[c] = 0.0;
-      if (lead[c]) den[c] = A.fits[f].k.pat[pid_of(ixrp[q0 + c][lane].y)].x;
+      if (lead[c] && upd[c]) den[c] = A.fits[f].k.pat[pid_of(ixrp[q0 + c][lane].y)].x;
     }
 #pragma unroll
     for (int c = 0; c < kChunk; ++c) {
       if (!live[c]) continue;
       const int f = pair_fit(wm, wave, q0 + c, F);
       const uint2 rp = ixrp[q0 + c][lane];
-      const WT wnew = wo[c] * (WT)dd[f][1];
-      if (lane < ixs[q0 + c][3]) ((WT*)A.fits[f].k.w)[rp.x] = wnew;
+      const WT wnew = wo[c] * (WT)ed[c];
+      if (upd[c]) ((WT*)A.fits[f].k.w)[rp.x] = wnew;
+      // a segment lies in one column, so its lanes agree on upd
       if (sizeof(WT) == 8) {
         const double num = seg_sum_v((double)wo[c], lane, seg_start[c]);
-        if (lead[c]) A.fits[f].k.pat[pid_of(rp.y)].x = den[c] + num * dd[f][2];
+        if (lead[c] && upd[c]) A.fits[f].k.pat[pid_of(rp.y)].x = den[c] + num * em1[c];
       } else {
         const double sdiff = seg_sum_v((double)wnew - (double)wo[c], lane, seg_start[c]);
-        if (lead[c]) A.fits[f].k.pat[pid_of(rp.y)].x = den[c] + sdiff;
+        if (lead[c] && upd[c]) A.fits[f].k.pat[pid_of(rp.y)].x = den[c] + sdiff;
       }
     }
   }
@@ -504,9 +540,9 @@ __device__ __forceinline__ void pairs_phase_b(const BatchArgs& A, const WaveMap&
   for (int q = 0; q < kFitsPerWave; ++q) {
     const int f = pair_fit(wm, wave, q, F);
     if (f >= F) break;
-    if (s_done[f] || dd[f][0] == 0.0) continue;
+    if (s_done[f] || !s_fstep[f]) continue;
     const int t0 = ixs[q][0], t1 = ixs[q][1], len0 = ixs[q][3];
-    const Coef cf{&dd[f][1], &dd[f][2]};
+    const Coef cf{s_ed + f * m, s_em1 + f * m};
     if (t0 < t1 && len0 > 64) tile_b<WT>(A.fits[f].k, t0, cf);
     if (wm.P > 1) tiles_b<WT>(A.fits[f].k, t0 + wm.P, t1, wm.P, cf);
   }
@@ -516,19 +552,21 @@ __device__ __forceinline__ void pairs_phase_b(const BatchArgs& A, const WaveMap&
   while (more) {
     const int f = __builtin_ctzll(more);
     more &= more - 1;
-    if (dd[f][0] == 0.0) continue;
+    if (!s_fstep[f]) continue;
     const int* ix = all_ixs[f % kBW][f / kBW];
     const int start = ix[0] + 1 + rot(wave, f);
-    if (start < ix[1]) tiles_b<WT>(A.fits[f].k, start, ix[1], kBW, Coef{&dd[f][1], &dd[f][2]});
+    if (start < ix[1]) tiles_b<WT>(A.fits[f].k, start, ix[1], kBW, Coef{s_ed + f * m, s_em1 + f * m});
   }
 }
 
-template <typename WT>
+template <typename WT, int NC>
 __global__ void __launch_bounds__(kBlock) k_batch(BatchArgs A) {
   __shared__ double stage[32 * kBatchSlotWords];
-  __shared__ double pp[kMaxFits][kBW][2];         // per (fit, worker or slice) partials
+  __shared__ double pp[kBW][kBatchSlotWords];     // per worker or slice: word 2 (f m + c) + {0, 1}
   __shared__ double part[kBatchSlotWords], tot[kBatchSlotWords];
-  __shared__ double dd[kMaxFits][3];              // d, e^d, e^d - 1
+  __shared__ double s_ed[kMaxFits], s_em1[kMaxFits];   // e^d, e^d - 1 of (fit f, column c) at f m + c
+  __shared__ int s_fstep[kMaxFits];                    // fit f took a nonzero step in this group
+  __shared__ int s_gcol[kMaxJ + 1];                    // column groups (shared by all fits)
   __shared__ double lp_prev[kMaxFits], s_var[kMaxFits], s_lam[kMaxFits], s_ivar[kMaxFits];
   __shared__ int s_link[kMaxFits], s_sw[kMaxFits], s_kind[kMaxFits], s_done[kMaxFits];
   __shared__ int flag, bad_any, n_active, since_refresh;
@@ -540,7 +578,13 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchArgs A) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int F = A.F, G = A.G, J = A.J;
   const WaveMap wm(F);
-  uint32_t seq = A.ctrl->seq;
+  // one sequence per slot class (group width m: 2 F m words); the objective
+  // and held-out reductions use class 0 (2 F words)
+  uint32_t gseq[kMaxGroup];
+#pragma unroll
+  for (int c = 0; c < kMaxGroup; ++c) gseq[c] = A.ctrl->gseq[c];
+  for (int i = tid; i <= A.n_groups; i += kBlock) s_gcol[i] = A.gcol[i];
+  const int NG = A.n_groups;
 
   auto set_link = [&](int f) {  // thread-local helper: prior of fit f's current link
     const BatchFit& bf = A.fits[f];
@@ -595,7 +639,7 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchArgs A) {
       }
     }
     __syncthreads();
-    bool okr = batch_allreduce(A.s1, A.s2, seq++, G, 2 * F, A.ctrl, part, tot, stage, &flag);
+    bool okr = batch_allreduce(A.s1, A.s2, gseq[0]++, G, 2 * F, A.ctrl, part, tot, stage, &flag);
     if (tid < F) {
       double L = Lout[tid] - (tot[2 * tid] - tot[2 * tid + 1]);
       Lout[tid] = L;
@@ -636,7 +680,7 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchArgs A) {
       }
     }
     __syncthreads();
-    bool okr = batch_allreduce(A.s1, A.s2, seq++, G, 2 * F, A.ctrl, part, tot, stage, &flag);
+    bool okr = batch_allreduce(A.s1, A.s2, gseq[0]++, G, 2 * F, A.ctrl, part, tot, stage, &flag);
     if (okr && b == 0 && tid < F && s_adv[tid] && A.fits[tid].ho_n)
       A.fits[tid].res_out[s_link[tid]].heldout = s_ho[tid] - (tot[2 * tid] - tot[2 * tid + 1]);
     __syncthreads();
@@ -663,76 +707,92 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchArgs A) {
     const bool worker = wave < kBW;
     if (worker) pair_index(A, wm, wave, 0, s_done, s_ixs[0][wave], s_ixrp[0][wave]);
     __syncthreads();   // every worker's staged indices, read across waves in phase A
-    // poller lane f < F: fit f's (beta_j, trust_j) and Y'X_j for the next step
+    // poller lane f m + c: (beta_j, trust_j) and Y'X_j of fit f, column j0 + c
+    // of the next group, prefetched
     double2 bt_next = make_double2(0.0, 0.0);
     double ytx_next = 0.0;
-    for (int j = 0; j < J && ok; ++j) {
-      const int cur = j & 1;
+    for (int g = 0; g < NG && ok; ++g) {
+      const int cur = g & 1;
+      const int j0 = s_gcol[g], m = s_gcol[g + 1] - j0;
       const int(*all_ixs[kBW])[4];
 #pragma unroll
       for (int w = 0; w < kBW; ++w) all_ixs[w] = s_ixs[cur][w];
-      if (worker) pairs_phase_a<WT>(A, wm, wave, s_done, s_ixs[cur][wave], s_ixrp[cur][wave], all_ixs, pp);
+      if (worker) pairs_phase_a<WT, NC>(A, wm, wave, m, s_done, s_ixs[cur][wave], s_ixrp[cur][wave], all_ixs, pp);
       __syncthreads();
       if (worker) {
-        // index data of the next coordinate (static), in the shadow of the reduction
-        if (j + 1 < J) pair_index(A, wm, wave, j + 1, s_done, s_ixs[cur ^ 1][wave], s_ixrp[cur ^ 1][wave]);
+        // index data of the next group (static), in the shadow of the reduction
+        if (g + 1 < NG) pair_index(A, wm, wave, g + 1, s_done, s_ixs[cur ^ 1][wave], s_ixrp[cur ^ 1][wave]);
       } else {
-        // the poller: each fit's two words summed over its partial slots in
-        // fixed order, the device-wide reduction, then one Newton /
-        // trust-region step per fit (lane f); (beta_j, trust_j) and Y'X_j
-        // come from the previous coordinate's prefetch
+        // the poller: each word summed over the partial rows in fixed order,
+        // the device-wide reduction (slot class m - 1), then one Newton /
+        // trust-region step per (fit, column) on lane f m + c; (beta_j,
+        // trust_j) and Y'X_j come from the previous group's prefetch
         const int lane = tid & 63;
         const int nslots = wm.P == 1 ? kBW : wm.P;
+        const int W = 2 * F * m, FM = F * m;
         double p0 = 0.0, p1 = 0.0;
-        if (lane < 2 * F)
-          for (int q = 0; q < nslots; ++q) p0 += pp[lane >> 1][q][lane & 1];
-        if (lane + 64 < 2 * F)
-          for (int q = 0; q < nslots; ++q) p1 += pp[(lane + 64) >> 1][q][lane & 1];
-        const bool okr = batch_reduce_poller(A.s1, A.s2, seq, G, 2 * F, A.ctrl, &p0, &p1, tot, stage);
+        if (lane < W)
+          for (int q = 0; q < nslots; ++q) p0 += pp[q][lane];
+        if (lane + 64 < W)
+          for (int q = 0; q < nslots; ++q) p1 += pp[q][lane + 64];
+        const int cls = m - 1;
+        uint32_t sq = gseq[0];
+#pragma unroll
+        for (int c = 1; c < kMaxGroup; ++c)
+          if (cls == c) sq = gseq[c];
+        const bool okr = batch_reduce_poller(A.s1 + (size_t)cls * kBatchSlots1, A.s2 + (size_t)cls * kBatchSlots2, sq,
+                                             G, W, A.ctrl, &p0, &p1, tot, stage);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        if (lane < F) {
-          const int f = lane;
-          double d = 0.0;
-          if (!s_done[f] && okr) {
-            const BatchFit& bf = A.fits[f];
-            double2* bt = bf.bt + (size_t)b * J + j;
-            if (j == 0) {
-              bt_next = *bt;
-              ytx_next = bf.k.ytx[0];
-            }
-            const double2 v = bt_next;
-            double g = ytx_next - tot[2 * f], h = -tot[2 * f + 1];
-            if (j + 1 < J) {
-              // the next coordinate's copies: nothing writes them before its step
-              bt_next = bt[1];
-              ytx_next = bf.k.ytx[j + 1];
-            }
-            if (isfinite(g) && isfinite(h)) {
-              double dv = prior_step(s_kind[f], s_ivar[f], s_lam[f], v.x, g, h);
-              d = fmin(fmax(dv, -v.y), v.y);
-              double nb = v.x + d;
-              if (isfinite(nb)) {
-                *bt = make_double2(nb, fmax(2.0 * fabs(d), 0.5 * v.y));
-              } else {
-                d = 0.0;
-                atomicOr(&bad_any, 1);
-              }
+        const int f = lane < FM ? fit_of(lane, m) : 0, c = lane - f * m;
+        double2 v = bt_next;
+        double yv = ytx_next;
+        if (g == 0 && lane < FM) {
+          v = A.fits[f].bt[(size_t)b * J + j0 + c];
+          yv = A.fits[f].k.ytx[j0 + c];
+        }
+        if (g + 1 < NG) {
+          // the next group's copies: nothing writes them before its step
+          const int j0n = s_gcol[g + 1], mn = s_gcol[g + 2] - j0n;
+          if (lane < F * mn) {
+            const int fn = fit_of(lane, mn), cn = lane - fn * mn;
+            bt_next = A.fits[fn].bt[(size_t)b * J + j0n + cn];
+            ytx_next = A.fits[fn].k.ytx[j0n + cn];
+          }
+        }
+        double d = 0.0;
+        if (lane < FM && !s_done[f] && okr) {
+          double gg = yv - tot[2 * lane], hh = -tot[2 * lane + 1];
+          if (isfinite(gg) && isfinite(hh)) {
+            double dv = prior_step(s_kind[f], s_ivar[f], s_lam[f], v.x, gg, hh);
+            d = fmin(fmax(dv, -v.y), v.y);
+            double nb = v.x + d;
+            if (isfinite(nb)) {
+              A.fits[f].bt[(size_t)b * J + j0 + c] = make_double2(nb, fmax(2.0 * fabs(d), 0.5 * v.y));
             } else {
+              d = 0.0;
               atomicOr(&bad_any, 1);
             }
+          } else {
+            atomicOr(&bad_any, 1);
           }
-          const double em1 = expm1(d);
-          dd[f][0] = d;
-          dd[f][1] = 1.0 + em1;
-          dd[f][2] = em1;
         }
+        if (lane < FM) {
+          const double em1 = expm1(d);
+          s_ed[lane] = 1.0 + em1;
+          s_em1[lane] = em1;
+        }
+        const uint64_t moved = __ballot(lane < FM && d != 0.0);
+        if (lane < F) s_fstep[lane] = ((moved >> (lane * m)) & ((1ull << m) - 1ull)) != 0ull;
         if (lane == 0) flag = okr ? 1 : 0;
       }
-      ++seq;
+#pragma unroll
+      for (int c = 0; c < kMaxGroup; ++c)
+        if (m - 1 == c) ++gseq[c];
       __syncthreads();
       if (!flag) { ok = false; break; }
       if (bad_any) { status = SCCS_ERR_NUMERIC; ok = false; break; }
-      if (worker) pairs_phase_b<WT>(A, wm, wave, s_done, s_ixs[cur][wave], s_ixrp[cur][wave], all_ixs, dd);
+      if (worker)
+        pairs_phase_b<WT, NC>(A, wm, wave, m, s_done, s_ixs[cur][wave], s_ixrp[cur][wave], all_ixs, s_fstep, s_ed, s_em1);
       __syncthreads();
     }
     if (!ok) break;
@@ -816,7 +876,8 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchArgs A) {
   }
   __syncthreads();
   if (b == 0 && tid == 0) {
-    A.ctrl->seq = seq;
+#pragma unroll
+    for (int c = 0; c < kMaxGroup; ++c) A.ctrl->gseq[c] = gseq[c];
     A.ctrl->sweeps = total_sweeps;
     if (status != SCCS_OK) A.ctrl->status = status;
   }
