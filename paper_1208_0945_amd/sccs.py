@@ -329,7 +329,7 @@ class Batch:
     """Many fits in one persistent launch (sccs_batch_*)."""
 
     def __init__(self, probs, specs, precision: int = PREC_FP64, n_workgroups: int = 0,
-                 refresh_period: int = -1, stream=None, tile_nnz: int = 0):
+                 refresh_period: int = -1, stream=None, tile_nnz: int = 0, max_group: int = 0):
         import torch
         if stream is None:
             stream = torch.cuda.current_stream()
@@ -339,7 +339,7 @@ class Batch:
         parr = (Problem_ * len(self._probs))(*[P.s for P in self._probs])
         sarr = (FitSpec_ * len(self._specs))(*[s.struct() for s in self._specs])
         self._parr, self._sarr = parr, sarr
-        o = options(precision, n_workgroups, refresh_period, stream.cuda_stream, tile_nnz)
+        o = options(precision, n_workgroups, refresh_period, stream.cuda_stream, tile_nnz, max_group)
         L = lib()
         n = ctypes.c_size_t()
         st = L.sccs_batch_query_workspace(ctypes.addressof(parr), len(self._probs), ctypes.addressof(sarr),

@@ -118,6 +118,29 @@ def test_bootstrap_replicates(sccs):
             assert abs(b.heldout(r) - oob) <= 1e-8 * abs(oob), r
 
 
+@pytest.mark.parametrize("n_reps,max_group", [(20, 0), (20, 1), (6, 2)])
+def test_bootstrap_column_groups(sccs, n_reps, max_group):
+    """Replicates of one problem share its column groups: 20 replicates give
+    groups of up to 3 columns (2 F m <= 128 words), 6 replicates up to the
+    requested width; every replicate against the oracle, and the grouped run
+    against the one-column-per-group run."""
+    prob = synth.zipf_problem("bootg", 4000, 40, 0.03, seed_path=(9, 5))
+    wts = synth.bootstrap_weights(prob.n_patients, n_reps, seed=6)
+    specs = [sccs.FitSpec(0, [(sccs.PRIOR_LAPLACE, 2.0)], weight=w) for w in wts]
+    with sccs.Batch([prob], specs, max_group=max_group) as b:
+        b.run(sccs.CRIT_FIXED, max_sweeps=6)
+        got = [b.get(r)[0] for r in range(n_reps)]
+    with sccs.Batch([prob], specs, max_group=1) as b:
+        b.run(sccs.CRIT_FIXED, max_sweeps=6)
+        plain = [b.get(r)[0] for r in range(n_reps)]
+    for r in range(n_reps):
+        assert rel_inf(got[r], plain[r]) <= 1e-12, r
+    for r in (0, n_reps - 1):
+        ref = oracle.ccd(prob, oracle.PRIOR_LAPLACE, 2.0, 6, weight=wts[r])
+        assert rel_inf(got[r], ref["beta"]) <= FP64_TOL, r
+        assert np.array_equal(got[r] == 0.0, ref["beta"] == 0.0)
+
+
 def test_batch_mixed_precision(sccs):
     probs = outcomes(4, seed=5)
     with sccs.Batch(probs, [sccs.FitSpec(f, [(sccs.PRIOR_LAPLACE, 2.0)]) for f in range(4)],
