@@ -24,7 +24,9 @@
 // Because a workgroup only touches state it owns, phase B of coordinate j
 // and phase A of coordinate j+1 are ordered by a workgroup barrier alone;
 // the only device-wide traffic per coordinate is the exchange of two
-// doubles per workgroup.
+// doubles per workgroup.  Independent coordinates share that exchange:
+// column groups (consecutive columns with no patient in common), and passes
+// of two groups when the columns linking them take zero steps (below).
 //
 // Tagged-slot reduction.  Both partials are sums of non-negative terms (the
 // per-patient factor 1 - r_i is clamped at zero, which only matters when
@@ -502,7 +504,9 @@ __device__ __forceinline__ void tiles_b(const KArgs& a, int t, int t1, int strid
 // every workgroup marks the patients of each group in an LDS bitmap over its
 // own patient range, and a speculative tile that holds a marked patient is
 // gathered again after the update.  The values used are therefore exactly
-// those of the sequential algorithm.
+// those of the sequential algorithm.  The merged-pass form does the same per
+// pass (one group, or two): the first tiles of both groups of the next pass
+// are gathered ahead, and the bitmap marks the patients of the whole pass.
 
 constexpr int kWorkers = kWaves - 1;
 
