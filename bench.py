@@ -104,15 +104,15 @@ KERNEL_SOURCES = ("sccs_kernels.hpp", "sccs_device.hpp", "sccs_limits.hpp", "scc
 def kernel_source_sha() -> str:
     """sha256 (first 16 hex digits) of the sources that decide the sweep
     kernel's memory traffic: device code, launch constants and the layout,
-    with comments and blank lines removed (a comment edit does not change
-    the kernel)."""
+    with comments, indentation and blank lines removed (an edit of comments
+    or layout does not change the kernel)."""
     import hashlib
     import re
     csrc = os.path.join(ROOT, "paper_1208_0945_amd", "csrc")
     code = []
     for f in KERNEL_SOURCES:
         for line in open(os.path.join(csrc, f)):
-            line = re.sub(r"//.*", "", line).rstrip()
+            line = re.sub(r"//.*", "", line).strip()
             if line:
                 code.append(line)
     return hashlib.sha256("\n".join(code).encode()).hexdigest()[:16]

@@ -855,10 +855,9 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
       while (cur.s < NG) {
         unsigned* bits_cur = par ? bits1 : bits0;
         unsigned* bits_prev = par ? bits0 : bits1;
-        // the pass after next: the tile ranges of the two groups it may hold
-        // are loaded now; it is planned later, in the shadow of the reduction
-        // (its descriptor was loaded one pass ago; reading it here would wait
-        // for the previous pass's stores as well)
+        // the pass after next: the tile range of its first group is loaded
+        // now; the pass is planned (one group or two) in the shadow of the
+        // reduction, from the descriptor loaded one pass ago
         Pass nn;
         nn.s = nxt.s + nxt.n;
         nn.n = 0;
@@ -894,9 +893,9 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
         }
         switch (m) {   // sum only the words of the pass's columns (m is uniform)
           case 1: block_sum_to<2>(loc, part, redg, kPoller); break;
-  #if SCCS_MAX_GROUP >= 2
+#if SCCS_MAX_GROUP >= 2
           case 2: block_sum_to<4>(loc, part, redg, kPoller); break;
-  #endif
+#endif
           default: block_sum_to<2 * kMaxGroup>(loc, part, redg, kPoller); break;
         }
         if (worker) {
@@ -936,12 +935,12 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
           bool okr;
           switch (m) {   // one width per slot class, fixed at compile time
             case 1: okr = allreduce2_wave<2>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
-  #if SCCS_MAX_GROUP >= 2
+#if SCCS_MAX_GROUP >= 2
             case 2: okr = allreduce2_wave<4>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
-  #endif
-  #if SCCS_MAX_GROUP >= 3
+#endif
+#if SCCS_MAX_GROUP >= 3
             case 3: okr = allreduce2_wave<6>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
-  #endif
+#endif
             default: okr = allreduce2_wave<2 * kMaxGroup>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
           }
 
@@ -1086,9 +1085,9 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
         }
         switch (m) {   // sum only the words of the group's columns (m is uniform)
           case 1: block_sum_to<2>(loc, part, redg, kPoller); break;
-  #if SCCS_MAX_GROUP >= 2
+#if SCCS_MAX_GROUP >= 2
           case 2: block_sum_to<4>(loc, part, redg, kPoller); break;
-  #endif
+#endif
           default: block_sum_to<2 * kMaxGroup>(loc, part, redg, kPoller); break;
         }
         Pf pf_next2;
@@ -1118,12 +1117,12 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
           bool okr;
           switch (m) {   // one width per slot class, fixed at compile time
             case 1: okr = allreduce2_wave<2>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
-  #if SCCS_MAX_GROUP >= 2
+#if SCCS_MAX_GROUP >= 2
             case 2: okr = allreduce2_wave<4>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
-  #endif
-  #if SCCS_MAX_GROUP >= 3
+#endif
+#if SCCS_MAX_GROUP >= 3
             case 3: okr = allreduce2_wave<6>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
-  #endif
+#endif
             default: okr = allreduce2_wave<2 * kMaxGroup>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
           }
 
