@@ -108,14 +108,15 @@ typedef struct sccs_options {
                               0 = 4, else 1..4 (1 = one column per reduction).  The batched
                               form groups columns only when all its fits share one problem,
                               with at most 64 / n_fits columns per group. */
-  int32_t merge_passes;    /* single fit: 1 = let the next group share the current group's
-                              reduction (up to max_group columns) when every column that links
-                              them through a shared patient took a zero step in its previous
-                              visit; the prediction is checked after the step and, where it
-                              fails, the second group is visited again on its own, so g_j, h_j
-                              and beta are those of the plain cyclic order (bit for bit);
-                              used for launches that follow one where most steps were zero
-                              (see sccs_pass_stats); 0 = off.  Default 1. */
+  int32_t merge_passes;    /* single fit: 1 = let up to 3 consecutive column groups (5 columns
+                              at most) share one reduction when every earlier column of the
+                              pass that shares a patient with a later group took a zero step
+                              in its previous visit; the prediction is checked after the step
+                              and, where it fails, the first group it fails for and the groups
+                              after it are visited again, so g_j, h_j and beta are those of
+                              the plain cyclic order (bit for bit); used for launches that
+                              follow one where most steps were zero (see sccs_pass_stats);
+                              0 = off.  Default 1. */
   void* stream;            /* hipStream_t */
 } sccs_options;
 
@@ -191,8 +192,8 @@ sccs_status sccs_last_kernel_ms(sccs_handle* h, double* ms);
 
 /* Schedule statistics of the most recent sccs_sweep / sccs_fit launch:
  * passes = device-wide coordinate reductions run (one per column group, or
- * per two groups merged as options.merge_passes describes), rejects =
- * merged passes whose second group had to be visited again, zero_steps =
+ * per run of groups merged as options.merge_passes describes), rejects =
+ * merged passes whose later groups had to be visited again, zero_steps =
  * coordinate visits whose step was exactly zero.  Merged passes are used
  * for a launch when at least half of the previous launch's visits took
  * zero steps (until that share falls below 35 %).  ERR_STATE before any

@@ -42,7 +42,7 @@ struct sccs_handle {
   int32_t* d_weight = nullptr;
   std::vector<int32_t> gcol;  // host copy of the column groups
   Ctrl* h_ctrl = nullptr;  // pinned host mirror of the control block
-  uint32_t gseq0[kMaxGroup] = {};  // reduction sequence numbers before the last sweep launch
+  uint32_t gseq0[kSlotClasses] = {};  // reduction sequence numbers before the last sweep launch
   int last_mode = -1;              // kind of the last launch
   int32_t passes = 0, rejects = 0, zero_steps = 0;  // schedule statistics of the last sweep launch
   bool swept = false;
@@ -101,8 +101,8 @@ size_t carve(void* base, const Layout& L, int prec, bool has_weight, Plan& P) {
   P.beta = c.take<double>((size_t)L.J);
   P.trust = c.take<double>((size_t)L.J);
   const size_t n1 = (size_t)2 * kMaxWorkgroups * kSlotWords, n2 = (size_t)2 * kReplicas * kGroups * kSlotWords;
-  P.slots = c.take<uint64_t>(kMaxGroup * kSlots1PerClass);
-  P.slots2 = c.take<uint64_t>(kMaxGroup * kSlots2PerClass);
+  P.slots = c.take<uint64_t>(kSlotClasses * kSlots1PerClass);
+  P.slots2 = c.take<uint64_t>(kSlotClasses * kSlots2PerClass);
   P.oslots = c.take<uint64_t>(n1);
   P.oslots2 = c.take<uint64_t>(n2);
   P.ctrl = c.take<Ctrl>(1);
@@ -186,7 +186,7 @@ sccs_status read_ctrl(sccs_handle* h) {
   if (h->last_mode == kModeSweep) {
     // one reduction per pass, each on the sequence of its width class
     uint32_t n = 0;
-    for (int c = 0; c < kMaxGroup; ++c) n += h->h_ctrl->gseq[c] - h->gseq0[c];
+    for (int c = 0; c < kSlotClasses; ++c) n += h->h_ctrl->gseq[c] - h->gseq0[c];
     h->passes = (int32_t)n;
     h->rejects = h->h_ctrl->rejects;
     h->zero_steps = h->h_ctrl->zero_steps;
@@ -237,7 +237,7 @@ sccs_status launch(sccs_handle* h, int mode, int n_sweeps, int criterion, double
   HIPCHK(h, hipEventRecord(h->ev0, h->stream));
   const bool merge = a.merge && h->use_merge;
   if (mode == kModeSweep)   // the mirror holds the state after the previous launch
-    for (int c = 0; c < kMaxGroup; ++c) h->gseq0[c] = h->h_ctrl->gseq[c];
+    for (int c = 0; c < kSlotClasses; ++c) h->gseq0[c] = h->h_ctrl->gseq[c];
   h->last_mode = mode;
   HIPCHK(h, hipLaunchCooperativeKernel(ccd_kernel(h->prec, mode, merge), dim3(h->G), dim3(kBlock), params,
                                         (unsigned)h->lds_bytes, h->stream));
@@ -421,8 +421,8 @@ sccs_status sccs_create(const sccs_problem* prob, const sccs_options* opts_in, v
   // reduction slots start with the tag that reductions 0 and 1 do not expect
   {
     const size_t n1 = (size_t)2 * kMaxWorkgroups * kSlotWords, n2 = (size_t)2 * kReplicas * kGroups * kSlotWords;
-    hipLaunchKernelGGL(k_fill_u64, dim3(64), dim3(256), 0, s, P.slots, kMaxGroup * kSlots1PerClass, kSign);
-    hipLaunchKernelGGL(k_fill_u64, dim3(16), dim3(256), 0, s, P.slots2, kMaxGroup * kSlots2PerClass, kSign);
+    hipLaunchKernelGGL(k_fill_u64, dim3(64), dim3(256), 0, s, P.slots, kSlotClasses * kSlots1PerClass, kSign);
+    hipLaunchKernelGGL(k_fill_u64, dim3(16), dim3(256), 0, s, P.slots2, kSlotClasses * kSlots2PerClass, kSign);
     hipLaunchKernelGGL(k_fill_u64, dim3(16), dim3(256), 0, s, P.oslots, n1, kSign);
     hipLaunchKernelGGL(k_fill_u64, dim3(4), dim3(256), 0, s, P.oslots2, n2, kSign);
   }

@@ -15,6 +15,7 @@ constexpr int kPoller = kWaves - 1;      // wave that runs the device-wide reduc
 constexpr int kSlotWords = 16;           // one 128-byte line per reduction slot
 constexpr int kReplicas = 8;             // copies of the group totals
 constexpr int kMaxJ = 6144;              // beta, trust, beta_prev live in LDS
+static_assert(kMaxJ < kDescMaxCols, "every column index fits in a pass descriptor");
 constexpr uint64_t kSign = 0x8000000000000000ull;
 constexpr long long kSpinLimit = 1ll << 22;  // bounded waits (about a second), then abort
 #ifndef SCCS_POLL_SLEEP
@@ -24,9 +25,12 @@ constexpr long long kSpinLimit = 1ll << 22;  // bounded waits (about a second), 
 // chain of reductions measured fastest with none.
 constexpr int kPollSleep = SCCS_POLL_SLEEP;
 
-// Coordinate reductions of a single fit use one slot array per group size
-// (class m - 1 for m columns), each with its own sequence number, so that
-// every reduction on a slot array writes and reads the same number of words.
+// Coordinate reductions of a single fit use one slot array per width (class
+// m - 1 for m <= kMaxGroup columns, 2m words; class kMaxGroup for merged
+// passes of more columns, 2 * kPassCols words), each with its own sequence
+// number, so that every reduction on a slot array writes and reads the same
+// number of words.
+constexpr int kSlotClasses = kMaxGroup + 1;
 constexpr size_t kSlots1PerClass = (size_t)2 * kMaxWorkgroups * kSlotWords;  // level 1, both parities
 constexpr size_t kSlots2PerClass = (size_t)2 * kReplicas * kGroups * kSlotWords;
 
@@ -42,8 +46,8 @@ struct Ctrl {
   int32_t pad;
   double loglik, logpost;
   double g, h;         // diagnostic output
-  uint32_t gseq[kMaxGroup];  // single fit: sequence number of each reduction class
-  int32_t rejects;     // single fit, last launch: merged passes whose second group was visited again
+  uint32_t gseq[kSlotClasses];  // single fit: sequence number of each reduction class
+  int32_t rejects;     // single fit, last launch: merged passes whose later groups were visited again
   int32_t zero_steps;  //   coordinate visits whose step was exactly zero
 };
 
@@ -64,8 +68,8 @@ struct KArgs {
   const double* ytx;          // [J]
   double* beta;               // [J]
   double* trust;              // [J]
-  uint64_t* slots;            // [kMaxGroup classes][2][256][16] coordinate reductions, level 1
-  uint64_t* slots2;           // [kMaxGroup classes][2][8 replicas][8 groups][16] group totals
+  uint64_t* slots;            // [kSlotClasses][2][256][16] coordinate reductions, level 1
+  uint64_t* slots2;           // [kSlotClasses][2][8 replicas][8 groups][16] group totals
   uint64_t* oslots;           // objective reduction, same shapes
   uint64_t* oslots2;
   Ctrl* ctrl;

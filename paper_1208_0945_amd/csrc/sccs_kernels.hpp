@@ -26,7 +26,8 @@
 // the only device-wide traffic per coordinate is the exchange of two
 // doubles per workgroup.  Independent coordinates share that exchange:
 // column groups (consecutive columns with no patient in common), and passes
-// of two groups when the columns linking them take zero steps (below).
+// of several consecutive groups when the columns linking them take zero
+// steps (below).
 //
 // Tagged-slot reduction.  Both partials are sums of non-negative terms (the
 // per-patient factor 1 - r_i is clamped at zero, which only matters when
@@ -72,6 +73,14 @@ __device__ __forceinline__ double wave_sum(double v) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)b, 63);
   const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Lane l's value (l a compile-time constant), as a scalar.
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
@@ -122,7 +131,7 @@ __device__ __forceinline__ bool poll_tagged(const uint64_t* src, bool active, ui
       return false;
     }
     if ((spins & 255) == 0 && load_agent_i(&ctrl->abort)) return false;
-    __builtin_amdgcn_s_sleep(2);
+    if (kPollSleep) __builtin_amdgcn_s_sleep(kPollSleep);
   }
 }
 
@@ -222,14 +231,17 @@ __device__ void block_sum(const double* v_in, double* out, double (*red)[W]) {
 }
 
 // Workgroup sum delivered to wave `dst`: wave sums, then the wave partials
-// combined inside wave dst (lane q*NV + i reads wave q's word i, one LDS read
-// per lane, all in flight at once; word i is the wave sum over its lanes).
-// The order is fixed.  Result valid in all lanes of wave dst; one barrier.
-// red[] may be reused after the caller's next barrier.
+// combined inside wave dst, eight words per round: lane 8k + q reads wave
+// q's word r + k, and three butterfly stages within each group of eight
+// lanes add ((w0 + w1) + (w2 + w3)) + ((w4 + w5) + (w6 + w7)).  The order
+// does not depend on NV, so a column's sum is the same whether its
+// reduction carries one column or several.  Result valid in all lanes of
+// wave dst (scalars); one barrier.  red[] may be reused after the caller's
+// next barrier.
 template <int NV, int W>
 __device__ __forceinline__ void block_sum_to(const double* v_in, double* out, double (*red)[W], int dst) {
   static_assert(NV <= W, "reduction rows too narrow");
-  static_assert(kWaves * NV <= 64, "one lane per (wave, word)");
+  static_assert(kWaves == 8, "one butterfly over eight lanes per word");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double v[NV];
 #pragma unroll
@@ -240,9 +252,17 @@ __device__ __forceinline__ void block_sum_to(const double* v_in, double* out, do
   }
   __syncthreads();
   if (wave == dst) {
-    const double x = lane < kWaves * NV ? red[lane / NV][lane % NV] : 0.0;
 #pragma unroll
-    for (int i = 0; i < NV; ++i) out[i] = wave_sum(lane % NV == i ? x : 0.0);
+    for (int r = 0; r < NV; r += 8) {
+      const int i = r + (lane >> 3);
+      double x = i < NV ? red[lane & 7][i] : 0.0;
+      x = dpp_add<0xB1, 0xf>(x);   // quad_perm [1,0,3,2]
+      x = dpp_add<0x4E, 0xf>(x);   // quad_perm [2,3,0,1]
+      x = dpp_add<0x141, 0xf>(x);  // row_half_mirror
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (r + k < NV) out[r + k] = readlane_d(x, 8 * k);
+    }
   }
 }
 
@@ -505,14 +525,15 @@ __device__ __forceinline__ void tiles_b(const KArgs& a, int t, int t1, int strid
 // own patient range, and a speculative tile that holds a marked patient is
 // gathered again after the update.  The values used are therefore exactly
 // those of the sequential algorithm.  The merged-pass form does the same per
-// pass (one group, or two): the first tiles of both groups of the next pass
-// are gathered ahead, and the bitmap marks the patients of the whole pass.
+// pass (one group or several): the first tiles of every group of the next
+// pass are gathered ahead, and the bitmap marks the patients of the whole
+// pass.
 
 constexpr int kWorkers = kWaves - 1;
 
 struct Pf {
   int t, t1;     // the wave's first tile; end of the workgroup's tile range
-  int e0, len;   // that tile's nonzero range
+  int len;       // that tile's number of nonzeros
   uint2 rp;      // this lane's (row, patient | column)
 };
 
@@ -531,23 +552,46 @@ __device__ __forceinline__ void pf_range(const KArgs& a, int g, int& t0, int& t1
   t1 = ld_idx(a.own + base + 1);
 }
 
-__device__ __forceinline__ void pf_tile(const KArgs& a, int t0, int t1, Pf& p) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+// The wave's first tile of range [t0, t1) in two steps, so that the loads of
+// several tiles can be in flight together: its bounds, then this lane's
+// index pair.  kUniform: tile bounds in scalar registers (the merged-pass
+// form holds many first tiles at once).
+template <bool kUniform>
+__device__ __forceinline__ void pf_bounds(const KArgs& a, int t0, int t1, Pf& p, int& e0) {
+  const int wave = threadIdx.x >> 6;
+  if (kUniform) {
+    t0 = __builtin_amdgcn_readfirstlane(t0);
+    t1 = __builtin_amdgcn_readfirstlane(t1);
+  }
   p.t = wave < kWorkers ? t0 + wave : t1;
+  if (kUniform) p.t = __builtin_amdgcn_readfirstlane(p.t);
   p.t1 = t1;
-  p.e0 = 0;
   p.len = 0;
-  p.rp = make_uint2(0u, 0xffffffffu);
+  e0 = 0;
   if (p.t < t1) {
-    p.e0 = ld_idx(a.tile_start + p.t);
-    p.len = ld_idx(a.tile_start + p.t + 1) - p.e0;
-    if (p.len <= 64 && lane < p.len) p.rp = a.rp[p.e0 + lane];
+    e0 = ld_idx(a.tile_start + p.t);
+    p.len = ld_idx(a.tile_start + p.t + 1) - e0;
   }
 }
+template <bool kUniform>
+__device__ __forceinline__ void pf_rows(const KArgs& a, Pf& p, int e0) {
+  const int lane = threadIdx.x & 63;
+  if (kUniform) p.len = __builtin_amdgcn_readfirstlane(p.len);
+  p.rp = make_uint2(0u, 0xffffffffu);
+  if (p.t < p.t1 && p.len <= 64 && lane < p.len) p.rp = a.rp[e0 + lane];
+}
+template <bool kUniform = false>
+__device__ __forceinline__ void pf_tile(const KArgs& a, int t0, int t1, Pf& p) {
+  int e0;
+  pf_bounds<kUniform>(a, t0, t1, p, e0);
+  pf_rows<kUniform>(a, p, e0);
+}
 
-// Gather the wave's first tile (short tiles only) into registers.
+// Gather the wave's first tile (short tiles only) into registers, in two
+// steps so that several tiles' loads can be in flight together: the loads of
+// w and (den_i, omega_i n_i), then the segment sums.
 template <typename WT>
-__device__ __forceinline__ void gather_first(const KArgs& a, const Pf& p, Cache& c) {
+__device__ __forceinline__ void gather_load(const KArgs& a, const Pf& p, Cache& c) {
   const int lane = threadIdx.x & 63;
   c.valid = true;
   c.lead = false;
@@ -561,14 +605,26 @@ __device__ __forceinline__ void gather_first(const KArgs& a, const Pf& p, Cache&
     int seg_start;
     seg_layout(p.rp.y, lane, p.len, lead, seg_start);
     const bool act = lane < p.len;
-    double wv = act ? (double)w[p.rp.x] : 0.0;
-    double2 pv = lead ? a.pat[pid_of(p.rp.y)] : make_double2(1.0, 0.0);
-    c.num = seg_sum_v(wv, lane, seg_start);
-    c.wv = wv;
+    c.wv = act ? (double)w[p.rp.x] : 0.0;
+    const double2 pv = lead ? a.pat[pid_of(p.rp.y)] : make_double2(1.0, 0.0);
     c.den = pv.x;
     c.wn = pv.y;
     c.lead = lead;
   }
+}
+__device__ __forceinline__ void gather_sum(const Pf& p, Cache& c) {
+  const int lane = threadIdx.x & 63;
+  if (p.t < p.t1 && p.len <= 64) {
+    bool lead;
+    int seg_start;
+    seg_layout(p.rp.y, lane, p.len, lead, seg_start);
+    c.num = seg_sum_v(c.wv, lane, seg_start);
+  }
+}
+template <typename WT>
+__device__ __forceinline__ void gather_first(const KArgs& a, const Pf& p, Cache& c) {
+  gather_load<WT>(a, p, c);
+  gather_sum(p, c);
 }
 
 __device__ __forceinline__ void mark_patient(unsigned* bits, unsigned q) { atomicOr(&bits[q >> 5], 1u << (q & 31)); }
@@ -586,8 +642,8 @@ __device__ __forceinline__ bool first_tile_stale(const Pf& p, const unsigned* bi
 
 // Phase A of the current group for one worker wave: the cached first tile
 // (validated by the caller) plus its remaining tiles.
-template <typename WT>
-__device__ __forceinline__ void phase_a_cached(const KArgs& a, const Pf& p, const Cache& c, Acc<kMaxGroup>& acc,
+template <typename WT, int NC>
+__device__ __forceinline__ void phase_a_cached(const KArgs& a, const Pf& p, const Cache& c, Acc<NC>& acc,
                                                unsigned* bits, int p0, uint32_t coff) {
   if (p.t < p.t1) {
     if (p.len <= 64) {
@@ -596,10 +652,10 @@ __device__ __forceinline__ void phase_a_cached(const KArgs& a, const Pf& p, cons
         mark_patient(bits, pid_of(p.rp.y) - (unsigned)p0);
       }
     } else {
-      tile_a<WT, kMaxGroup, true>(a, p.t, acc, bits, p0, coff);
+      tile_a<WT, NC, true>(a, p.t, acc, bits, p0, coff);
     }
   }
-  tiles_a<WT, kMaxGroup, true>(a, p.t + kWorkers, p.t1, kWorkers, acc, bits, p0, coff);
+  tiles_a<WT, NC, true>(a, p.t + kWorkers, p.t1, kWorkers, acc, bits, p0, coff);
 }
 
 template <typename WT>
@@ -633,27 +689,33 @@ __device__ __forceinline__ void phase_b_cached(const KArgs& a, const Pf& p, cons
 
 // ---- passes
 //
-// A pass is one device-wide reduction: a column group, or two consecutive
-// groups when the second is predicted independent of the first.  Group
-// g + 1 depends on group g only through the columns of g that share a
-// patient with it (bit c of the descriptor's mask), and only if one of them
-// takes a nonzero step: until it does, the state of the shared patients is
-// untouched.  Under the Laplace prior many coordinates stay at zero sweep
-// after sweep, so the prediction is "those columns did not move in their
-// last visit" (bit j of a per-column bitmap, identical in every workgroup
-// because every workgroup takes the same steps).  After the reduction the
-// prediction is checked against the steps actually taken; when it fails the
-// second group's sums are dropped and that group is visited again, alone, in
-// the next pass.  Either way every column's g_j and h_j are those of the
-// sequential order, and each column's partial sums are accumulated in the
-// same order as without merging (the other group adds exact zeros).
+// A pass is one device-wide reduction: a column group, or up to kPassGroups
+// consecutive groups (kPassCols columns at most) when each later group is
+// predicted independent of the pass's earlier columns.  A group depends on
+// an earlier column only if they share a patient (bit of the group's link
+// mask) and only if that column takes a nonzero step: until it does, the
+// state of the shared patients is untouched.  Under the Laplace prior many
+// coordinates stay at zero sweep after sweep, so the prediction is "those
+// columns did not move in their last visit" (bit j of a per-column bitmap,
+// identical in every workgroup because every workgroup takes the same
+// steps).  After the reduction the prediction is checked against the steps
+// actually taken: the first group with a linked column that moved, and the
+// groups after it, keep no step, and they form the next pass, from fresh
+// data.  Either way every column's g_j and h_j are those of the sequential
+// order, and each column's partial sums are accumulated in the same order as
+// in a pass of its group alone (the other groups add exact zeros, and the
+// workgroup and device-wide sums add each word in an order that does not
+// depend on the pass's width).
 
 __device__ __forceinline__ int desc_j0(uint32_t d) { return (int)(d & ((1u << kDescColBits) - 1u)); }
-__device__ __forceinline__ int desc_m(uint32_t d) { return (int)((d >> 13) & 7u); }
-__device__ __forceinline__ int desc_mnext(uint32_t d) { return (int)((d >> 16) & 7u); }
-__device__ __forceinline__ uint32_t desc_cmask(uint32_t d) { return (d >> 19) & 15u; }
+__device__ __forceinline__ int desc_m(uint32_t d) { return (int)((d >> kDescWidthShift) & 7u); }
+// Links of the group with descriptor d to the `off` columns just before it
+// (off <= kLinkCols): bit t for column j0 - off + t.
+__device__ __forceinline__ uint32_t desc_links(uint32_t d, int off) {
+  return (d >> (kDescLinkShift + kLinkCols - off)) & ((1u << off) - 1u);
+}
 
-// Bits [j0, j0 + m) of an LDS bitmap (m <= 4; the bitmap covers j0 + m).
+// Bits [j0, j0 + m) of an LDS bitmap (m <= 8; the bitmap covers j0 + m).
 __device__ __forceinline__ uint32_t get_bits(const uint32_t* bm, int j0, int m) {
   const int w = j0 >> 5, sh = j0 & 31;
   uint64_t v = bm[w];
@@ -673,31 +735,86 @@ __device__ __forceinline__ void set_bits(uint32_t* bm, int j0, int m, uint32_t v
   }
 }
 
-// Groups in the pass that starts with descriptor d: 2 when the next group
-// fits in the reduction and every column linking the two is predicted to
-// stay put, else 1.  Uniform (LDS reads of identical values).
-__device__ __forceinline__ int plan_pass(uint32_t d, const uint32_t* mv, int merge) {
-  const int m = desc_m(d);
-  if (!merge || m + desc_mnext(d) > kMaxGroup) return 1;   // also when d is the last group (width 7)
-  const uint32_t linked = desc_cmask(d) & get_bits(mv, desc_j0(d), m);
-  return __builtin_amdgcn_readfirstlane(linked ? 1 : 2);
-}
-
 struct Pass {
-  int s, n;      // first group, number of groups (0: past the last group)
-  uint32_t d;    // descriptor of group s
-  Pf p[2];       // the wave's first tile of each group
+  int s, n;                 // first group, number of groups (0: past the last group)
+  uint32_t D[kPassGroups];  // descriptors of groups s, s + 1, ... (0 past the last group)
+  Pf p[kPassGroups];        // the wave's first tile of each group
 };
 
-// Tile indices of every group of pass p, loaded in sequence (pipeline start).
-__device__ __forceinline__ void load_pass(const KArgs& a, Pass& p) {
-  int t0, t1;
-  pf_range(a, p.s, t0, t1);
-  pf_tile(a, t0, t1, p.p[0]);
-  if (p.n == 2) {
-    pf_range(a, p.s + 1, t0, t1);
-    pf_tile(a, t0, t1, p.p[1]);
+// Descriptors of groups s .. s + kPassGroups - 1 in lanes 0 .. kPassGroups-1.
+__device__ __forceinline__ uint32_t ld_descs(const KArgs& a, int s) {
+  const int l = threadIdx.x & 63;
+  return (l < kPassGroups && s + l < a.n_groups) ? ld_idx(a.gdesc + s + l) : 0u;
+}
+__device__ __forceinline__ void take_descs(uint32_t dv, Pass& p) {
+#pragma unroll
+  for (int k = 0; k < kPassGroups; ++k) p.D[k] = (uint32_t)__builtin_amdgcn_readlane((int)dv, k);
+}
+
+// Groups in the pass that starts at group p.s: the longest run of groups
+// that fits in kPassCols columns and whose links to the pass's earlier
+// columns all point at columns predicted to stay put.  Uniform (scalar
+// values and LDS reads of identical values).
+__device__ __forceinline__ int plan_pass(const Pass& p, const uint32_t* mv, const KArgs& a) {
+  if (!a.merge) return 1;
+  const int j0 = desc_j0(p.D[0]);
+  const uint32_t pred = get_bits(mv, j0, min(kLinkCols, a.J - j0));
+  int cols = desc_m(p.D[0]), n = 1;
+  bool open = true;
+#pragma unroll
+  for (int k = 1; k < kPassGroups; ++k) {
+    if (open && p.s + k < a.n_groups) {
+      const int mk = desc_m(p.D[k]);
+      if (cols + mk <= kPassCols && (desc_links(p.D[k], cols) & pred) == 0u) {
+        cols += mk;
+        n = k + 1;
+      } else {
+        open = false;
+      }
+    }
   }
+  return __builtin_amdgcn_readfirstlane(n);
+}
+
+// Columns of the first `n` groups of pass p.
+__device__ __forceinline__ int pass_cols(const Pass& p, int n) {
+  int cols = 0;
+#pragma unroll
+  for (int k = 0; k < kPassGroups; ++k)
+    if (k < n) cols += desc_m(p.D[k]);
+  return cols;
+}
+
+// Tile indices of every group of pass p (pipeline start).
+__device__ __forceinline__ void load_pass(const KArgs& a, Pass& p) {
+  int t0[kPassGroups], t1[kPassGroups];
+#pragma unroll
+  for (int k = 0; k < kPassGroups; ++k)
+    if (k < p.n) pf_range(a, p.s + k, t0[k], t1[k]);
+  int e0[kPassGroups];
+#pragma unroll
+  for (int k = 0; k < kPassGroups; ++k)
+    if (k < p.n) pf_bounds<true>(a, t0[k], t1[k], p.p[k], e0[k]);
+#pragma unroll
+  for (int k = 0; k < kPassGroups; ++k)
+    if (k < p.n) pf_rows<true>(a, p.p[k], e0[k]);
+}
+
+// The pass without its first r groups (a rejected tail, visited again).
+__device__ __forceinline__ void drop_groups(Pass& p, int r) {
+#pragma unroll
+  for (int q = 1; q < kPassGroups; ++q) {
+    if (q <= r) {
+#pragma unroll
+      for (int k = 0; k + 1 < kPassGroups; ++k) {
+        p.D[k] = p.D[k + 1];
+        p.p[k] = p.p[k + 1];
+      }
+      p.D[kPassGroups - 1] = 0u;
+    }
+  }
+  p.s += r;
+  p.n -= r;
 }
 
 // Exact recomputation of w = L x exp(X beta) and den = M w for patients
@@ -777,10 +894,10 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
   double* strust = lds_dyn + a.J;       // [J]
   double* sprev = lds_dyn + 2 * a.J;    // [J] beta at the start of the sweep
   __shared__ double red[kWaves][4];
-  __shared__ double redg[kWaves][2 * kMaxGroup];
+  __shared__ double redg[kWaves][2 * kPassCols];
   __shared__ double bc[8];
   __shared__ int bci[4];
-  __shared__ double s_ed[kMaxGroup], s_em1[kMaxGroup];
+  __shared__ double s_ed[kPassCols], s_em1[kPassCols];
 
   const int tid = threadIdx.x, b = blockIdx.x;
   for (int j = tid; j < a.J; j += kBlock) {
@@ -788,9 +905,9 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
     strust[j] = a.trust[j];
   }
   // identical in all workgroups (written by the previous launch)
-  uint32_t gseq[kMaxGroup];   // sequence number per reduction class
+  uint32_t gseq[kSlotClasses];   // sequence number per reduction class
 #pragma unroll
-  for (int c = 0; c < kMaxGroup; ++c) gseq[c] = a.ctrl->gseq[c];
+  for (int c = 0; c < kSlotClasses; ++c) gseq[c] = a.ctrl->gseq[c];
   uint32_t oseq = a.ctrl->oseq;
   int since_refresh = a.ctrl->since_refresh;
   __syncthreads();
@@ -816,7 +933,7 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
   unsigned* bits1 = bits0 + a.nbits;                  // patients of odd passes
   uint32_t* s_mv = bits1 + a.nbits;                   // moved-column bits (identical in every workgroup)
   for (int i = tid; i < a.mv_words; i += kBlock) s_mv[i] = a.moved[i];
-  __shared__ uint32_t s_nn[2];   // merged passes: the pass after next (groups, descriptor), for the poller
+  __shared__ uint32_t s_nn[1 + kPassGroups];   // merged passes: the pass after next (groups, descriptors), for the poller
   // poller lane 0: rejected merges and coordinate visits with an exactly
   // zero step in this launch
   int n_rej = 0, n_zero = 0;
@@ -831,122 +948,185 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
       // pipeline start: the first two passes' indices; nothing speculated
       Pass cur, nxt;
       cur.s = 0;
-      cur.d = __builtin_amdgcn_readfirstlane(ld_idx(a.gdesc));
-      cur.n = plan_pass(cur.d, s_mv, a.merge);
+      take_descs(ld_descs(a, 0), cur);
+      cur.n = plan_pass(cur, s_mv, a);
       load_pass(a, cur);
       nxt.s = cur.s + cur.n;
       nxt.n = 0;
-      nxt.d = 0u;
+      take_descs(nxt.s < NG ? ld_descs(a, nxt.s) : 0u, nxt);
       if (nxt.s < NG) {
-        nxt.d = __builtin_amdgcn_readfirstlane(ld_idx(a.gdesc + nxt.s));
-        nxt.n = plan_pass(nxt.d, s_mv, a.merge);
+        nxt.n = plan_pass(nxt, s_mv, a);
         load_pass(a, nxt);
       } else {
         nxt.s = NG;
       }
-      uint32_t d_nn = 0u;   // descriptor of the pass after nxt
-      if (nxt.n > 0 && nxt.s + nxt.n < NG) d_nn = ld_idx(a.gdesc + nxt.s + nxt.n);
-      Cache c_cur[2], c_nxt[2];
-      c_cur[0].valid = c_cur[1].valid = false;
-      c_nxt[0].valid = c_nxt[1].valid = false;
-      int par = 0;
-      int mv_cols = 0;        // poller: columns whose moved bits this pass sets
-      uint32_t mv_val = 0u;
-      while (cur.s < NG) {
-        unsigned* bits_cur = par ? bits1 : bits0;
-        unsigned* bits_prev = par ? bits0 : bits1;
-        // the pass after next: the tile range of its first group is loaded
-        // now; the pass is planned (one group or two) in the shadow of the
-        // reduction, from the descriptor loaded one pass ago
-        Pass nn;
-        nn.s = nxt.s + nxt.n;
-        nn.n = 0;
-        nn.d = 0u;
-        const bool nn_live = nxt.n > 0 && nn.s < NG;
-        int nr0 = 0, nr1 = 0;
-        uint32_t d_nnn = 0u;
-        if (nn_live && worker) {
-          pf_range(a, nn.s, nr0, nr1);
-        }
-        const int j0 = desc_j0(cur.d);
-        const int ma = desc_m(cur.d);                              // columns of the pass's first group
-        const int m = ma + (cur.n == 2 ? desc_mnext(cur.d) : 0);   // columns of the pass
-        const double ytx_cur = (wave == kPoller && lane < m) ? a.ytx[j0 + lane] : 0.0;
-
-        // phase A: validate the speculative first tiles, then accumulate
-        Acc<kMaxGroup> acc;
-        acc.zero();
-        if (worker) {
-          if (!c_cur[0].valid || first_tile_stale(cur.p[0], bits_prev, p0)) gather_first<WT>(a, cur.p[0], c_cur[0]);
-          phase_a_cached<WT>(a, cur.p[0], c_cur[0], acc, bits_cur, p0, 0u);
-          if (cur.n == 2) {
-            if (!c_cur[1].valid || first_tile_stale(cur.p[1], bits_prev, p0)) gather_first<WT>(a, cur.p[1], c_cur[1]);
-            phase_a_cached<WT>(a, cur.p[1], c_cur[1], acc, bits_cur, p0, (uint32_t)ma);
-          }
-        }
-        double loc[2 * kMaxGroup], part[2 * kMaxGroup];
+      // The workers and the poller run the pass sequence in loops of their
+      // own, with the same barriers in the same order and the same decisions
+      // (every one taken from LDS values that both sides read after a
+      // barrier), so that the poller carries none of the workers' tile state
+      // through the reduction.
+      if (worker) {
+        // descriptors of the pass after nxt (lanes 0 .. kPassGroups-1)
+        uint32_t dv_nn = (nxt.n > 0 && nxt.s + nxt.n < NG) ? ld_descs(a, nxt.s + nxt.n) : 0u;
+        Cache c_cur[kPassGroups], c_nxt[kPassGroups];
 #pragma unroll
-        for (int i = 0; i < kMaxGroup; ++i) {
-          loc[2 * i] = acc.g[i];
-          loc[2 * i + 1] = acc.h[i];
-          part[2 * i] = part[2 * i + 1] = 0.0;
-        }
-        switch (m) {   // sum only the words of the pass's columns (m is uniform)
-          case 1: block_sum_to<2>(loc, part, redg, kPoller); break;
-#if SCCS_MAX_GROUP >= 2
-          case 2: block_sum_to<4>(loc, part, redg, kPoller); break;
-#endif
-          default: block_sum_to<2 * kMaxGroup>(loc, part, redg, kPoller); break;
-        }
-        if (worker) {
-          // in the shadow of the reduction: clear the other bitmap, gather the
-          // next pass speculatively, load the tile indices of the pass after it
-          for (int i = tid; i < a.nbits; i += kWorkers * 64) bits_prev[i] = 0u;
-          if (nxt.n > 0) gather_first<WT>(a, nxt.p[0], c_nxt[0]);
-          if (nxt.n == 2) gather_first<WT>(a, nxt.p[1], c_nxt[1]);
-          if (nn_live) {
-            nn.d = __builtin_amdgcn_readfirstlane(d_nn);
-            nn.n = plan_pass(nn.d, s_mv, a.merge);
-            if (nn.s + nn.n < NG) d_nnn = ld_idx(a.gdesc + nn.s + nn.n);
-            pf_tile(a, nr0, nr1, nn.p[0]);
-            if (nn.n == 2) {   // the second group's range only now (merged passes are the fewer)
-              int t0, t1;
-              pf_range(a, nn.s + 1, t0, t1);
-              pf_tile(a, t0, t1, nn.p[1]);
+        for (int k = 0; k < kPassGroups; ++k) c_cur[k].valid = c_nxt[k].valid = false;
+        int par = 0;
+        while (cur.s < NG) {
+          unsigned* bits_cur = par ? bits1 : bits0;
+          unsigned* bits_prev = par ? bits0 : bits1;
+          // the pass after next: the tile range of its first group is loaded
+          // now; the pass is planned in the shadow of the reduction, from the
+          // descriptors loaded one pass ago
+          Pass nn;
+          nn.s = nxt.s + nxt.n;
+          nn.n = 0;
+#pragma unroll
+          for (int k = 0; k < kPassGroups; ++k) nn.D[k] = 0u;
+          const bool nn_live = nxt.n > 0 && nn.s < NG;
+          int nr0 = 0, nr1 = 0;
+          uint32_t dv_nnn = 0u;
+          if (nn_live) pf_range(a, nn.s, nr0, nr1);
+          const int j0 = desc_j0(cur.D[0]);
+          const int m = pass_cols(cur, cur.n);                       // columns of the pass
+          const int cls = m <= kMaxGroup ? m - 1 : kMaxGroup;        // its reduction class
+
+          // phase A: validate the speculative first tiles, then accumulate
+          Acc<kPassCols> acc;
+          acc.zero();
+#pragma unroll
+          for (int k = 0; k < kPassGroups; ++k) {
+            if (k < cur.n) {
+              if (!c_cur[k].valid || first_tile_stale(cur.p[k], bits_prev, p0)) gather_first<WT>(a, cur.p[k], c_cur[k]);
+              phase_a_cached<WT>(a, cur.p[k], c_cur[k], acc, bits_cur, p0, (uint32_t)(desc_j0(cur.D[k]) - j0));
             }
+          }
+          double loc[2 * kPassCols], part[2 * kPassCols];
+#pragma unroll
+          for (int i = 0; i < kPassCols; ++i) {
+            loc[2 * i] = acc.g[i];
+            loc[2 * i + 1] = acc.h[i];
+          }
+          switch (m) {   // sum only the words of the pass's columns (m is uniform)
+            case 1: block_sum_to<2>(loc, part, redg, kPoller); break;
+            case 2: block_sum_to<4>(loc, part, redg, kPoller); break;
+            case 3:
+            case 4: block_sum_to<8>(loc, part, redg, kPoller); break;
+            default: block_sum_to<2 * kPassCols>(loc, part, redg, kPoller); break;
+          }
+          // in the shadow of the reduction: clear the other bitmap, gather the
+          // next pass speculatively, plan the pass after it and load its
+          // tile indices
+          for (int i = tid; i < a.nbits; i += kWorkers * 64) bits_prev[i] = 0u;
+#pragma unroll
+          for (int k = 0; k < kPassGroups; ++k)
+            if (k < nxt.n) gather_load<WT>(a, nxt.p[k], c_nxt[k]);
+#pragma unroll
+          for (int k = 0; k < kPassGroups; ++k)
+            if (k < nxt.n) gather_sum(nxt.p[k], c_nxt[k]);
+          if (nn_live) {
+            take_descs(dv_nn, nn);
+            nn.n = plan_pass(nn, s_mv, a);
+            if (nn.s + nn.n < NG) dv_nnn = ld_descs(a, nn.s + nn.n);
+            int t0[kPassGroups], t1[kPassGroups], e0[kPassGroups];
+            t0[0] = nr0;
+            t1[0] = nr1;
+#pragma unroll
+            for (int k = 1; k < kPassGroups; ++k)
+              if (k < nn.n) pf_range(a, nn.s + k, t0[k], t1[k]);
+#pragma unroll
+            for (int k = 0; k < kPassGroups; ++k)
+              if (k < nn.n) pf_bounds<true>(a, t0[k], t1[k], nn.p[k], e0[k]);
+#pragma unroll
+            for (int k = 0; k < kPassGroups; ++k)
+              if (k < nn.n) pf_rows<true>(a, nn.p[k], e0[k]);
           }
           if (tid == 0) {
             s_nn[0] = (uint32_t)nn.n;
-            s_nn[1] = nn.d;
+#pragma unroll
+            for (int k = 0; k < kPassGroups; ++k) s_nn[1 + k] = nn.D[k];
           }
-        } else {
+          __syncthreads();   // the poller's step is in LDS
+#pragma unroll
+          for (int c = 0; c < kSlotClasses; ++c)
+            if (cls == c) ++gseq[c];
+          if (!bci[0]) { ok = false; break; }
+          if (bci[1]) { status = SCCS_ERR_NUMERIC; ok = false; break; }
+          const int na = __builtin_amdgcn_readfirstlane(bci[3]);   // groups whose steps are taken
+          if (bci[2]) {
+#pragma unroll
+            for (int k = 0; k < kPassGroups; ++k)
+              if (k < na) {
+                const int off = desc_j0(cur.D[k]) - j0;
+                phase_b_cached<WT>(a, cur.p[k], c_cur[k], Coef{s_ed + off, s_em1 + off});
+              }
+          }
+          __syncthreads();
+          par ^= 1;
+          if (na < cur.n) {
+            // the rejected groups, from fresh data; nxt and the passes after
+            // it stay as planned (their speculative gathers are repeated)
+            drop_groups(cur, na);
+#pragma unroll
+            for (int k = 0; k < kPassGroups; ++k) c_cur[k].valid = false;
+          } else {
+            cur = nxt;
+#pragma unroll
+            for (int k = 0; k < kPassGroups; ++k) c_cur[k] = c_nxt[k];
+            nxt = nn;
+            dv_nn = dv_nnn;
+            if (nxt.n == 0) nxt.s = NG;
+          }
+        }
+      } else {
+        int mv_cols = 0;        // columns whose moved bits this pass sets
+        uint32_t mv_val = 0u;
+        while (cur.s < NG) {
+          Pass nn;
+          nn.s = nxt.s + nxt.n;
+          const int j0 = desc_j0(cur.D[0]);
+          const int m = pass_cols(cur, cur.n);
+          const int cls = m <= kMaxGroup ? m - 1 : kMaxGroup;
+          const double ytx_cur = lane < m ? a.ytx[j0 + lane] : 0.0;
+          double loc[2 * kPassCols], part[2 * kPassCols];
+#pragma unroll
+          for (int i = 0; i < 2 * kPassCols; ++i) loc[i] = part[i] = 0.0;
+          switch (m) {
+            case 1: block_sum_to<2>(loc, part, redg, kPoller); break;
+            case 2: block_sum_to<4>(loc, part, redg, kPoller); break;
+            case 3:
+            case 4: block_sum_to<8>(loc, part, redg, kPoller); break;
+            default: block_sum_to<2 * kPassCols>(loc, part, redg, kPoller); break;
+          }
           // device-wide reduction of the pass's 2m partials, then one Newton /
           // trust-region step (Eq. 4) per column, lane c for column j0 + c
-          double tot[2 * kMaxGroup];
-          const int cls = m - 1;
+          double tot[2 * kPassCols];
           uint32_t sq = gseq[0];
 #pragma unroll
-          for (int c = 1; c < kMaxGroup; ++c)
+          for (int c = 1; c < kSlotClasses; ++c)
             if (cls == c) sq = gseq[c];
           uint64_t* s1 = a.slots + cls * kSlots1PerClass;
           uint64_t* s2 = a.slots2 + cls * kSlots2PerClass;
 #pragma unroll
-          for (int i = 0; i < 2 * kMaxGroup; ++i) tot[i] = 0.0;
+          for (int i = 0; i < 2 * kPassCols; ++i) tot[i] = 0.0;
           bool okr;
-          switch (m) {   // one width per slot class, fixed at compile time
-            case 1: okr = allreduce2_wave<2>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
+          switch (cls) {   // one width per slot class, fixed at compile time
+            case 0: okr = allreduce2_wave<2>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
 #if SCCS_MAX_GROUP >= 2
-            case 2: okr = allreduce2_wave<4>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
+            case 1: okr = allreduce2_wave<4>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
 #endif
 #if SCCS_MAX_GROUP >= 3
-            case 3: okr = allreduce2_wave<6>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
+            case 2: okr = allreduce2_wave<6>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
 #endif
-            default: okr = allreduce2_wave<2 * kMaxGroup>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
+#if SCCS_MAX_GROUP >= 4
+            case 3: okr = allreduce2_wave<8>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
+#endif
+            default: okr = allreduce2_wave<2 * kPassCols>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
           }
 
           double Gc = 0.0, Hc = 0.0;
 #pragma unroll
-          for (int i = 0; i < kMaxGroup; ++i)
+          for (int i = 0; i < kPassCols; ++i)
             if (lane == i) {
               Gc = tot[2 * i];
               Hc = tot[2 * i + 1];
@@ -963,12 +1143,23 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
               d = fmin(fmax(dv, -tr), tr);
             }
           }
-          // a merged pass keeps its second group only if no column of the first
-          // group that shares a patient with it moved; else that group is
-          // visited again, alone, in the next pass (its sums are discarded)
-          const uint32_t cmask = desc_cmask(cur.d);
-          const bool rej = cur.n == 2 && __ballot(lane < ma && d != 0.0 && ((cmask >> lane) & 1u)) != 0ull;
-          const int mc = rej ? ma : m;   // columns whose step is taken
+          // the first group of the pass with a linked column that moved, and
+          // the groups after it, keep no step (their sums are discarded); they
+          // are visited again in the next pass
+          const uint32_t moved_all = (uint32_t)__ballot(lane < m && d != 0.0);
+          int na = cur.n, mc = m;   // groups and columns whose steps are taken
+          bool open = true;
+#pragma unroll
+          for (int k = 1; k < kPassGroups; ++k) {
+            if (open && k < cur.n) {
+              const int off = desc_j0(cur.D[k]) - j0;
+              if (desc_links(cur.D[k], off) & moved_all) {
+                na = k;
+                mc = off;
+                open = false;
+              }
+            }
+          }
           if (lane >= mc) {
             d = 0.0;
             bad = 0;
@@ -979,7 +1170,7 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
             if (!isfinite(nb)) { bad = 1; d = 0.0; }
             else sbeta[j0 + lane] = nb;
           }
-          if (lane < kMaxGroup) {
+          if (lane < kPassCols) {
             const double em1 = expm1(d);
             s_ed[lane] = 1.0 + em1;
             s_em1[lane] = em1;
@@ -990,51 +1181,33 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
             bci[0] = okr ? 1 : 0;
             bci[1] = any_bad ? 1 : 0;
             bci[2] = moved != 0ull ? 1 : 0;
-            bci[3] = rej ? 1 : 0;
+            bci[3] = na;
           }
           mv_cols = okr ? mc : 0;
           mv_val = (uint32_t)moved;
-          n_rej += rej ? 1 : 0;
+          n_rej += na < cur.n ? 1 : 0;
           n_zero += mv_cols - __popcll(moved);
-        }
-        __syncthreads();
+          __syncthreads();   // the workers' plan of the pass after next is in LDS
 #pragma unroll
-        for (int c = 0; c < kMaxGroup; ++c)
-          if (m - 1 == c) ++gseq[c];
-        if (!bci[0]) { ok = false; break; }
-        if (bci[1]) { status = SCCS_ERR_NUMERIC; ok = false; break; }
-        const bool rejected = __builtin_amdgcn_readfirstlane(bci[3]) != 0;
-        if (worker) {
-          if (bci[2]) {
-            phase_b_cached<WT>(a, cur.p[0], c_cur[0], cf);
-            // a rejected second group is left untouched
-            if (cur.n == 2 && !rejected) phase_b_cached<WT>(a, cur.p[1], c_cur[1], Coef{s_ed + ma, s_em1 + ma});
-          }
-        } else {
+          for (int c = 0; c < kSlotClasses; ++c)
+            if (cls == c) ++gseq[c];
+          if (!bci[0]) { ok = false; break; }
+          if (bci[1]) { status = SCCS_ERR_NUMERIC; ok = false; break; }
           // while the workers update: record which columns moved (no pass
           // reads these bits before the next sweep); take the plan of the
           // pass after next from the workers
           if (lane == 0 && mv_cols > 0) set_bits(s_mv, j0, mv_cols, mv_val);
           nn.n = (int)__builtin_amdgcn_readfirstlane(s_nn[0]);
-          nn.d = __builtin_amdgcn_readfirstlane(s_nn[1]);
-        }
-        __syncthreads();
-        par ^= 1;
-        if (rejected) {
-          // the second group alone, from fresh data; nxt and the passes after
-          // it stay as planned (their speculative gathers are repeated)
-          cur.s += 1;
-          cur.n = 1;
-          cur.d = (uint32_t)(j0 + ma) | ((uint32_t)desc_mnext(cur.d) << 13) | (7u << 16);
-          cur.p[0] = cur.p[1];
-          c_cur[0].valid = false;
-        } else {
-          cur = nxt;
-          c_cur[0] = c_nxt[0];
-          c_cur[1] = c_nxt[1];
-          nxt = nn;
-          d_nn = d_nnn;
-          if (nxt.n == 0) nxt.s = NG;
+#pragma unroll
+          for (int k = 0; k < kPassGroups; ++k) nn.D[k] = __builtin_amdgcn_readfirstlane(s_nn[1 + k]);
+          __syncthreads();
+          if (na < cur.n) {
+            drop_groups(cur, na);
+          } else {
+            cur = nxt;
+            nxt = nn;
+            if (nxt.n == 0) nxt.s = NG;
+          }
         }
       }
     } else {
@@ -1222,7 +1395,7 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
       a.ctrl->converged = converged;
       a.ctrl->loglik = L;
       a.ctrl->logpost = P;
-      for (int c = 0; c < kMaxGroup; ++c) a.ctrl->gseq[c] = gseq[c];
+      for (int c = 0; c < kSlotClasses; ++c) a.ctrl->gseq[c] = gseq[c];
       a.ctrl->oseq = oseq;
       a.ctrl->since_refresh = since_refresh;
       if (status != SCCS_OK) a.ctrl->status = status;

@@ -21,9 +21,9 @@ int host_threads() {
 
 // f(lo, hi) over [0, n) split into contiguous chunks, one per thread.
 template <typename F>
-void parallel_ranges(int64_t n, F f) {
-  const int T = host_threads();
-  if (n < 1 << 16 || T == 1) {
+void parallel_ranges(int64_t n, F f, int max_threads = 1 << 30, int64_t min_n = 1 << 16) {
+  const int T = std::max(1, std::min(host_threads(), max_threads));
+  if (n < min_n || T == 1) {
     f((int64_t)0, n);
     return;
   }
@@ -160,26 +160,29 @@ void build_layout(const sccs_problem* p, int32_t G, Layout& L, int32_t tile_nnz,
   const int32_t NG = (int32_t)L.gcol.size() - 1;
   L.n_groups = NG;
 
-  // pass descriptors: which columns of group g share a patient with g + 1
+  // pass descriptors: which of the kLinkCols columns before group g share a
+  // patient with g (blocks of groups in parallel, one patient stamp per
+  // thread, at most about 256 MB of stamps)
   L.gdesc.assign((size_t)NG, 0u);
   if (J < kDescMaxCols) {
-    std::vector<int32_t> stamp((size_t)N, -1);
-    for (int32_t g = 0; g < NG; ++g) {
-      const uint32_t j0 = (uint32_t)L.gcol[g], m = (uint32_t)(L.gcol[g + 1] - L.gcol[g]);
-      uint32_t mnext = 7u, cmask = 0u;
-      if (g + 1 < NG) {
-        mnext = (uint32_t)(L.gcol[g + 2] - L.gcol[g + 1]);
-        for (int32_t j = L.gcol[g + 1]; j < L.gcol[g + 2]; ++j)
-          for (int64_t e = p->col_ptr[j]; e < p->col_ptr[j + 1]; ++e) stamp[era_pid[p->row_idx[e]]] = g + 1;
-        for (uint32_t c = 0; c < m; ++c) {
-          const int32_t j = (int32_t)(j0 + c);
+    const int stamp_threads = (int)std::max<int64_t>(1, ((int64_t)256 << 20) / (4 * (int64_t)N + 1));
+    parallel_ranges(NG, [&](int64_t glo, int64_t ghi) {
+      std::vector<int32_t> stamp((size_t)N, -1);
+      for (int64_t g = glo; g < ghi; ++g) {
+        const int32_t j0 = L.gcol[g], m = L.gcol[g + 1] - L.gcol[g];
+        for (int32_t j = j0; j < j0 + m; ++j)
+          for (int64_t e = p->col_ptr[j]; e < p->col_ptr[j + 1]; ++e) stamp[era_pid[p->row_idx[e]]] = (int32_t)g;
+        uint32_t lmask = 0u;
+        for (int32_t i = 0; i < kLinkCols; ++i) {
+          const int32_t c = j0 - kLinkCols + i;
+          if (c < 0) continue;
           bool hit = false;
-          for (int64_t e = p->col_ptr[j]; e < p->col_ptr[j + 1] && !hit; ++e) hit = stamp[era_pid[p->row_idx[e]]] == g + 1;
-          if (hit) cmask |= 1u << c;
+          for (int64_t e = p->col_ptr[c]; e < p->col_ptr[c + 1] && !hit; ++e) hit = stamp[era_pid[p->row_idx[e]]] == g;
+          if (hit) lmask |= 1u << i;
         }
+        L.gdesc[g] = (uint32_t)j0 | ((uint32_t)m << kDescWidthShift) | (lmask << kDescLinkShift);
       }
-      L.gdesc[g] = j0 | (m << 13) | (mnext << 16) | (cmask << 19);
-    }
+    }, stamp_threads, 64);
   }
 
   // cwb[j*(G+1) + b]: first CSC position of column j at or after workgroup b's eras

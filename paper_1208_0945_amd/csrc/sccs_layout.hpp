@@ -28,11 +28,11 @@
 // with c the column's index within its group.
 //
 // Pass descriptors.  gdesc[g] packs what the sweep needs to decide, at run
-// time, whether group g+1 can share group g's reduction (see
-// sccs_kernels.hpp): g's first column (bits 0-12), its width (bits 13-15),
-// the width of group g+1 (bits 16-18; 7 when g is the last group) and a mask
-// (bits 19-22) whose bit c is set when column c of g shares a patient with
-// group g+1.
+// time, whether group g can join a pass that starts with earlier groups (see
+// sccs_kernels.hpp): g's first column j0 (bits 0-12), its width (bits
+// 13-15) and a link mask (kLinkCols bits from bit 16) whose bit i is set
+// when column j0 - kLinkCols + i (>= 0) shares a patient with some column of
+// g.
 #pragma once
 #include <cstdint>
 #include <string>

@@ -25,6 +25,8 @@ extern "C" int layout_probe(const sccs_problem* p, int G, int tile_nnz, int max_
   return 0;
 }
 
+extern "C" int link_cols() { return sccs::kLinkCols; }
+
 extern "C" int ytx_probe(const sccs_problem* p, double* out) {
   std::vector<double> y;
   sccs::host_ytx(p, p->patient_weight, y);

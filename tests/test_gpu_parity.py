@@ -172,19 +172,20 @@ def test_zipf_laplace_merged_form(sccs, n_workgroups, tile_nnz, max_group):
     assert np.array_equal(beta == 0.0, ref["beta"] == 0.0)
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_merged_passes_match_plain_order(sccs, precision):
-    """Merged passes (two column groups in one reduction when the columns
-    linking them are predicted to stay put) against one pass per group: the
-    same beta bit for bit after every sweep, also after a prior change that
-    makes predicted-quiet columns move (merges rejected and the second group
-    visited again); merges and rejections both occur; FP64 beta equals the
-    oracle's for the same prior chain."""
+@pytest.mark.parametrize("precision,max_group", [(0, 0), (1, 0), (0, 1)])
+def test_merged_passes_match_plain_order(sccs, precision, max_group):
+    """Merged passes (consecutive column groups in one reduction when the
+    columns linking them are predicted to stay put) against one pass per
+    group: the same beta bit for bit after every sweep, also after a prior
+    change that makes predicted-quiet columns move (merges rejected and the
+    rejected groups visited again); merges and rejections both occur, and
+    with one-column groups some passes hold more than two groups; FP64 beta
+    equals the oracle's for the same prior chain."""
     prob = zipf_small()
     chain = [(0.05, 12), (5.0, 8)]
     betas, stats = {}, {}
     for merge in (0, 1):
-        with sccs.Handle(prob, precision=precision, merge_passes=merge) as h:
+        with sccs.Handle(prob, precision=precision, merge_passes=merge, max_group=max_group) as h:
             seq, st = [], []
             for var, n in chain:
                 h.set_prior(2, var)
@@ -198,6 +199,9 @@ def test_merged_passes_match_plain_order(sccs, precision):
     print("passes/rejects/zero steps per sweep, merged:", stats[1], "plain:", stats[0][0])
     assert len({p for p, _, _ in stats[0]}) == 1 and all(r == 0 for _, r, _ in stats[0])
     assert sum(p for p, _, _ in stats[1]) < sum(p for p, _, _ in stats[0])
+    if max_group == 1:
+        n_groups = stats[0][0][0]
+        assert 2 * min(p for p, _, _ in stats[1]) < n_groups, "some pass holds three groups or more"
     assert sum(r for _, r, _ in stats[1]) > 0
     # a zero step leaves beta_j unchanged (not conversely: a step can be lost
     # in rounding); both forms count the same zero steps

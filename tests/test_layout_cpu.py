@@ -166,9 +166,10 @@ def test_host_ytx(probe):
 
 @pytest.mark.parametrize("max_group", [1, 2, 4])
 def test_pass_descriptors(probe, max_group):
-    """Pass descriptors: first column and width of each group, width of the
-    next group (7 after the last), and the mask of the group's columns that
-    share a patient with the next group -- against sets of patients."""
+    """Pass descriptors: first column and width of each group, and the mask
+    of the L columns just before the group that share a patient with it
+    (bit i for column j0 - L + i; L = columns per merged pass - 1) --
+    against sets of patients."""
     prob = synth.zipf_problem("desc", 3000, 70, 0.03, seed_path=(11, 200 + max_group))
     J = prob.n_cols
     gdesc = np.zeros(J, np.uint32)
@@ -177,19 +178,18 @@ def test_pass_descriptors(probe, max_group):
     NG = len(gcol) - 1
     era_pid = np.repeat(np.arange(prob.n_patients), np.diff(prob.patient_ptr))
     pats = [set(era_pid[prob.column(j)].tolist()) for j in range(J)]
-    n_linked = 0
+    L = probe.link_cols()
+    assert 1 <= L <= 7
+    n_linked = n_window = 0
     for g in range(NG):
         d = int(gdesc[g])
-        assert d & 0x1FFF == gcol[g]
-        assert (d >> 13) & 7 == gcol[g + 1] - gcol[g]
-        if g + 1 < NG:
-            assert (d >> 16) & 7 == gcol[g + 2] - gcol[g + 1]
-            nxt = set().union(*(pats[j] for j in range(gcol[g + 1], gcol[g + 2])))
-            mask = sum(1 << c for c, j in enumerate(range(gcol[g], gcol[g + 1])) if pats[j] & nxt)
-        else:
-            assert (d >> 16) & 7 == 7
-            mask = 0
-        assert (d >> 19) & 15 == mask, g
-        assert d >> 23 == 0
-        n_linked += mask != 0
-    assert 0 < n_linked < NG, "both linked and independent neighbours should occur"
+        j0 = gcol[g]
+        assert d & 0x1FFF == j0
+        assert (d >> 13) & 7 == gcol[g + 1] - j0
+        mine = set().union(*(pats[j] for j in range(j0, gcol[g + 1])))
+        mask = sum(1 << i for i in range(L) if j0 - L + i >= 0 and pats[j0 - L + i] & mine)
+        assert (d >> 16) & ((1 << L) - 1) == mask, g
+        assert d >> (16 + L) == 0
+        n_linked += bin(mask).count("1")
+        n_window += min(L, j0)
+    assert 0 < n_linked < n_window, "both linked and independent columns should occur"
