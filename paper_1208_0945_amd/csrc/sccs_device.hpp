@@ -11,6 +11,7 @@ constexpr int kBlock = 512;              // threads per persistent workgroup
 constexpr int kWaves = kBlock / 64;      // wavefronts per workgroup
 constexpr int kMaxWorkgroups = 256;       // two-level reduction: <= 32 members per group
 constexpr int kGroups = 8;               // reduction groups (one per XCD under round-robin placement)
+static_assert(kMaxWorkgroups <= 32 * kGroups && kGroups <= 8, "level-1 members in lanes 0..31, group totals in lanes 0..7");
 constexpr int kPoller = kWaves - 1;      // wave that runs the device-wide reduction
 constexpr int kSlotWords = 16;           // one 128-byte line per reduction slot
 constexpr int kReplicas = 8;             // copies of the group totals
