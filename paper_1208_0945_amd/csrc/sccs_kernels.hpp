@@ -1193,7 +1193,8 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
             else sbeta[j0 + lane] = nb;
           }
           if (lane < kPassCols) {
-            const double em1 = expm1(d);
+            double em1 = 0.0;   // most late-sweep steps are exactly zero
+            if (d != 0.0) em1 = expm1(d);
             s_ed[lane] = 1.0 + em1;
             s_em1[lane] = em1;
           }
@@ -1345,7 +1346,8 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
             }
           }
           if (lane < kMaxGroup) {
-            const double em1 = expm1(d);
+            double em1 = 0.0;   // most late-sweep steps are exactly zero
+            if (d != 0.0) em1 = expm1(d);
             s_ed[lane] = 1.0 + em1;
             s_em1[lane] = em1;
           }
