@@ -14,7 +14,11 @@ constexpr int kGroups = 8;               // reduction groups (one per XCD under 
 static_assert(kMaxWorkgroups <= 32 * kGroups && kGroups <= 8, "level-1 members in lanes 0..31, group totals in lanes 0..7");
 constexpr int kPoller = kWaves - 1;      // wave that runs the device-wide reduction
 constexpr int kSlotWords = 16;           // one 128-byte line per reduction slot
-constexpr int kReplicas = 8;             // copies of the group totals
+#ifndef SCCS_REPLICAS
+#define SCCS_REPLICAS 8
+#endif
+constexpr int kReplicas = SCCS_REPLICAS;  // copies of the group totals
+static_assert(kReplicas >= 1 && kReplicas <= 64, "one leader lane per copy");
 constexpr int kMaxJ = 6144;              // beta, trust, beta_prev live in LDS
 static_assert(kMaxJ < kDescMaxCols, "every column index fits in a pass descriptor");
 constexpr uint64_t kSign = 0x8000000000000000ull;
