@@ -1235,8 +1235,8 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
       }
     } else {
       // one pass per column group (few zero steps to exploit, or merging
-      // off); the moved bits are left as they are (the first merged sweep
-      // brings them up to date)
+      // off); the moved bits are kept up to date as well, so that a
+      // following merged-pass launch starts with a prediction
       // pipeline start: indices of groups 0 and 1; nothing speculated
       Pf pf_cur, pf_next;
       {
@@ -1247,6 +1247,7 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
         pf_tile(a, t0, t1, pf_next);
       }
       Cache c_cur, c_next;
+      uint32_t mv_val = 0u;   // poller: the last group's moved columns
       c_cur.valid = false;
       // group bounds gcol[g], gcol[g+1], gcol[g+2] roll through registers, each
       // loaded two groups before it is needed
@@ -1359,6 +1360,7 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
             bci[2] = moved != 0ull ? 1 : 0;
           }
           n_zero += okr ? m - __popcll(moved) : 0;
+          mv_val = (uint32_t)moved;
         }
         __syncthreads();
 #pragma unroll
@@ -1366,7 +1368,11 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
           if (m - 1 == c) ++gseq[c];
         if (!bci[0]) { ok = false; break; }
         if (bci[1]) { status = SCCS_ERR_NUMERIC; ok = false; break; }
-        if (worker && bci[2]) phase_b_cached<WT>(a, pf_cur, c_cur, cf);
+        if (worker) {
+          if (bci[2]) phase_b_cached<WT>(a, pf_cur, c_cur, cf);
+        } else if (lane == 0) {
+          set_bits(s_mv, j0, m, mv_val);   // while the workers update
+        }
         __syncthreads();
         pf_cur = pf_next;
         pf_next = pf_next2;
