@@ -1236,68 +1236,100 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
     } else {
       // one pass per column group (few zero steps to exploit, or merging
       // off); the moved bits are kept up to date as well, so that a
-      // following merged-pass launch starts with a prediction
-      // pipeline start: indices of groups 0 and 1; nothing speculated
-      Pf pf_cur, pf_next;
-      {
-        int t0, t1;
-        pf_range(a, 0, t0, t1);
-        pf_tile(a, t0, t1, pf_cur);
-        pf_range(a, NG > 1 ? 1 : 0, t0, t1);
-        pf_tile(a, t0, t1, pf_next);
-      }
-      Cache c_cur, c_next;
-      uint32_t mv_val = 0u;   // poller: the last group's moved columns
-      c_cur.valid = false;
-      // group bounds gcol[g], gcol[g+1], gcol[g+2] roll through registers, each
-      // loaded two groups before it is needed
-      int j0 = a.gcol[0], gc1 = a.gcol[1], gc2 = NG > 1 ? a.gcol[2] : gc1;
-      int m = gc1 - j0;
-      double ytx_cur = (wave == kPoller && lane < m) ? a.ytx[j0 + lane] : 0.0;
-      __syncthreads();
-      for (int g = 0; g < NG; ++g) {
-        unsigned* bits_cur = (g & 1) ? bits1 : bits0;
-        unsigned* bits_prev = (g & 1) ? bits0 : bits1;
-        const bool has_next = g + 1 < NG;
-        int nt0 = 0, nt1 = 0;
-        if (g + 2 < NG) pf_range(a, g + 2, nt0, nt1);
-        const int gc3 = g + 3 <= NG ? ld_idx(a.gcol + g + 3) : gc2;
-        const int j0n = gc1;
-        const int mn = has_next ? gc2 - gc1 : 0;
-        const double ytx_next = (wave == kPoller && lane < mn) ? a.ytx[j0n + lane] : 0.0;
+      // following merged-pass launch starts with a prediction.  As in the
+      // merged-pass form, the workers and the poller run the group sequence
+      // in loops of their own with the same barriers.
+      const bool worker_u = __builtin_amdgcn_readfirstlane(tid >> 6) < kWorkers;
+      if (worker_u) {
+        // pipeline start: indices of groups 0 and 1; nothing speculated
+        Pf pf_cur, pf_next;
+        {
+          int t0, t1;
+          pf_range(a, 0, t0, t1);
+          pf_tile(a, t0, t1, pf_cur);
+          pf_range(a, NG > 1 ? 1 : 0, t0, t1);
+          pf_tile(a, t0, t1, pf_next);
+        }
+        Cache c_cur, c_next;
+        c_cur.valid = false;
+        // group bounds gcol[g], gcol[g+1], gcol[g+2] roll through registers,
+        // each loaded two groups before it is needed
+        int j0 = a.gcol[0], gc1 = a.gcol[1], gc2 = NG > 1 ? a.gcol[2] : gc1;
+        int m = gc1 - j0;
+        __syncthreads();
+        for (int g = 0; g < NG; ++g) {
+          unsigned* bits_cur = (g & 1) ? bits1 : bits0;
+          unsigned* bits_prev = (g & 1) ? bits0 : bits1;
+          const bool has_next = g + 1 < NG;
+          int nt0 = 0, nt1 = 0;
+          if (g + 2 < NG) pf_range(a, g + 2, nt0, nt1);
+          const int gc3 = g + 3 <= NG ? ld_idx(a.gcol + g + 3) : gc2;
+          const int mn = has_next ? gc2 - gc1 : 0;
 
-        // phase A: validate the speculative first tile, then accumulate
-        Acc<kMaxGroup> acc;
-        acc.zero();
-        if (worker) {
+          // phase A: validate the speculative first tile, then accumulate
+          Acc<kMaxGroup> acc;
+          acc.zero();
           if (!c_cur.valid || (g > 0 && first_tile_stale(pf_cur, bits_prev, p0))) gather_first<WT>(a, pf_cur, c_cur);
           phase_a_cached<WT>(a, pf_cur, c_cur, acc, bits_cur, p0, 0u);
-        }
-        double loc[2 * kMaxGroup], part[2 * kMaxGroup];
+          double loc[2 * kMaxGroup], part[2 * kMaxGroup];
 #pragma unroll
-        for (int i = 0; i < kMaxGroup; ++i) {
-          loc[2 * i] = acc.g[i];
-          loc[2 * i + 1] = acc.h[i];
-          part[2 * i] = part[2 * i + 1] = 0.0;
-        }
-        switch (m) {   // sum only the words of the group's columns (m is uniform)
-          case 1: block_sum_to<2>(loc, part, redg, kPoller); break;
+          for (int i = 0; i < kMaxGroup; ++i) {
+            loc[2 * i] = acc.g[i];
+            loc[2 * i + 1] = acc.h[i];
+          }
+          switch (m) {   // sum only the words of the group's columns (m is uniform)
+            case 1: block_sum_to<2>(loc, part, redg, kPoller); break;
 #if SCCS_MAX_GROUP >= 2
-          case 2: block_sum_to<4>(loc, part, redg, kPoller); break;
+            case 2: block_sum_to<4>(loc, part, redg, kPoller); break;
 #endif
-          default: block_sum_to<2 * kMaxGroup>(loc, part, redg, kPoller); break;
-        }
-        Pf pf_next2;
-        pf_next2.t = pf_next2.t1 = 0;
-        c_next.valid = false;
-        if (worker) {
+            default: block_sum_to<2 * kMaxGroup>(loc, part, redg, kPoller); break;
+          }
           // in the shadow of the reduction: clear the bitmap of group g+1,
           // gather group g+1 speculatively, load indices of group g+2
-          unsigned* bits_next = bits_prev;
-          for (int i = tid; i < a.nbits; i += kWorkers * 64) bits_next[i] = 0u;
+          Pf pf_next2;
+          pf_next2.t = pf_next2.t1 = 0;
+          c_next.valid = false;
+          for (int i = tid; i < a.nbits; i += kWorkers * 64) bits_prev[i] = 0u;
           if (has_next) gather_first<WT>(a, pf_next, c_next);
           if (g + 2 < NG) pf_tile(a, nt0, nt1, pf_next2);
-        } else {
+          __syncthreads();   // the poller's step is in LDS
+#pragma unroll
+          for (int c = 0; c < kMaxGroup; ++c)
+            if (m - 1 == c) ++gseq[c];
+          if (!bci[0]) { ok = false; break; }
+          if (bci[1]) { status = SCCS_ERR_NUMERIC; ok = false; break; }
+          if (bci[2]) phase_b_cached<WT>(a, pf_cur, c_cur, cf);
+          __syncthreads();
+          pf_cur = pf_next;
+          pf_next = pf_next2;
+          c_cur = c_next;
+          j0 = gc1;
+          m = mn;
+          gc1 = gc2;
+          gc2 = gc3;
+        }
+      } else {
+        uint32_t mv_val = 0u;   // the last group's moved columns
+        int j0 = a.gcol[0], gc1 = a.gcol[1], gc2 = NG > 1 ? a.gcol[2] : gc1;
+        int m = gc1 - j0;
+        double ytx_cur = lane < m ? a.ytx[j0 + lane] : 0.0;
+        __syncthreads();
+        for (int g = 0; g < NG; ++g) {
+          const bool has_next = g + 1 < NG;
+          const int gc3 = g + 3 <= NG ? ld_idx(a.gcol + g + 3) : gc2;
+          const int j0n = gc1;
+          const int mn = has_next ? gc2 - gc1 : 0;
+          const double ytx_next = lane < mn ? a.ytx[j0n + lane] : 0.0;
+          double loc[2 * kMaxGroup], part[2 * kMaxGroup];
+#pragma unroll
+          for (int i = 0; i < 2 * kMaxGroup; ++i) loc[i] = part[i] = 0.0;
+          switch (m) {
+            case 1: block_sum_to<2>(loc, part, redg, kPoller); break;
+#if SCCS_MAX_GROUP >= 2
+            case 2: block_sum_to<4>(loc, part, redg, kPoller); break;
+#endif
+            default: block_sum_to<2 * kMaxGroup>(loc, part, redg, kPoller); break;
+          }
           // device-wide reduction of the group's 2m partials, then one
           // Newton / trust-region step (Eq. 4) per column, lane c for column
           // j0 + c (the columns are independent)
@@ -1361,27 +1393,20 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
           }
           n_zero += okr ? m - __popcll(moved) : 0;
           mv_val = (uint32_t)moved;
-        }
-        __syncthreads();
+          __syncthreads();
 #pragma unroll
-        for (int c = 0; c < kMaxGroup; ++c)
-          if (m - 1 == c) ++gseq[c];
-        if (!bci[0]) { ok = false; break; }
-        if (bci[1]) { status = SCCS_ERR_NUMERIC; ok = false; break; }
-        if (worker) {
-          if (bci[2]) phase_b_cached<WT>(a, pf_cur, c_cur, cf);
-        } else if (lane == 0) {
-          set_bits(s_mv, j0, m, mv_val);   // while the workers update
+          for (int c = 0; c < kMaxGroup; ++c)
+            if (m - 1 == c) ++gseq[c];
+          if (!bci[0]) { ok = false; break; }
+          if (bci[1]) { status = SCCS_ERR_NUMERIC; ok = false; break; }
+          if (lane == 0) set_bits(s_mv, j0, m, mv_val);   // while the workers update
+          __syncthreads();
+          ytx_cur = ytx_next;
+          j0 = j0n;
+          m = mn;
+          gc1 = gc2;
+          gc2 = gc3;
         }
-        __syncthreads();
-        pf_cur = pf_next;
-        pf_next = pf_next2;
-        c_cur = c_next;
-        ytx_cur = ytx_next;
-        j0 = j0n;
-        m = mn;
-        gc1 = gc2;
-        gc2 = gc3;
       }
     }
     if (!ok) break;
