@@ -777,7 +777,8 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchArgs A) {
           }
         }
         if (lane < FM) {
-          const double em1 = expm1(d);
+          double em1 = 0.0;   // zero steps are common once fits converge
+          if (d != 0.0) em1 = expm1(d);
           s_ed[lane] = 1.0 + em1;
           s_em1[lane] = em1;
         }
