@@ -385,7 +385,10 @@ def main():
         "schedule": {"passes_per_sweep_mean": float(np.mean([q[0] for q in fp["passes"]])),
                      "passes_last_sweep": int(fp["passes"][-1][0]),
                      "rejected_merges_per_sweep_mean": float(np.mean([q[1] for q in fp["passes"]])),
-                     "zero_step_share_mean": float(np.mean([q[2] for q in fp["passes"]])) / prob.n_cols},
+                     "zero_step_share_mean": float(np.mean([q[2] for q in fp["passes"]])) / prob.n_cols,
+                     # each pass is one device-wide reduction: the serial chain
+                     # that bounds the sweep, not HBM bandwidth
+                     "us_per_pass_mean": 1e3 * float(np.sum(fp["kernel_ms"])) / float(np.sum([q[0] for q in fp["passes"]]))},
     }
     if not args.no_mixed:
         mx = run_form(sccs, prob, 1, args.steps, args.warmup, c, p)
