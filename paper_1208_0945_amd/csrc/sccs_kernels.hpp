@@ -994,6 +994,9 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
 #pragma unroll
         for (int k = 0; k < kPassGroups; ++k) c_cur[k].valid = c_nxt[k].valid = false;
         int par = 0;
+        // the previous pass changed the state (some step was nonzero): only
+        // then can a speculative gather be stale
+        bool prev_moved = true;
         while (cur.s < NG) {
           unsigned* bits_cur = par ? bits1 : bits0;
           unsigned* bits_prev = par ? bits0 : bits1;
@@ -1019,7 +1022,8 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
 #pragma unroll
           for (int k = 0; k < kPassGroups; ++k) {
             if (k < cur.n) {
-              if (!c_cur[k].valid || first_tile_stale(cur.p[k], bits_prev, p0)) gather_first<WT>(a, cur.p[k], c_cur[k]);
+              if (!c_cur[k].valid || (prev_moved && first_tile_stale(cur.p[k], bits_prev, p0)))
+                gather_first<WT>(a, cur.p[k], c_cur[k]);
               phase_a_cached<WT>(a, cur.p[k], c_cur[k], acc, bits_cur, p0, (uint32_t)(desc_j0(cur.D[k]) - j0));
             }
           }
@@ -1075,7 +1079,8 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
           if (!bci[0]) { ok = false; break; }
           if (bci[1]) { status = SCCS_ERR_NUMERIC; ok = false; break; }
           const int na = __builtin_amdgcn_readfirstlane(bci[3]);   // groups whose steps are taken
-          if (bci[2]) {
+          prev_moved = __builtin_amdgcn_readfirstlane(bci[2]) != 0;
+          if (prev_moved) {
 #pragma unroll
             for (int k = 0; k < kPassGroups; ++k)
               if (k < na) {
@@ -1256,6 +1261,7 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
         // each loaded two groups before it is needed
         int j0 = a.gcol[0], gc1 = a.gcol[1], gc2 = NG > 1 ? a.gcol[2] : gc1;
         int m = gc1 - j0;
+        bool prev_moved = true;   // the previous group took a nonzero step
         __syncthreads();
         for (int g = 0; g < NG; ++g) {
           unsigned* bits_cur = (g & 1) ? bits1 : bits0;
@@ -1269,7 +1275,8 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
           // phase A: validate the speculative first tile, then accumulate
           Acc<kMaxGroup> acc;
           acc.zero();
-          if (!c_cur.valid || (g > 0 && first_tile_stale(pf_cur, bits_prev, p0))) gather_first<WT>(a, pf_cur, c_cur);
+          if (!c_cur.valid || (g > 0 && prev_moved && first_tile_stale(pf_cur, bits_prev, p0)))
+            gather_first<WT>(a, pf_cur, c_cur);
           phase_a_cached<WT>(a, pf_cur, c_cur, acc, bits_cur, p0, 0u);
           double loc[2 * kMaxGroup], part[2 * kMaxGroup];
 #pragma unroll
@@ -1298,7 +1305,8 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
             if (m - 1 == c) ++gseq[c];
           if (!bci[0]) { ok = false; break; }
           if (bci[1]) { status = SCCS_ERR_NUMERIC; ok = false; break; }
-          if (bci[2]) phase_b_cached<WT>(a, pf_cur, c_cur, cf);
+          prev_moved = __builtin_amdgcn_readfirstlane(bci[2]) != 0;
+          if (prev_moved) phase_b_cached<WT>(a, pf_cur, c_cur, cf);
           __syncthreads();
           pf_cur = pf_next;
           pf_next = pf_next2;
