@@ -54,9 +54,9 @@ def bytes_per_sweep(c, p, active, precision):
     return float(a + b)
 
 
-def run_form(sccs, prob, precision, steps, warmup, c, p):
+def run_form(sccs, prob, precision, steps, warmup, c, p, n_workgroups=0):
     import torch
-    h = sccs.Handle(prob, precision=precision)
+    h = sccs.Handle(prob, precision=precision, n_workgroups=n_workgroups)
     h.set_prior(sccs.PRIOR_LAPLACE, 2.0)
     beta_prev, _ = h.get_beta()
     for _ in range(warmup):
@@ -313,6 +313,13 @@ def main():
     ap.add_argument("--print-sha", action="store_true", help="print the sweep kernel's source hash and exit")
     ap.add_argument("--cv-max-sweeps", type=int, default=50)
     ap.add_argument("--cv-tol", type=float, default=1e-8)
+    # The single fit is bound by its chain of device-wide reductions, not by
+    # bandwidth: on mid, 128 persistent workgroups (16 per XCD, half the CUs)
+    # finish a sweep about 2 % sooner than one per CU, because each
+    # reduction has half the members.  0 = one workgroup per CU.
+    ap.add_argument("--workgroups", type=int, default=128)
+    # the mixed form (one pass per group throughout) is fastest on every CU
+    ap.add_argument("--mixed-workgroups", type=int, default=0)
     args = ap.parse_args()
     if args.print_sha:
         print(kernel_source_sha())
@@ -354,7 +361,7 @@ def main():
     print(f"[bench] generated {prob.summary()} in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     c, p = column_stats(prob)
 
-    fp = run_form(sccs, prob, 0, args.steps, args.warmup, c, p)
+    fp = run_form(sccs, prob, 0, args.steps, args.warmup, c, p, args.workgroups)
     print(f"[bench] fp64 done: {args.steps / fp['wall_s']:.1f} sweeps/s", file=sys.stderr, flush=True)
     ms = float(np.mean(fp["kernel_ms"]))
     achieved = float(np.mean(fp["bytes"])) / (ms * 1e-3) / 1e9
@@ -374,14 +381,15 @@ def main():
         "config": {"workload": f"mid SCCS: {prob.n_patients} patients, {prob.n_rows} eras, J={prob.n_cols} "
                                f"Zipf(1.1) drugs, {prob.nnz} nonzeros, Laplace lambda=1, FP64, one sweep per step",
                    "n_patients": prob.n_patients, "n_eras": prob.n_rows, "n_cols": prob.n_cols,
-                   "nnz": prob.nnz, "prior": "laplace", "variance": 2.0, "parallelism": "single GPU"},
+                   "nnz": prob.nnz, "prior": "laplace", "variance": 2.0, "parallelism": "single GPU",
+                   "n_workgroups": args.workgroups},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(ms),
                      "kernel": "k_ccd<double, *> (one-pass-per-group and merged-pass forms)", "kernel_ms_mean": ms,
                      "algo_bytes_per_launch": float(np.mean(fp["bytes"]))},
-        # device-wide reductions per sweep (column groups, two merged into one
-        # pass when predicted independent), merges undone per sweep, and the
-        # share of coordinates whose step was exactly zero
+        # device-wide reductions per sweep (column groups; consecutive groups
+        # share a pass when predicted independent), merges undone per sweep,
+        # and the share of coordinates whose step was exactly zero
         "schedule": {"passes_per_sweep_mean": float(np.mean([q[0] for q in fp["passes"]])),
                      "passes_last_sweep": int(fp["passes"][-1][0]),
                      "rejected_merges_per_sweep_mean": float(np.mean([q[1] for q in fp["passes"]])),
@@ -391,13 +399,14 @@ def main():
                      "us_per_pass_mean": 1e3 * float(np.sum(fp["kernel_ms"])) / float(np.sum([q[0] for q in fp["passes"]]))},
     }
     if not args.no_mixed:
-        mx = run_form(sccs, prob, 1, args.steps, args.warmup, c, p)
+        mx = run_form(sccs, prob, 1, args.steps, args.warmup, c, p, args.mixed_workgroups)
         err = float(np.max(np.abs(mx["beta"] - fp["beta"])) / max(np.max(np.abs(fp["beta"])), 1e-300))
         mms = float(np.mean(mx["kernel_ms"]))
         out["mixed"] = {"value": args.steps / mx["wall_s"], "unit": "sweeps/s",
                         "kernel_ms_mean": mms,
                         "achieved_GBs": float(np.mean(mx["bytes"])) / (mms * 1e-3) / 1e9,
                         "rel_err_vs_fp64_gpu": err,
+                        "n_workgroups": args.mixed_workgroups,
                         "sweeps_compared": args.steps + args.warmup}
         print(f"[bench] mixed done: {out['mixed']['value']:.1f} sweeps/s, rel err {err:.2e}",
               file=sys.stderr, flush=True)

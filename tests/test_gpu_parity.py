@@ -390,13 +390,15 @@ def test_no_nonzeros_and_single_patient(sccs):
     assert rel_inf(beta, ref["beta"]) <= FP64_TOL
 
 
-def test_full_size_mid_parity(sccs):
+@pytest.mark.parametrize("n_workgroups", [128, 0])
+def test_full_size_mid_parity(sccs, n_workgroups):
     """Full mid workload (2M patients, ~20M eras, J = 2000, Laplace lambda = 1)
-    in the benchmark's launch configuration: the first 3 sweeps against the
-    oracle, then g_j, h_j of sampled columns at the reached beta."""
+    in the benchmark's launch configuration (128 workgroups) and with one
+    workgroup per CU: the first 3 sweeps against the oracle, then g_j, h_j of
+    sampled columns at the reached beta."""
     prob = synth.mid()
     ref = oracle.ccd(prob, 2, 2.0, 3)
-    with sccs.Handle(prob) as h:
+    with sccs.Handle(prob, n_workgroups=n_workgroups) as h:
         h.set_prior(2, 2.0)
         h.sweep(3)
         beta, _ = h.get_beta()
