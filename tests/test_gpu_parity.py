@@ -411,6 +411,31 @@ def test_full_size_mid_parity(sccs, n_workgroups):
             assert abs(hh - ho) <= 1e-9 * abs(ho), (j, hh, ho)
 
 
+def test_full_size_mid_merged_passes_parity(sccs):
+    """Full mid workload in the benchmark's launch configuration and schedule
+    (128 workgroups, one sweep per launch) until the merged-pass form has run
+    a few sweeps: beta after 14 sweeps against the oracle's, the same exact
+    zeros, and g_j, h_j of sampled columns at the reached beta."""
+    prob = synth.mid()
+    ref = oracle.ccd(prob, 2, 2.0, 14)
+    with sccs.Handle(prob, n_workgroups=128) as h:
+        h.set_prior(2, 2.0)
+        passes = []
+        for _ in range(14):
+            h.sweep(1)
+            passes.append(h.pass_stats()[0])
+        beta, _ = h.get_beta()
+        assert passes[-1] < passes[0], passes   # the last launches merged groups
+        assert rel_inf(beta, ref["beta"]) <= FP64_TOL
+        assert np.array_equal(beta == 0.0, ref["beta"] == 0.0)
+        c = np.diff(prob.col_ptr)
+        for j in [int(np.argmax(c)), int(np.argsort(c)[len(c) // 2]), 1999]:
+            g, hh = h.grad_hess(j)
+            go, ho = oracle.grad_hess(prob, beta, j)
+            assert abs(g - go) <= 1e-9 * max(1.0, abs(ho)), (j, g, go)
+            assert abs(hh - ho) <= 1e-9 * abs(ho), (j, hh, ho)
+
+
 def test_autotuner_picks_a_candidate_and_its_schedule_is_exact(sccs):
     prob = zipf_small(n_patients=20000, n_cols=120, seed=9)
     best, table = sccs.tune(prob, sccs.PRIOR_LAPLACE, 2.0, n_sweeps=2)
