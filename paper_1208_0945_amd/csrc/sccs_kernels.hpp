@@ -76,20 +76,18 @@ __device__ __forceinline__ double wave_sum(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// Sum over lanes 0 .. L-1 (L = 8 or 32; the other lanes hold +0), returned
-// to every lane: the first three (L = 8) or five (L = 32) stages of
-// wave_sum, read from the last lane they fill.  The stages left out would
+// Sum over lanes 0 .. L-1 (L = 8, 16 or 32; the other lanes hold +0),
+// returned to every lane: the first three, four or five stages of wave_sum,
+// read from the last lane they fill.  The stages left out would
 // only add +0, so the value is wave_sum's, bit for bit.
 template <int L>
 __device__ __forceinline__ double wave_sum_lo(double v) {
-  static_assert(L == 8 || L == 32, "eight or thirty-two lanes");
+  static_assert(L == 8 || L == 16 || L == 32, "eight, sixteen or thirty-two lanes");
   v = dpp_add<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]
   v = dpp_add<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]
   v = dpp_add<0x141, 0xf>(v);  // row_half_mirror
-  if (L == 32) {
-    v = dpp_add<0x140, 0xf>(v);  // row_mirror
-    v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 -> rows 1, 3
-  }
+  if (L >= 16) v = dpp_add<0x140, 0xf>(v);  // row_mirror
+  if (L == 32) v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 -> rows 1, 3
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)b, L - 1);
   const int hi = __builtin_amdgcn_readlane((int)(b >> 32), L - 1);
@@ -187,9 +185,14 @@ __device__ bool allreduce2_wave(uint64_t* s1, uint64_t* s2, uint32_t seq, int G,
   if (b < ng) {
     const int member = b + lane * ng;
     if (!poll_tagged<NV>(L1 + (size_t)(member < G ? member : b) * kSlotWords, member < G, tag, v, ctrl)) return false;
-    // members sit in lanes 0..31 (G <= 32 ng)
+    // members sit in lanes 0..31 (G <= 32 ng), lanes 0..15 when G <= 16 ng
+    if (G <= 16 * ng) {
 #pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = wave_sum_lo<32>(v[i]);
+      for (int i = 0; i < NV; ++i) v[i] = wave_sum_lo<16>(v[i]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) v[i] = wave_sum_lo<32>(v[i]);
+    }
     if (lane < kReplicas) {
 #pragma unroll
       for (int i = 0; i < NV; ++i)
