@@ -232,6 +232,9 @@ int ora_ccd(const ora_problem* p, int32_t prior_kind, double var, double* beta,
       double G = 0.0, H = 0.0;
       for (int32_t t = 0; t < nt; ++t) {
         int32_t i = touched[t];
+        /* W_i = 0 adds nothing (also when all of the patient's eras have
+         * length 0, where den_i = 0 too and such a patient has n_i = 0) */
+        if (num[i] == 0.0) continue;
         double W = num[i] / den[i];
         G += wn[i] * W;
         H += wn[i] * W * (1.0 - W);

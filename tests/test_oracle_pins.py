@@ -393,3 +393,161 @@ def test_rel_logpost_and_dxbeta_criteria(oracle_lib):
     # warm start from a finished fit does not move (up to the tolerance)
     r4 = oracle_lib.ccd(prob, 1, 1.0, 1, beta0=r1["beta"], trust0=r1["trust"])
     assert np.max(np.abs(r4["beta"] - r1["beta"])) < 1e-3
+
+
+def test_golden_second_visits_follow_the_sequential_order(oracle_lib):
+    """Algorithm 1 visits coordinates one after the other: coordinate 1 sees
+    the weights that coordinate 0's step left behind, and sweep 2's first
+    visit sees both steps (hand-derived closed forms in exp(6/13))."""
+    with open(os.path.join(HERE, "golden", "two_patient.json")) as f:
+        fx = json.load(f)
+    P = fx["problem"]
+    cols = [P["row_idx"][P["col_ptr"][j]:P["col_ptr"][j + 1]] for j in range(2)]
+    prob = make(P["patient_ptr"], P["offset"], P["count"], cols)
+    sv = fx["second_visits_normal_var1"]
+    env = {"exp": math.exp, "log": math.log, "max": max, "min": min}
+    for k in ("E", "g1", "h1", "dbeta1", "trust1", "F", "logpost_sweep1", "W0_sweep2", "g0_sweep2",
+              "h0_sweep2", "dbeta0_sweep2"):
+        env[k] = eval(sv[k], {"__builtins__": {}}, env)
+    r = oracle_lib.ccd(prob, oracle_lib.PRIOR_NORMAL, 1.0, 2, want_trace=True)
+    tr = r["trace"]
+    assert tr[0, 1, 0] == pytest.approx(env["g1"], rel=1e-14)
+    assert tr[0, 1, 1] == pytest.approx(env["h1"], rel=1e-14)
+    assert tr[0, 1, 2] == pytest.approx(env["dbeta1"], rel=1e-14)
+    assert r["logpost_trace"][0] == pytest.approx(env["logpost_sweep1"], rel=1e-14)
+    assert tr[1, 0, 0] == pytest.approx(env["g0_sweep2"], rel=1e-13)
+    assert tr[1, 0, 1] == pytest.approx(env["h0_sweep2"], rel=1e-13)
+    assert tr[1, 0, 2] == pytest.approx(env["dbeta0_sweep2"], rel=1e-13)
+    r1 = oracle_lib.ccd(prob, oracle_lib.PRIOR_NORMAL, 1.0, 1)
+    assert r1["trust"][1] == pytest.approx(env["trust1"], rel=1e-14)
+    assert r1["beta"][1] == pytest.approx(env["dbeta1"], rel=1e-14)
+
+
+# ---------------------------------------------------------------- log prior
+
+def test_log_prior_hand_values(oracle_lib):
+    """Eq. 3 with constants dropped: Normal -sum b^2 / (2 var); Laplace
+    -lambda sum |b| with lambda = sqrt(2 / var)."""
+    b = [1.0, -2.0, 0.0]
+    assert oracle_lib.log_prior(oracle_lib.PRIOR_NORMAL, 0.5, b) == pytest.approx(-5.0, abs=1e-15)
+    assert oracle_lib.log_prior(oracle_lib.PRIOR_NORMAL, 2.0, b) == pytest.approx(-1.25, abs=1e-15)
+    assert oracle_lib.log_prior(oracle_lib.PRIOR_LAPLACE, 2.0, b) == pytest.approx(-3.0, abs=1e-15)    # lambda 1
+    assert oracle_lib.log_prior(oracle_lib.PRIOR_LAPLACE, 0.5, b) == pytest.approx(-6.0, abs=1e-15)    # lambda 2
+    assert oracle_lib.log_prior(oracle_lib.PRIOR_LAPLACE, 0.08, b) == pytest.approx(-15.0, abs=1e-13)  # lambda 5
+    assert oracle_lib.log_prior(oracle_lib.PRIOR_NONE, 1.0, b) == 0.0
+    rng = np.random.default_rng(8)
+    for _ in range(5):
+        beta = rng.normal(size=40) * (rng.random(40) < 0.5)
+        for kind in (0, 1, 2):
+            var = float(rng.uniform(0.01, 5.0))
+            assert oracle_lib.log_prior(kind, var, beta) == pytest.approx(defn.log_prior(kind, var, beta),
+                                                                        rel=1e-13, abs=1e-13)
+
+
+@pytest.mark.parametrize("kind,var", [(1, 0.5), (1, 2.0), (2, 2.0), (2, 0.5), (2, 0.05)])
+def test_log_prior_density_has_the_stated_variance(oracle_lib, kind, var):
+    """The prior's second argument is its variance (Laplace(0, var) included):
+    exp(log p) of one coordinate, normalised by numerical integration, has
+    mean 0 and variance var.  A Laplace rate of 1/var or 1/sqrt(var) fails."""
+    import scipy.integrate as si
+    lp0 = oracle_lib.log_prior(kind, var, [0.0])
+
+    def dens(b, power):
+        return b ** power * math.exp(oracle_lib.log_prior(kind, var, [b]) - lp0)
+    pieces = [(-math.inf, 0.0), (0.0, math.inf)]   # the Laplace kink sits at 0
+    Z = sum(si.quad(dens, lo, hi, args=(0,), epsabs=0, epsrel=1e-12)[0] for lo, hi in pieces)
+    M1 = sum(si.quad(dens, lo, hi, args=(1,), epsabs=0, epsrel=1e-12)[0] for lo, hi in pieces)
+    M2 = sum(si.quad(dens, lo, hi, args=(2,), epsabs=0, epsrel=1e-12)[0] for lo, hi in pieces)
+    assert abs(M1 / Z) < 1e-10
+    assert M2 / Z == pytest.approx(var, rel=1e-9)
+
+
+# ---------------------------------------------------------------- stopping rules
+
+def _sweep_betas(oracle_lib, prob, kind, var, n):
+    """beta after sweeps 0..n, rebuilt from the oracle's per-visit steps."""
+    r = oracle_lib.ccd(prob, kind, var, n, want_trace=True)
+    steps = r["trace"][:, :, 2]
+    betas = np.zeros((n + 1, prob.n_cols))
+    for t in range(n):
+        betas[t + 1] = betas[t] + steps[t]
+    return betas, r
+
+
+@pytest.mark.parametrize("kind,var", [(1, 1.0), (2, 0.5)])
+def test_rel_logpost_rule_fires_at_the_first_qualifying_sweep(oracle_lib, kind, var):
+    """Section 2.2 reading R6: stop after sweep t, the first with
+    |P_t - P_{t-1}| < tol |P_t|, P_0 at the start point; P from Eq. 2 and
+    Eq. 3 evaluated independently (defn) on the oracle's per-sweep beta."""
+    prob = synth.tiny(n_patients=300, n_cols=8, seed=5)
+    n = 12
+    betas, r = _sweep_betas(oracle_lib, prob, kind, var, n)
+    X = defn.dense_x(prob)
+    P = np.array([float(np.real(defn.loglik(prob, b, X=X))) + defn.log_prior(kind, var, b) for b in betas])
+    # the oracle's per-sweep log posterior is Eq. 2 + Eq. 3 at each sweep's beta
+    assert np.allclose(r["logpost_trace"], P[1:], rtol=1e-12, atol=0)
+    ratio = np.abs(np.diff(P)) / np.abs(P[1:])       # ratio[t-1] belongs to sweep t
+    # thresholds half-way (geometrically) between consecutive ratios: the rule
+    # must fire exactly at the sweep whose ratio first drops below
+    fired = 0
+    for t in range(2, 9):
+        # sweeps whose change is above rounding level, well below the earlier ones
+        if not (1e-14 < ratio[t - 1] < ratio[: t - 1].min() / 4):
+            continue
+        tol = math.sqrt(ratio[t - 1] * ratio[: t - 1].min())
+        rr = oracle_lib.ccd(prob, kind, var, 50, oracle_lib.CRIT_REL_LOGPOST, tol)
+        assert rr["converged"] and rr["sweeps"] == t, (t, tol, ratio[:t])
+        assert np.array_equal(rr["beta"], betas[t])
+        fired += 1
+    assert fired >= 2
+
+
+@pytest.mark.parametrize("kind,var", [(1, 1.0), (2, 0.5)])
+def test_abs_dxbeta_rule_fires_at_the_first_qualifying_sweep(oracle_lib, kind, var):
+    """Section 2.2: stop after the first sweep whose sum over eras of
+    |(X beta)_t - (X beta)_{t-1}| falls below eps, with X beta formed from
+    the dense design (defn) and the oracle's per-sweep beta."""
+    prob = synth.tiny(n_patients=300, n_cols=8, seed=6)
+    n = 12
+    betas, _ = _sweep_betas(oracle_lib, prob, kind, var, n)
+    X = defn.dense_x(prob)
+    S = np.array([np.sum(np.abs(X @ (betas[t] - betas[t - 1]))) for t in range(1, n + 1)])
+    fired = 0
+    for t in range(2, 9):
+        if not (1e-12 < S[t - 1] < S[: t - 1].min() / 4):
+            continue
+        eps = math.sqrt(S[t - 1] * S[: t - 1].min())
+        rr = oracle_lib.ccd(prob, kind, var, 50, oracle_lib.CRIT_ABS_DXBETA, eps)
+        assert rr["converged"] and rr["sweeps"] == t, (t, eps, S[:t])
+        assert np.array_equal(rr["beta"], betas[t])
+        fired += 1
+    assert fired >= 2
+    # the paper's own threshold, 5e-4 absolute
+    t_paper = int(np.argmax(S < 5e-4)) + 1
+    assert S[t_paper - 1] < 5e-4 <= S[: t_paper - 1].min()
+    rr = oracle_lib.ccd(prob, kind, var, 50, oracle_lib.CRIT_ABS_DXBETA, 5e-4)
+    assert rr["sweeps"] == t_paper
+
+
+def test_patient_with_zero_total_length_adds_nothing(oracle_lib):
+    """A patient whose eras all have length 0 has den_i = 0 and (validation
+    requires y_k = 0 where l_k = 0) n_i = 0: Eq. 2 gives it no term, so adding
+    it to a column leaves every fit unchanged and finite."""
+    prob = small(31, n_patients=120, n_cols=4, p=0.25)
+    base = _fit(oracle_lib, prob)
+    X = defn.dense_x(prob)
+    ptr = np.concatenate([prob.patient_ptr, [prob.n_rows + 3]]).astype(np.int64)
+    offset = np.concatenate([prob.offset, [0, 0, 0]])
+    count = np.concatenate([prob.count, [0, 0, 0]])
+    Xn = np.vstack([X, np.ones((3, prob.n_cols))])
+    cols = [np.flatnonzero(Xn[:, j]) for j in range(prob.n_cols)]
+    p2 = make(ptr, offset, count, cols)
+    for kind, var in ((1, 0.5), (2, 2.0), (0, 1.0)):
+        a = _ccd_converged(oracle_lib, prob, kind, var)["beta"]
+        b = _ccd_converged(oracle_lib, p2, kind, var)["beta"]
+        assert np.all(np.isfinite(b))
+        assert np.max(np.abs(a - b)) < 1e-12
+    for j in range(prob.n_cols):
+        g, h = oracle_lib.grad_hess(p2, base, j)
+        g0, h0 = oracle_lib.grad_hess(prob, base, j)
+        assert g == pytest.approx(g0, rel=1e-13, abs=1e-13) and h == pytest.approx(h0, rel=1e-13)
