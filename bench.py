@@ -5,12 +5,17 @@ Workload (the configuration the headline metric is quoted on): 2M patients,
 popularity, Laplace prior lambda = 1 (variance 2), FP64.  One step = one full
 cyclic sweep over all 2000 coordinates (gather + segmented sums, device-wide
 reduction, Newton/trust-region step, sparse update), one persistent launch.
+After the warm-up sweeps the fit is reset to beta = 0, so the timed steps
+are sweeps 1..K of a fit from zero.
 
 Prints one JSON line.  Besides the required fields it carries:
-  roofline      algorithmic HBM bytes of the sweep kernel / its mean launch
-                time (HIP events on the launch stream) against 8 TB/s;
+  roofline      algorithmic bytes of the sweep (stated byte model) / the
+                sweep kernel's mean launch time (HIP events on the launch
+                stream) against 8 TB/s, and the library's own byte model;
+  schedule      device-wide reductions (passes) per sweep and their mean time;
+  late_sweeps   the sweeps after the headline ones, timed on their own;
   cpu_baseline  the FP64 C oracle timed on the host on a bounded sample;
-  mixed         the mixed-precision form on the same workload: sweeps/s and
+  mixed         the mixed-precision form on the same schedule: sweeps/s and
                 its relative beta error against the FP64 GPU path.
 """
 from __future__ import annotations
@@ -43,42 +48,70 @@ def column_stats(prob):
 
 
 def bytes_per_sweep(c, p, active, precision):
-    """Algorithmic bytes of one sweep.  Phase A, every coordinate: per nonzero
-    the (row, patient) index pair (8 B) and the gathered weight (8 B FP64,
-    4 B mixed); per patient segment den_i and omega_i n_i (16 B).  Phase B,
-    coordinates with a nonzero step: the new weight per nonzero (8 / 4 B)
-    and the new den_i per segment (8 B)."""
+    """Algorithmic bytes of one sweep, per coordinate j with c_j nonzeros and
+    p_j distinct patients (the method's own data movement, X beta kept as an
+    era array as in Section 2.4 Steps 1-4):
+      phase A, every coordinate: 12 c_j + 16 p_j -- per nonzero its row index
+        (4 B) and the gathered w_k (8 B); per patient segment its patient
+        index (4 B), den_i (8 B) and n_i (4 B);
+      phase B, coordinates with a nonzero step: 28 c_j + 8 p_j -- per nonzero
+        the read-modify-write of (X beta)_k (16 B), l_k (4 B) and the new w_k
+        (8 B); per segment the new den_i (8 B).
+    The mixed form stores w in 4 B: 8 c_j + 16 p_j and 24 c_j + 8 p_j."""
+    wb = 8 if precision == 0 else 4
+    a = (4 + wb) * c.sum() + 16 * p.sum()
+    b = (20 + wb) * c[active].sum() + 8 * p[active].sum()
+    return float(a + b)
+
+
+def bytes_per_sweep_library(c, p, active, precision):
+    """The bytes this library's kernel has to move for the same sweep: it
+    stores (row, patient) pairs (8 B per nonzero), gathers (den_i, omega_i
+    n_i) as one 16-byte pair, and updates w multiplicatively (no X beta
+    array, no l read): phase A (8 + wb) c_j + 16 p_j, phase B wb c_j + 8 p_j
+    (wb = 8 FP64, 4 mixed)."""
     wb = 8 if precision == 0 else 4
     a = (8 + wb) * c.sum() + 16 * p.sum()
     b = wb * c[active].sum() + 8 * p[active].sum()
     return float(a + b)
 
 
-def run_form(sccs, prob, precision, steps, warmup, c, p, n_workgroups=0):
+def run_form(sccs, prob, precision, steps, warmup, c, p, n_workgroups=0, late=0):
+    """warmup sweeps, then beta reset to 0 (exact state recomputation) and
+    `steps` timed sweeps from beta = 0, one launch each; then `late` more
+    sweeps timed on their own (the fit continuing toward convergence)."""
     import torch
     h = sccs.Handle(prob, precision=precision, n_workgroups=n_workgroups)
     h.set_prior(sccs.PRIOR_LAPLACE, 2.0)
-    beta_prev, _ = h.get_beta()
     for _ in range(warmup):
         h.sweep(1)
+    h.set_beta(np.zeros(prob.n_cols))
     beta_prev, _ = h.get_beta()
     torch.cuda.synchronize()
-    kernel_ms = []
-    algo_bytes = []
-    passes = []
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        h.sweep(1)
-        kernel_ms.append(h.last_kernel_ms())
-        passes.append(h.pass_stats())
-        beta, _ = h.get_beta()
-        algo_bytes.append(bytes_per_sweep(c, p, beta != beta_prev, precision))
-        beta_prev = beta
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    beta, _ = h.get_beta()
+
+    def timed(n):
+        nonlocal beta_prev
+        rec = {"kernel_ms": [], "bytes": [], "bytes_lib": [], "passes": []}
+        t0 = time.perf_counter()
+        for _ in range(n):
+            h.sweep(1)
+            rec["kernel_ms"].append(h.last_kernel_ms())
+            rec["passes"].append(h.pass_stats())
+            beta, _ = h.get_beta()
+            moved = beta != beta_prev
+            rec["bytes"].append(bytes_per_sweep(c, p, moved, precision))
+            rec["bytes_lib"].append(bytes_per_sweep_library(c, p, moved, precision))
+            beta_prev = beta
+        torch.cuda.synchronize()
+        rec["wall_s"] = time.perf_counter() - t0
+        return rec
+
+    out = timed(steps)
+    out["beta"] = beta_prev.copy()
+    if late:
+        out["late"] = timed(late)
     h.close()
-    return {"wall_s": wall, "kernel_ms": kernel_ms, "bytes": algo_bytes, "beta": beta, "passes": passes}
+    return out
 
 
 def profiled_traffic(kernel_ms):
@@ -118,6 +151,25 @@ def kernel_source_sha() -> str:
     return hashlib.sha256("\n".join(code).encode()).hexdigest()[:16]
 
 
+def host_description():
+    """CPU model, logical CPUs visible to this process and the C compiler."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        import subprocess
+        cc = subprocess.run(["gcc", "--version"], capture_output=True, text=True).stdout.splitlines()[0]
+    except Exception:
+        cc = "unknown"
+    return {"cpu_model": model, "nproc": len(os.sched_getaffinity(0)), "compiler": cc,
+            "flags": "-O2 -std=c99 (no fast-math)"}
+
+
 def cpu_baseline(prob, sweeps):
     import oracle
     oracle.build(force=False)
@@ -130,8 +182,10 @@ def cpu_baseline(prob, sweeps):
     t = time.perf_counter() - t0
     per = max(t - t_setup, 1e-9) / sweeps
     return {"value": 1.0 / per, "unit": "sweeps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{sweeps} CCD sweeps of the same workload by the single-threaded FP64 C oracle "
-                      f"(-O2), one-time setup ({t_setup:.2f} s) subtracted; {t:.1f} s total"}
+            "sample": f"the first {sweeps} CCD sweeps from beta = 0 of the same workload by the "
+                      f"single-threaded FP64 C oracle, one-time setup ({t_setup:.2f} s) subtracted; "
+                      f"{t:.1f} s total",
+            "host": host_description()}
 
 
 def copy_calibration(n_bytes: int = 1 << 30, reps: int = 3):
@@ -301,9 +355,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--late", type=int, default=20,
+                    help="sweeps timed after the headline ones, continuing the fit (0 = none)")
     ap.add_argument("--patients", type=int, default=2_000_000)
     ap.add_argument("--cols", type=int, default=2000)
-    ap.add_argument("--cpu-sweeps", type=int, default=4)
+    ap.add_argument("--cpu-sweeps", type=int, default=12)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", choices=["mid", "outcomes", "cv", "full", "paper"], default="mid")
@@ -361,10 +417,19 @@ def main():
     print(f"[bench] generated {prob.summary()} in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     c, p = column_stats(prob)
 
-    fp = run_form(sccs, prob, 0, args.steps, args.warmup, c, p, args.workgroups)
+    fp = run_form(sccs, prob, 0, args.steps, args.warmup, c, p, args.workgroups, late=args.late)
     print(f"[bench] fp64 done: {args.steps / fp['wall_s']:.1f} sweeps/s", file=sys.stderr, flush=True)
     ms = float(np.mean(fp["kernel_ms"]))
-    achieved = float(np.mean(fp["bytes"])) / (ms * 1e-3) / 1e9
+    algo = float(np.mean(fp["bytes"]))
+    achieved = algo / (ms * 1e-3) / 1e9
+
+    def sched(r):
+        return {"passes_per_sweep_mean": float(np.mean([q[0] for q in r["passes"]])),
+                "passes_last_sweep": int(r["passes"][-1][0]),
+                "rejected_merges_per_sweep_mean": float(np.mean([q[1] for q in r["passes"]])),
+                "zero_step_share_mean": float(np.mean([q[2] for q in r["passes"]])) / prob.n_cols,
+                "us_per_pass_mean": 1e3 * float(np.sum(r["kernel_ms"])) / float(np.sum([q[0] for q in r["passes"]])),
+                "kernel_ms_per_sweep": [round(x, 4) for x in r["kernel_ms"]]}
     out = {
         "metric": METRIC,
         "value": args.steps / fp["wall_s"],
@@ -379,25 +444,33 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"mid SCCS: {prob.n_patients} patients, {prob.n_rows} eras, J={prob.n_cols} "
-                               f"Zipf(1.1) drugs, {prob.nnz} nonzeros, Laplace lambda=1, FP64, one sweep per step",
+                               f"Zipf(1.1) drugs, {prob.nnz} nonzeros, Laplace lambda=1, FP64; "
+                               f"sweeps 1..{args.steps} from beta = 0, one sweep per step",
                    "n_patients": prob.n_patients, "n_eras": prob.n_rows, "n_cols": prob.n_cols,
                    "nnz": prob.nnz, "prior": "laplace", "variance": 2.0, "parallelism": "single GPU",
                    "n_workgroups": args.workgroups},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(ms),
                      "kernel": "k_ccd<double, *> (one-pass-per-group and merged-pass forms)", "kernel_ms_mean": ms,
-                     "algo_bytes_per_launch": float(np.mean(fp["bytes"]))},
-        # device-wide reductions per sweep (column groups; consecutive groups
-        # share a pass when predicted independent), merges undone per sweep,
-        # and the share of coordinates whose step was exactly zero
-        "schedule": {"passes_per_sweep_mean": float(np.mean([q[0] for q in fp["passes"]])),
-                     "passes_last_sweep": int(fp["passes"][-1][0]),
-                     "rejected_merges_per_sweep_mean": float(np.mean([q[1] for q in fp["passes"]])),
-                     "zero_step_share_mean": float(np.mean([q[2] for q in fp["passes"]])) / prob.n_cols,
-                     # each pass is one device-wide reduction: the serial chain
-                     # that bounds the sweep, not HBM bandwidth
-                     "us_per_pass_mean": 1e3 * float(np.sum(fp["kernel_ms"])) / float(np.sum([q[0] for q in fp["passes"]]))},
+                     "algo_bytes_per_launch": algo,
+                     "byte_model": "per coordinate 12 c_j + 16 p_j, plus 28 c_j + 8 p_j when its step is "
+                                   "nonzero (c_j nonzeros, p_j patients of column j)",
+                     "achieved_library_bytes": float(np.mean(fp["bytes_lib"])) / (ms * 1e-3) / 1e9,
+                     "library_byte_model": "per coordinate 16 c_j + 16 p_j, plus 8 c_j + 8 p_j when its step is "
+                                           "nonzero (what this kernel moves: (row, patient) pairs, 16-byte "
+                                           "(den, omega n) gathers, multiplicative w update)",
+                     # the sweep is a chain of device-wide reductions (one per
+                     # pass): their latency, not HBM bandwidth, sets its time
+                     "limiter": "latency of the chain of device-wide reductions, one per pass"},
+        "schedule": sched(fp),
     }
+    if args.late:
+        lt = fp["late"]
+        lms = float(np.mean(lt["kernel_ms"]))
+        out["late_sweeps"] = {"sweeps": f"{args.steps + 1}..{args.steps + args.late}",
+                              "value": args.late / lt["wall_s"], "unit": "sweeps/s", "kernel_ms_mean": lms,
+                              "achieved_GBs": float(np.mean(lt["bytes"])) / (lms * 1e-3) / 1e9,
+                              "schedule": sched(lt)}
     if not args.no_mixed:
         mx = run_form(sccs, prob, 1, args.steps, args.warmup, c, p, args.mixed_workgroups)
         err = float(np.max(np.abs(mx["beta"] - fp["beta"])) / max(np.max(np.abs(fp["beta"])), 1e-300))
@@ -407,7 +480,7 @@ def main():
                         "achieved_GBs": float(np.mean(mx["bytes"])) / (mms * 1e-3) / 1e9,
                         "rel_err_vs_fp64_gpu": err,
                         "n_workgroups": args.mixed_workgroups,
-                        "sweeps_compared": args.steps + args.warmup}
+                        "sweeps_compared": f"1..{args.steps} from beta = 0"}
         print(f"[bench] mixed done: {out['mixed']['value']:.1f} sweeps/s, rel err {err:.2e}",
               file=sys.stderr, flush=True)
     if not args.no_cpu:

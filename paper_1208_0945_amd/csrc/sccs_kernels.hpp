@@ -391,7 +391,9 @@ __device__ __forceinline__ double seg_sum(double v, uint32_t key, int lane, int 
 // Contribution of one patient segment to G and H (the transform of Eq. 8
 // fused with the two inner products of Eqs. 7 and 9).
 __device__ __forceinline__ void accum_patient(double num, double2 pv, double& Gl, double& Hl) {
-  double r = num / pv.x;
+  // num = 0 gives r = 0, also for a patient whose eras all have length 0
+  // (den_i = 0; such a patient has n_i = 0 and no term in Eq. 2)
+  double r = num != 0.0 ? num / pv.x : 0.0;
   double tg = pv.y * r;
   Gl += tg;
   Hl += tg * fmax(1.0 - r, 0.0);
@@ -423,7 +425,7 @@ struct Acc {
     for (int i = 0; i < NC; ++i) g[i] = h[i] = 0.0;
   }
   __device__ __forceinline__ void add(uint32_t c, double num, double2 pv) {
-    const double r = num / pv.x;
+    const double r = num != 0.0 ? num / pv.x : 0.0;   // as in accum_patient
     const double tg = pv.y * r;
     const double th = tg * fmax(1.0 - r, 0.0);
 #pragma unroll

@@ -6,8 +6,11 @@ raises if ``libsccs.so`` has not been built -- there is no fallback path.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 from typing import Optional, Tuple
 
 import numpy as np
@@ -71,6 +74,23 @@ class FitResult_(ctypes.Structure):
 
 
 _lib = None
+
+# Handles and batches still open when the interpreter exits are destroyed by
+# an atexit hook, i.e. before the C-level exit handlers (HIP's own teardown,
+# and a profiler's, if one is attached) run; a destructor that runs later,
+# during interpreter finalisation, makes no HIP call at all.
+_live = weakref.WeakSet()
+
+
+def _close_live():
+    for obj in list(_live):
+        try:
+            obj.close()
+        except Exception:
+            pass
+
+
+atexit.register(_close_live)
 
 
 def _hip_runtimes_mapped():
@@ -218,6 +238,7 @@ class Handle:
         self.h = h
         self.J = P.n_cols
         self.precision = precision
+        _live.add(self)
 
     def _check(self, st: int, allow=(OK,)) -> int:
         if st not in allow:
@@ -231,6 +252,8 @@ class Handle:
             self.ws = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -356,6 +379,7 @@ class Batch:
             raise SccsError(st, L.sccs_batch_last_error(None).decode())
         self.h = h
         self.J = self._probs[0].n_cols
+        _live.add(self)
 
     def _check(self, st):
         if st != OK:
@@ -389,6 +413,8 @@ class Batch:
             self.ws = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -227,19 +227,31 @@ def outcome_sizes(n_fits: int = 64, lo: float = 1e4, hi: float = 2e6, seed: int 
     return np.round(np.exp(rng.uniform(math.log(lo), math.log(hi), size=n_fits))).astype(np.int64)
 
 
+def outcome_vocabulary(n_cols: int = 1000, seed: int = 0) -> np.ndarray:
+    """Per-drug exposure probabilities shared by every outcome of a batch."""
+    return zipf_probs(n_cols, 0.1, 1.1, _rng(4, seed, 9))
+
+
+def outcome(f: int, n_patients: int, n_cols: int = 1000, seed: int = 0,
+            probs: Optional[np.ndarray] = None) -> Problem:
+    """Outcome f of a batch over one shared vocabulary: the same problem that
+    batched_outcomes returns at position f for this size."""
+    if probs is None:
+        probs = outcome_vocabulary(n_cols, seed)
+    beta = sparse_beta(n_cols, 50, 0.7, _rng(4, seed, 10, f))
+    return make_problem(f"outcome{f}", int(n_patients), n_cols, 9.0, probs, beta, seed_path=(4, seed, f))
+
+
 def batched_outcomes(n_fits: int = 64, n_cols: int = 1000, seed: int = 0,
                      sizes: Optional[Sequence[int]] = None, progress=None) -> List[Problem]:
     """Independent outcomes over one shared J-drug vocabulary (shared Zipf
     popularity), patient counts log-uniform 10k..2M."""
     if sizes is None:
         sizes = outcome_sizes(n_fits, seed=seed)
-    rng = _rng(4, seed, 9)
-    probs = zipf_probs(n_cols, 0.1, 1.1, rng)
+    probs = outcome_vocabulary(n_cols, seed)
     out = []
     for f, n in enumerate(sizes):
-        beta = sparse_beta(n_cols, 50, 0.7, _rng(4, seed, 10, f))
-        out.append(make_problem(f"outcome{f}", int(n), n_cols, 9.0, probs, beta,
-                                seed_path=(4, seed, f)))
+        out.append(outcome(f, int(n), n_cols, seed, probs))
         if progress is not None:
             progress(f)
     return out

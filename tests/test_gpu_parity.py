@@ -83,8 +83,10 @@ def test_grad_hess_at_warm_start_match_oracle(sccs, precision, tol):
         for j in range(prob.n_cols):
             g, hh = h.grad_hess(j)
             go, ho = oracle.grad_hess(prob, beta, j)
-            assert abs(g - go) <= tol * max(1.0, abs(ho)), (j, g, go)
-            assert abs(hh - ho) <= tol * max(1.0, abs(ho)), (j, hh, ho)
+            # g = Y'X_j - N'W: its error is relative to the size of the two terms
+            scale = max(1.0, float(prob.count[prob.column(j)].sum()))
+            assert abs(g - go) <= tol * scale, (j, g, go)
+            assert abs(hh - ho) <= tol * abs(ho), (j, hh, ho)
 
 
 def test_grad_hess_inside_column_groups(sccs):
@@ -97,8 +99,9 @@ def test_grad_hess_inside_column_groups(sccs):
         for j in range(0, prob.n_cols, 3):
             g, hh = h.grad_hess(j)
             go, ho = oracle.grad_hess(prob, beta, j)
-            assert abs(g - go) <= 1e-11 * max(1.0, abs(ho)), (j, g, go)
-            assert abs(hh - ho) <= 1e-11 * max(1.0, abs(ho)), (j, hh, ho)
+            scale = max(1.0, float(prob.count[prob.column(j)].sum()))
+            assert abs(g - go) <= 1e-12 * scale, (j, g, go)
+            assert abs(hh - ho) <= 1e-11 * abs(ho), (j, hh, ho)
 
 
 @pytest.mark.parametrize("kind,var", [(1, 1.0), (2, 2.0), (0, 1.0), (2, 0.02)])
@@ -121,7 +124,12 @@ def test_tiny_fit_to_convergence(sccs):
         r = h.fit(sccs.CRIT_REL_LOGPOST, 500, 1e-8)
         beta, _ = h.get_beta()
         assert r["converged"]
-        assert abs(r["sweeps"] - ref["sweeps"]) <= 1
+        # the stopping decision is taken on the same sweep (the relative change
+        # at the firing sweep is far from the threshold on this problem)
+        lp = np.concatenate([[oracle.loglik(prob, np.zeros(prob.n_cols))], ref["logpost_trace"]])
+        ratio = np.abs(np.diff(lp)) / np.abs(lp[1:])
+        assert ratio[ref["sweeps"] - 1] < 0.5e-8 and ratio[ref["sweeps"] - 2] > 2e-8, ratio
+        assert r["sweeps"] == ref["sweeps"]
         assert abs(r["logpost"] - ref["logpost"]) <= 1e-10 * abs(ref["logpost"])
     # replay exactly the oracle's sweep count
     beta2, _ = run_gpu(sccs, prob, 1, 1.0, ref["sweeps"])
@@ -129,12 +137,37 @@ def test_tiny_fit_to_convergence(sccs):
 
 
 def test_abs_dxbeta_criterion(sccs):
+    """Section 2.2's rule, sum over eras of |change of (X beta)_k| below
+    5e-4: the GPU stops after the oracle's sweep, with the oracle's beta."""
     prob = synth.tiny(seed=2)
     ref = oracle.ccd(prob, 2, 2.0, 500, oracle.CRIT_ABS_DXBETA, 5e-4)
     with sccs.Handle(prob) as h:
         h.set_prior(2, 2.0)
         r = h.fit(sccs.CRIT_ABS_DXBETA, 500, 5e-4)
-        assert r["converged"] and abs(r["sweeps"] - ref["sweeps"]) <= 1
+        beta, _ = h.get_beta()
+        assert r["converged"] and r["sweeps"] == ref["sweeps"]
+    assert rel_inf(beta, ref["beta"]) <= FP64_TOL
+    assert np.array_equal(beta == 0.0, ref["beta"] == 0.0)
+
+
+def test_patient_with_zero_total_length(sccs):
+    """A patient whose eras all have length 0 (so n_i = 0 and den_i = 0) in
+    every column: the fit stays finite and equals the oracle's."""
+    base = zipf_small(n_patients=3000, n_cols=40, seed=4)
+    J = base.n_cols
+    ptr = np.concatenate([base.patient_ptr, [base.n_rows + 2]]).astype(np.int64)
+    offset = np.concatenate([base.offset, [0, 0]]).astype(np.int32)
+    count = np.concatenate([base.count, [0, 0]]).astype(np.int32)
+    cols = [np.concatenate([base.column(j), [base.n_rows, base.n_rows + 1]]) for j in range(J)]
+    col_ptr = np.zeros(J + 1, np.int64)
+    col_ptr[1:] = np.cumsum([len(c) for c in cols])
+    prob = synth.Problem("zero_len", base.n_patients + 1, ptr, offset, count, J, col_ptr,
+                         np.concatenate(cols).astype(np.int32), np.zeros(J))
+    for kind, var in ((2, 2.0), (1, 0.5)):
+        ref = oracle.ccd(prob, kind, var, 5)
+        beta, _ = run_gpu(sccs, prob, kind, var, 5)
+        assert np.all(np.isfinite(beta))
+        assert rel_inf(beta, ref["beta"]) <= FP64_TOL
 
 
 @pytest.mark.parametrize("n_workgroups,tile_nnz,max_group",
