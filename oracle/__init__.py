@@ -36,7 +36,7 @@ class _Problem(ctypes.Structure):
                 ("n_cols", ctypes.c_int32), ("patient_ptr", ctypes.c_void_p),
                 ("offset", ctypes.c_void_p), ("count", ctypes.c_void_p),
                 ("col_ptr", ctypes.c_void_p), ("row_idx", ctypes.c_void_p),
-                ("weight", ctypes.c_void_p)]
+                ("weight", ctypes.c_void_p), ("value", ctypes.c_void_p)]
 
 
 class _Result(ctypes.Structure):
@@ -88,12 +88,15 @@ class OracleProblem:
         self.col_ptr = _c(prob.col_ptr, np.int64)
         self.row_idx = _c(prob.row_idx, np.int32)
         self.weight = None if weight is None else _c(weight, np.int32)
+        v = getattr(prob, "value", None)
+        self.value = None if v is None else _c(v, np.float64)
         self.J = int(prob.n_cols)
         self.s = _Problem(int(prob.n_patients), int(self.patient_ptr[-1]), self.J,
                           self.patient_ptr.ctypes.data, self.offset.ctypes.data,
                           self.count.ctypes.data, self.col_ptr.ctypes.data,
                           self.row_idx.ctypes.data,
-                          None if self.weight is None else self.weight.ctypes.data)
+                          None if self.weight is None else self.weight.ctypes.data,
+                          None if self.value is None else self.value.ctypes.data)
 
 
 def _prob(prob, weight=None) -> OracleProblem:
@@ -156,3 +159,41 @@ def ccd(prob, prior_kind: int, var: float, max_sweeps: int, criterion: int = CRI
     return {"beta": beta, "trust": trust, "sweeps": n, "converged": bool(res.converged),
             "loglik": res.loglik, "logpost": res.logpost,
             "trace": None if trace is None else trace[:n], "logpost_trace": lpt[:n]}
+
+
+def _quantile_sorted(x, q: float) -> float:
+    """Quantile of an ascending list at probability q by linear interpolation
+    between order statistics at position (R - 1) q (the paper names no
+    quantile rule; this is the common default, Hyndman and Fan's type 7)."""
+    pos = (len(x) - 1) * q
+    k = int(np.floor(pos))
+    k1 = min(k + 1, len(x) - 1)
+    return x[k] + (pos - k) * (x[k1] - x[k])
+
+
+def bootstrap_summary(betas, level: float = 0.95):
+    """Section 2.5, non-parametric bootstrap: per coefficient j, the interval
+    from the (1 - level)/2 and (1 + level)/2 quantiles of the replicate
+    estimates, and p_hat_j, the share of replicates whose MAP estimate of
+    beta_j is not zero.  betas: [R, J].  Returns (lo, hi, p_hat)."""
+    B = np.asarray(betas, dtype=np.float64)
+    R, J = B.shape
+    lo, hi, p_hat = np.zeros(J), np.zeros(J), np.zeros(J)
+    for j in range(J):
+        x = sorted(float(v) for v in B[:, j])
+        lo[j] = _quantile_sorted(x, 0.5 * (1.0 - level))
+        hi[j] = _quantile_sorted(x, 0.5 * (1.0 + level))
+        p_hat[j] = sum(1 for v in x if v != 0.0) / R
+    return lo, hi, p_hat
+
+
+def bootstrap(prob, prior_kind: int, var: float, weights, max_sweeps: int, criterion: int = CRIT_FIXED,
+              tol: float = 0.0, level: float = 0.95):
+    """One Algorithm 1 fit per replicate, from beta = 0, with the replicate's
+    patient weights (weights: [R, N]); then bootstrap_summary.  Returns
+    dict(beta [R, J], sweeps [R], lo, hi, p_hat)."""
+    W = np.asarray(weights)
+    fits = [ccd(prob, prior_kind, var, max_sweeps, criterion, tol, weight=W[r]) for r in range(W.shape[0])]
+    betas = np.array([f["beta"] for f in fits])
+    lo, hi, p_hat = bootstrap_summary(betas, level)
+    return {"beta": betas, "sweeps": np.array([f["sweeps"] for f in fits]), "lo": lo, "hi": hi, "p_hat": p_hat}

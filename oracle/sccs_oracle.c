@@ -11,6 +11,16 @@
  * Patient weights omega_i (1 by default) multiply patient i's whole
  * log-likelihood term; they express cross-validation folds (0/1) and
  * bootstrap resamples (counts).
+ *
+ * Covariates are binary drug exposures unless the problem carries values
+ * x_kj (Section 4 names dense, non-binary covariates such as baseline
+ * measurements).  Then eta_k = sum_j x_kj beta_j, and differentiating Eq. 2
+ * twice along beta_j gives, with A_i = M[w x X_j]_i / den_i and
+ * B_i = M[w x X_j^2]_i / den_i,
+ *   g_j = sum_i omega_i (sum_k y_ik x_kj) - sum_i omega_i n_i A_i,
+ *   h_j = -sum_i omega_i n_i (B_i - A_i^2);
+ * for binary x, B = A = W and this is Eq. 9's W(1 - W).  The binary case
+ * keeps the formulas of Eqs. 7-9 as written.
  */
 #include "sccs_oracle.h"
 
@@ -20,6 +30,11 @@
 
 static double weight_of(const ora_problem* p, int64_t i) {
   return p->weight ? (double)p->weight[i] : 1.0;
+}
+
+/* x of the CSC entry e (1 for a binary problem) */
+static double value_of(const ora_problem* p, int64_t e) {
+  return p->value ? p->value[e] : 1.0;
 }
 
 static int check_problem(const ora_problem* p) {
@@ -34,7 +49,10 @@ static int check_problem(const ora_problem* p) {
 static void linear_predictor(const ora_problem* p, const double* beta, double* eta) {
   for (int64_t k = 0; k < p->n_rows; ++k) eta[k] = 0.0;
   for (int32_t j = 0; j < p->n_cols; ++j)
-    for (int64_t e = p->col_ptr[j]; e < p->col_ptr[j + 1]; ++e) eta[p->row_idx[e]] += beta[j];
+    for (int64_t e = p->col_ptr[j]; e < p->col_ptr[j + 1]; ++e) {
+      if (p->value) eta[p->row_idx[e]] += p->value[e] * beta[j];
+      else eta[p->row_idx[e]] += beta[j];
+    }
 }
 
 /* Eq. 2: L(beta) = sum_i omega_i [ sum_k y_ik x_ik'beta - n_i log sum_k l_ik exp(x_ik'beta) ]. */
@@ -78,10 +96,14 @@ int ora_grad_hess(const ora_problem* p, const double* beta, int32_t j, double* g
   int64_t K = p->n_rows, N = p->n_patients;
   double* eta = (double*)malloc(sizeof(double) * (size_t)(K > 0 ? K : 1));
   double* num = (double*)calloc((size_t)(N > 0 ? N : 1), sizeof(double));
+  double* num2 = (double*)calloc((size_t)(N > 0 ? N : 1), sizeof(double));
   double* den = (double*)calloc((size_t)(N > 0 ? N : 1), sizeof(double));
   double* nn = (double*)calloc((size_t)(N > 0 ? N : 1), sizeof(double));
   int32_t* pid = (int32_t*)malloc(sizeof(int32_t) * (size_t)(K > 0 ? K : 1));
-  if (!eta || !num || !den || !nn || !pid) { free(eta); free(num); free(den); free(nn); free(pid); return -2; }
+  if (!eta || !num || !num2 || !den || !nn || !pid) {
+    free(eta); free(num); free(num2); free(den); free(nn); free(pid);
+    return -2;
+  }
   linear_predictor(p, beta, eta);
   double yx = 0.0;
   for (int64_t i = 0; i < N; ++i)
@@ -93,20 +115,28 @@ int ora_grad_hess(const ora_problem* p, const double* beta, int32_t j, double* g
   for (int64_t e = p->col_ptr[j]; e < p->col_ptr[j + 1]; ++e) {
     int64_t k = p->row_idx[e];
     int32_t i = pid[k];
-    num[i] += (double)p->offset[k] * exp(eta[k]);
-    yx += weight_of(p, i) * (double)p->count[k];
+    double x = value_of(p, e);
+    num[i] += (double)p->offset[k] * exp(eta[k]) * x;
+    num2[i] += (double)p->offset[k] * exp(eta[k]) * x * x;
+    yx += weight_of(p, i) * (double)p->count[k] * x;
   }
   double G = 0.0, H = 0.0;
   for (int64_t i = 0; i < N; ++i) {
-    if (num[i] == 0.0) continue;
-    double W = num[i] / den[i];
+    if (num[i] == 0.0 && num2[i] == 0.0) continue;
     double wn = weight_of(p, i) * nn[i];
-    G += wn * W;
-    H += wn * W * (1.0 - W);
+    if (p->value) {
+      double A = num[i] / den[i], B = num2[i] / den[i];
+      G += wn * A;
+      H += wn * (B - A * A);
+    } else {
+      double W = num[i] / den[i];
+      G += wn * W;
+      H += wn * W * (1.0 - W);
+    }
   }
   *g = yx - G;
   *h = -H;
-  free(eta); free(num); free(den); free(nn); free(pid);
+  free(eta); free(num); free(num2); free(den); free(nn); free(pid);
   return 0;
 }
 
@@ -175,11 +205,13 @@ int ora_ccd(const ora_problem* p, int32_t prior_kind, double var, double* beta,
   int32_t* pid = (int32_t*)malloc(sizeof(int32_t) * KK);
   double* den = (double*)malloc(sizeof(double) * NN);
   double* num = (double*)calloc(NN, sizeof(double));
+  double* num2 = (double*)calloc(NN, sizeof(double));    /* M[w x X_j^2], covariate values only */
   double* wn = (double*)malloc(sizeof(double) * NN);     /* omega_i n_i */
   double* ytx = (double*)malloc(sizeof(double) * (size_t)(J > 0 ? J : 1));
   int32_t* touched = (int32_t*)malloc(sizeof(int32_t) * NN);
-  if (!eta || !eta_prev || !w || !pid || !den || !num || !wn || !ytx || !touched) {
-    free(eta); free(eta_prev); free(w); free(pid); free(den); free(num); free(wn); free(ytx); free(touched);
+  if (!eta || !eta_prev || !w || !pid || !den || !num || !num2 || !wn || !ytx || !touched) {
+    free(eta); free(eta_prev); free(w); free(pid); free(den); free(num); free(num2); free(wn); free(ytx);
+    free(touched);
     return -2;
   }
 
@@ -196,7 +228,7 @@ int ora_ccd(const ora_problem* p, int32_t prior_kind, double var, double* beta,
     double s = 0.0;
     for (int64_t e = p->col_ptr[j]; e < p->col_ptr[j + 1]; ++e) {
       int64_t k = p->row_idx[e];
-      s += weight_of(p, pid[k]) * (double)p->count[k];
+      s += weight_of(p, pid[k]) * (double)p->count[k] * value_of(p, e);
     }
     ytx[j] = s;
   }
@@ -226,18 +258,30 @@ int ora_ccd(const ora_problem* p, int32_t prior_kind, double var, double* beta,
         int64_t k = p->row_idx[e];
         int32_t i = pid[k];
         if (nt == 0 || touched[nt - 1] != i) touched[nt++] = i;
-        num[i] += w[k];
+        if (p->value) {
+          num[i] += w[k] * p->value[e];
+          num2[i] += w[k] * p->value[e] * p->value[e];
+        } else {
+          num[i] += w[k];
+        }
       }
-      /* fused transform and the two inner products N'W and N'[W(1-W)] */
+      /* fused transform and the two inner products N'W and N'[W(1-W)]
+       * (general form with covariate values: N'A and N'(B - A^2)) */
       double G = 0.0, H = 0.0;
       for (int32_t t = 0; t < nt; ++t) {
         int32_t i = touched[t];
         /* W_i = 0 adds nothing (also when all of the patient's eras have
          * length 0, where den_i = 0 too and such a patient has n_i = 0) */
-        if (num[i] == 0.0) continue;
-        double W = num[i] / den[i];
-        G += wn[i] * W;
-        H += wn[i] * W * (1.0 - W);
+        if (num[i] == 0.0 && num2[i] == 0.0) continue;
+        if (p->value) {
+          double A = num[i] / den[i], B = num2[i] / den[i];
+          G += wn[i] * A;
+          H += wn[i] * (B - A * A);
+        } else {
+          double W = num[i] / den[i];
+          G += wn[i] * W;
+          H += wn[i] * W * (1.0 - W);
+        }
       }
       double g = ytx[j] - G, h = -H;
       double dv = ora_newton_step(prior_kind, var, beta[j], g, h);
@@ -250,7 +294,8 @@ int ora_ccd(const ora_problem* p, int32_t prior_kind, double var, double* beta,
         beta[j] += db;
         for (int64_t e = p->col_ptr[j]; e < p->col_ptr[j + 1]; ++e) {
           int64_t k = p->row_idx[e];
-          eta[k] += db;
+          if (p->value) eta[k] += db * p->value[e];
+          else eta[k] += db;
           w[k] = (double)p->offset[k] * exp(eta[k]);
         }
         for (int32_t t = 0; t < nt; ++t) {
@@ -260,7 +305,7 @@ int ora_ccd(const ora_problem* p, int32_t prior_kind, double var, double* beta,
           den[i] = s;
         }
       }
-      for (int32_t t = 0; t < nt; ++t) num[touched[t]] = 0.0;
+      for (int32_t t = 0; t < nt; ++t) num[touched[t]] = num2[touched[t]] = 0.0;
     }
     ++sweep;
     double L;
@@ -283,6 +328,7 @@ int ora_ccd(const ora_problem* p, int32_t prior_kind, double var, double* beta,
   res->converged = converged;
   res->loglik = L;
   res->logpost = L + ora_log_prior(prior_kind, var, J, beta);
-  free(eta); free(eta_prev); free(w); free(pid); free(den); free(num); free(wn); free(ytx); free(touched);
+  free(eta); free(eta_prev); free(w); free(pid); free(den); free(num); free(num2); free(wn); free(ytx);
+  free(touched);
   return 0;
 }

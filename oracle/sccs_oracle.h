@@ -33,6 +33,7 @@ typedef struct ora_problem {
   const int64_t* col_ptr;      /* [J+1] CSC column pointers */
   const int32_t* row_idx;      /* [nnz] CSC rows, ascending within a column */
   const int32_t* weight;       /* [N] patient weight (CV / bootstrap), NULL = 1 */
+  const double* value;         /* [nnz] covariate values x_kj in CSC order, NULL = all 1 (binary) */
 } ora_problem;
 
 enum { ORA_PRIOR_NONE = 0, ORA_PRIOR_NORMAL = 1, ORA_PRIOR_LAPLACE = 2 };
@@ -52,7 +53,8 @@ int ora_loglik(const ora_problem* p, const double* beta, double* loglik);
  * -sqrt(2/var) sum |b|, none 0. */
 double ora_log_prior(int32_t kind, double var, int32_t J, const double* beta);
 
-/* g_j and h_j of Eqs. 7-9 at beta (likelihood only, no prior). */
+/* g_j and h_j of Eqs. 7-9 at beta (likelihood only, no prior).  With
+ * covariate values the Hessian takes its general form (see the .c file). */
 int ora_grad_hess(const ora_problem* p, const double* beta, int32_t j, double* g, double* h);
 
 /* Unbounded single-coordinate step of Eq. 4 under the prior (see the .c

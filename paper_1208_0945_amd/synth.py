@@ -29,7 +29,16 @@ Layout of a ``Problem`` (all numpy, C-contiguous):
   patient_ptr[i] .. patient_ptr[i+1]-1 (rows grouped by patient).
 * ``offset`` int32 [K]: l_ik; ``count`` int32 [K]: y_ik.
 * ``col_ptr`` int64 [J+1], ``row_idx`` int32 [nnz]: X in compressed column
-  storage; rows strictly ascending inside each column; values are all one.
+  storage; rows strictly ascending inside each column; values are all one
+  unless ``value`` (float64 [nnz]) holds non-binary covariate values.
+
+Non-binary covariates (``valued``; the paper's discussion names dense
+covariates such as baseline measurements): besides binary drugs, sparse
+"dose" columns whose exposed eras carry a dose level, and dense columns
+present on every era that vary within a patient (an age-like covariate,
+baseline age plus elapsed time, standardised; a seasonal cosine of the era's
+calendar position).  A covariate constant within a patient cancels from the
+conditional likelihood, so only within-patient variation is generated.
 """
 from __future__ import annotations
 
@@ -55,6 +64,7 @@ class Problem:
     row_idx: np.ndarray
     beta_true: np.ndarray
     seed_info: str = ""
+    value: Optional[np.ndarray] = None   # float64 [nnz] covariate values (CSC order), None = binary
 
     @property
     def n_rows(self) -> int:
@@ -159,6 +169,73 @@ def make_problem(name: str, n_patients: int, n_cols: int, era_mean: float,
                    offset=offset, count=count, n_cols=n_cols, col_ptr=col_ptr,
                    row_idx=row_idx, beta_true=beta_true,
                    seed_info=f"root={ROOT_SEED} path={tuple(seed_path)}")
+
+
+def valued(n_patients: int = 5000, n_drugs: int = 40, n_dose: int = 6, n_dense: int = 2, seed: int = 0,
+           era_mean: float = 6.0) -> Problem:
+    """Cases-only SCCS data with non-binary covariates: n_drugs binary drugs
+    (Zipf popularity, p0 = 0.1), n_dose sparse dose columns (exposed with
+    probability 0.1, dose ~ lognormal(0, 0.5)), and n_dense dense columns on
+    every era (even index: age-like, (baseline age + elapsed years - 50) / 10
+    with baseline ~ U[20, 80]; odd index: cos(2 pi t / 365) at the era's
+    midpoint t in days since the patient's first era).  Columns are ordered
+    drugs, doses, dense.  True effects: 8 drugs ~ N(0, 0.5), every dose
+    column ~ N(0, 0.2), dense columns 0.3 and -0.2 alternately."""
+    path = (10, seed)
+    rng = _rng(*path, 9)
+    J = n_drugs + n_dose + n_dense
+    probs = zipf_probs(n_drugs, 0.1, 1.1, rng)
+    beta = np.zeros(J)
+    beta[:n_drugs] = sparse_beta(n_drugs, min(8, n_drugs), 0.5, rng)
+    beta[n_drugs:n_drugs + n_dose] = rng.normal(0.0, math.sqrt(0.2), size=n_dose)
+    beta[n_drugs + n_dose:] = [0.3 if c % 2 == 0 else -0.2 for c in range(n_dense)]
+    rng_eras = _rng(*path, 0)
+    k_i = 1 + rng_eras.poisson(era_mean, size=n_patients).astype(np.int64)
+    patient_ptr = np.zeros(n_patients + 1, dtype=np.int64)
+    np.cumsum(k_i, out=patient_ptr[1:])
+    K = int(patient_ptr[-1])
+    offset = rng_eras.integers(1, 366, size=K, dtype=np.int32)
+    pid = np.repeat(np.arange(n_patients, dtype=np.int64), k_i)
+    # days from the patient's first era to each era's midpoint
+    start = np.cumsum(offset.astype(np.float64)) - offset
+    start -= start[patient_ptr[:-1]][pid]
+    mid_t = start + 0.5 * offset
+    cols, vals = [], []
+    for j in range(n_drugs):
+        r = _bernoulli_rows(_rng(*path, 1, j), K, float(probs[j]))
+        cols.append(r)
+        vals.append(np.ones(len(r)))
+    for c in range(n_dose):
+        g = _rng(*path, 3, c)
+        r = _bernoulli_rows(g, K, 0.1)
+        cols.append(r)
+        vals.append(np.exp(g.normal(0.0, 0.5, size=len(r))))
+    base_age = _rng(*path, 4).uniform(20.0, 80.0, size=n_patients)
+    for c in range(n_dense):
+        cols.append(np.arange(K, dtype=np.int32))
+        if c % 2 == 0:
+            vals.append((base_age[pid] + mid_t / 365.0 - 50.0) / 10.0)
+        else:
+            vals.append(np.cos(2.0 * math.pi * mid_t / 365.0))
+    col_ptr = np.zeros(J + 1, dtype=np.int64)
+    np.cumsum([len(c) for c in cols], out=col_ptr[1:])
+    row_idx = np.concatenate(cols).astype(np.int32)
+    value = np.concatenate(vals).astype(np.float64)
+    eta_true = np.zeros(K)
+    for j in range(J):
+        eta_true[cols[j]] += beta[j] * vals[j]
+    mean = offset.astype(np.float64) * np.exp(eta_true) * RATE_PER_DAY
+    rng_y = _rng(*path, 2)
+    count = rng_y.poisson(mean).astype(np.int32)
+    todo = np.flatnonzero(np.bincount(pid, weights=count, minlength=n_patients) == 0)
+    while todo.size:
+        rows = _rows_of(patient_ptr, todo)
+        count[rows] = rng_y.poisson(mean[rows]).astype(np.int32)
+        tot = np.bincount(pid[rows], weights=count[rows], minlength=n_patients)[todo]
+        todo = todo[tot == 0]
+    return Problem(name="valued", n_patients=n_patients, patient_ptr=patient_ptr, offset=offset, count=count,
+                   n_cols=J, col_ptr=col_ptr, row_idx=row_idx, beta_true=beta,
+                   seed_info=f"root={ROOT_SEED} path={path}", value=value)
 
 
 def _rows_of(patient_ptr: np.ndarray, pats: np.ndarray) -> np.ndarray:

@@ -18,9 +18,13 @@ import numpy as np
 
 
 def dense_x(prob) -> np.ndarray:
+    """X as a dense [K, J] matrix: ones at the stored entries of a binary
+    problem, the stored covariate values otherwise."""
     X = np.zeros((prob.n_rows, prob.n_cols))
+    v = getattr(prob, "value", None)
     for j in range(prob.n_cols):
-        X[prob.row_idx[prob.col_ptr[j]:prob.col_ptr[j + 1]], j] = 1.0
+        sl = slice(prob.col_ptr[j], prob.col_ptr[j + 1])
+        X[prob.row_idx[sl], j] = 1.0 if v is None else v[sl]
     return X
 
 

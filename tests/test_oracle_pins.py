@@ -7,6 +7,7 @@ with patient fixed effects fitted by SciPy, a full multivariate Newton on the
 textbook multinomial form, the KKT conditions of the lasso, and invariances
 of the likelihood.
 """
+import dataclasses
 import json
 import math
 import os
@@ -551,3 +552,183 @@ def test_patient_with_zero_total_length_adds_nothing(oracle_lib):
         g, h = oracle_lib.grad_hess(p2, base, j)
         g0, h0 = oracle_lib.grad_hess(prob, base, j)
         assert g == pytest.approx(g0, rel=1e-13, abs=1e-13) and h == pytest.approx(h0, rel=1e-13)
+
+
+# ---------------------------------------------------------------- bootstrap summary (Section 2.5)
+
+def test_bootstrap_quantiles_match_numpy_and_hand_values(oracle_lib):
+    """The percentile rule is linear interpolation between order statistics;
+    numpy's default quantile is that rule, and small cases are done by hand."""
+    rng = np.random.default_rng(11)
+    B = rng.normal(size=(37, 9))
+    B[rng.random(B.shape) < 0.3] = 0.0          # exact zeros, as under the Laplace prior
+    B[:, 4] = 0.0                                # a coefficient that never enters
+    B[:5, 5] = 2.5                               # ties
+    for level in (0.95, 0.9, 0.5):
+        lo, hi, p = oracle_lib.bootstrap_summary(B, level)
+        assert np.allclose(lo, np.quantile(B, 0.5 * (1 - level), axis=0), rtol=0, atol=1e-15)
+        assert np.allclose(hi, np.quantile(B, 0.5 * (1 + level), axis=0), rtol=0, atol=1e-15)
+        assert np.array_equal(p, (B != 0).mean(axis=0))
+    # R = 5, values 1..5 (shuffled): the 25 % / 75 % quantiles sit on order statistics 2 and 4
+    lo, hi, p = oracle_lib.bootstrap_summary(np.array([[3.0], [1.0], [5.0], [2.0], [4.0]]), 0.5)
+    assert (lo[0], hi[0], p[0]) == (2.0, 4.0, 1.0)
+    # R = 4, values 0, 0, 1, 3 at level 0.95: positions 0.075 and 2.925
+    lo, hi, p = oracle_lib.bootstrap_summary(np.array([[0.0], [3.0], [0.0], [1.0]]), 0.95)
+    assert lo[0] == 0.0 and abs(hi[0] - (1.0 + 0.925 * 2.0)) < 1e-15 and p[0] == 0.5
+    # a single replicate: both bounds are its value
+    lo, hi, p = oracle_lib.bootstrap_summary(np.array([[-0.7, 0.0]]), 0.95)
+    assert lo.tolist() == [-0.7, 0.0] and hi.tolist() == [-0.7, 0.0] and p.tolist() == [1.0, 0.0]
+
+
+def test_bootstrap_weights_are_resample_counts():
+    """Replicate weights are multiplicities of N draws with replacement: each
+    row sums to N, and across many replicates each patient's mean is 1."""
+    W = synth.bootstrap_weights(400, 300, seed=2)
+    assert W.shape == (300, 400) and (W >= 0).all()
+    assert (W.sum(axis=1) == 400).all()
+    assert abs(W.mean() - 1.0) < 1e-12
+    assert abs(W.mean(axis=0).mean() - 1.0) < 1e-12 and W.mean(axis=0).std() < 0.15
+
+
+def test_bootstrap_replicate_with_unit_weights_is_the_plain_fit(oracle_lib):
+    """A replicate that draws every patient once is the original fit, and one
+    that draws a patient twice equals the fit on the data with that patient
+    duplicated (the weight multiplies the patient's terms of Eq. 2)."""
+    prob = synth.tiny(n_patients=120, n_cols=6, seed=9)
+    ones = np.ones((1, prob.n_patients), dtype=np.int32)
+    r = oracle_lib.bootstrap(prob, oracle_lib.PRIOR_NORMAL, 1.0, ones, 12)
+    ref = oracle_lib.ccd(prob, oracle_lib.PRIOR_NORMAL, 1.0, 12)["beta"]
+    assert np.array_equal(r["beta"][0], ref)
+    w = ones.copy()
+    w[0, 7] = 2
+    w[0, 8] = 0
+    rw = oracle_lib.bootstrap(prob, oracle_lib.PRIOR_NORMAL, 1.0, w, 12)
+    dup = _resample(prob, [i for i in range(prob.n_patients) if i != 8] + [7])
+    rd = oracle_lib.ccd(dup, oracle_lib.PRIOR_NORMAL, 1.0, 12)["beta"]
+    assert np.max(np.abs(rw["beta"][0] - rd)) <= 1e-12 * max(1.0, np.max(np.abs(rd)))
+
+
+def _resample(prob, patients):
+    """The problem made of the listed patients (repeats allowed), in order."""
+    X = defn.dense_x(prob)
+    rows = [np.arange(prob.patient_ptr[i], prob.patient_ptr[i + 1]) for i in patients]
+    ptr = np.zeros(len(rows) + 1, np.int64)
+    ptr[1:] = np.cumsum([len(r) for r in rows])
+    allr = np.concatenate(rows)
+    Xn = X[allr]
+    return make(ptr, prob.offset[allr], prob.count[allr], [np.flatnonzero(Xn[:, j]) for j in range(prob.n_cols)])
+
+
+# ---------------------------------------------------------------- non-binary covariates (Section 4)
+
+def _valued_small(seed=0, n_patients=250):
+    return synth.valued(n_patients=n_patients, n_drugs=5, n_dose=2, n_dense=2, seed=seed)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_valued_grad_hess_match_complex_step(oracle_lib, seed):
+    """With covariate values, g_j and h_j (the general form of Eqs. 7-9:
+    -sum omega n (M[w x^2]/den - (M[w x]/den)^2)) against derivatives of
+    Eq. 2 taken by the complex step, for drug, dose and dense columns."""
+    prob = _valued_small(seed)
+    X = defn.dense_x(prob)
+    rng = np.random.default_rng(seed)
+    for beta in (np.zeros(prob.n_cols), rng.normal(0, 0.3, prob.n_cols)):
+        for j in range(prob.n_cols):
+            g, h = oracle_lib.grad_hess(prob, beta, j)
+            gc = defn.grad_cs(prob, beta, j, X=X)
+            hf = defn.hess_fd(prob, beta, j, X=X)
+            assert abs(g - gc) <= 1e-11 * max(1.0, abs(gc))
+            assert abs(h - hf) <= 1e-8 * abs(hf)
+            assert h <= 0.0
+    assert oracle_lib.loglik(prob, beta) == pytest.approx(float(np.real(defn.loglik(prob, beta, X=X))), rel=1e-13)
+
+
+@pytest.mark.parametrize("kind,var", [(1, 1.0), (0, 1.0)])
+def test_valued_ccd_reaches_full_newton_optimum(oracle_lib, kind, var):
+    """Multivariate Newton with the textbook Hessian -sum n_i Cov_i(x) on
+    real-valued x, against CCD run to convergence."""
+    prob = _valued_small(2, n_patients=400)
+    X = defn.dense_x(prob)
+    b = np.zeros(prob.n_cols)
+    for _ in range(80):
+        g, H = defn.grad_hess_full(prob, b, X=X)
+        if kind == 1:
+            g = g - b / var
+            H = H - np.eye(len(b)) / var
+        step = np.linalg.solve(H, -g)
+        b = b + step
+        if np.max(np.abs(step)) < 1e-15:
+            break
+    r = _ccd_converged(oracle_lib, prob, kind, var)
+    assert r["converged"]
+    assert np.max(np.abs(r["beta"] - b)) < 1e-8
+
+
+def test_valued_matches_poisson_glm_with_patient_fixed_effects(oracle_lib):
+    """Profiling out patient intercepts of a Poisson GLM with real-valued
+    covariates gives the conditional MLE."""
+    prob = _valued_small(3, n_patients=120)
+    X = defn.dense_x(prob)
+    pid = defn.patient_of_row(prob)
+    y = prob.count.astype(float)
+    logl = np.log(prob.offset.astype(float))
+    N, J = prob.n_patients, prob.n_cols
+
+    def f(th):
+        phi, b = th[:N], th[N:]
+        eta = phi[pid] + X @ b + logl
+        mu = np.exp(eta)
+        r = y - mu
+        return -np.sum(y * eta - mu), np.concatenate([-np.bincount(pid, weights=r, minlength=N), -(X.T @ r)])
+    res = scipy.optimize.minimize(f, np.zeros(N + J), jac=True, method="L-BFGS-B",
+                                  options={"ftol": 1e-16, "gtol": 1e-11, "maxiter": 20000, "maxcor": 50})
+    r = _ccd_converged(oracle_lib, prob, 0, 1.0)
+    assert np.max(np.abs(r["beta"] - res.x[N:])) < 2e-5
+
+
+def test_valued_scaling_a_column_rescales_its_coefficient(oracle_lib):
+    """Without a prior, multiplying column j's values by c divides the MLE's
+    beta_j by c and leaves the others."""
+    prob = _valued_small(4, n_patients=300)
+    # a fixed number of cycles: the log posterior is flat to 1e-15 well
+    # before beta is settled to 1e-9
+    base = oracle_lib.ccd(prob, 0, 1.0, 400)["beta"]
+    J = prob.n_cols
+    for j, c in ((J - 2, 2.5), (J - 4, 0.4)):
+        v = prob.value.copy()
+        v[prob.col_ptr[j]:prob.col_ptr[j + 1]] *= c
+        scaled = dataclasses.replace(prob, value=v)
+        b = oracle_lib.ccd(scaled, 0, 1.0, 400)["beta"]
+        expect = base.copy()
+        expect[j] /= c
+        assert np.max(np.abs(b - expect)) < 1e-9
+
+
+def test_valued_all_ones_reproduces_the_binary_path(oracle_lib):
+    """Values of 1 at every stored entry are the binary model: same
+    trajectory as the binary problem up to rounding (the valued form
+    evaluates B - A^2 where the binary one evaluates W(1 - W))."""
+    prob = small(5, n_patients=300, n_cols=6, p=0.2)
+    ones = dataclasses.replace(prob, value=np.ones(prob.nnz))
+    for kind, var in ((1, 0.5), (2, 0.3)):
+        a = oracle_lib.ccd(prob, kind, var, 12)
+        b = oracle_lib.ccd(ones, kind, var, 12)
+        assert np.max(np.abs(a["beta"] - b["beta"])) <= 1e-12 * max(1.0, np.max(np.abs(a["beta"])))
+        assert np.array_equal(a["beta"] == 0.0, b["beta"] == 0.0)
+
+
+def test_valued_generator_shapes():
+    """Dense columns cover every era and vary within patients; dose values
+    are positive; drugs are binary."""
+    prob = synth.valued(n_patients=500, n_drugs=6, n_dose=3, n_dense=2, seed=1)
+    c = np.diff(prob.col_ptr)
+    assert (c[-2:] == prob.n_rows).all()
+    d0 = prob.col_ptr[6]
+    assert np.all(prob.value[:d0] == 1.0)
+    assert np.all(prob.value[d0:prob.col_ptr[9]] > 0.0) and np.any(prob.value[d0:prob.col_ptr[9]] != 1.0)
+    age = prob.value[prob.col_ptr[-3]:prob.col_ptr[-2]]
+    pid = defn.patient_of_row(prob)
+    within = np.bincount(pid, weights=age ** 2) / np.diff(prob.patient_ptr) - \
+        (np.bincount(pid, weights=age) / np.diff(prob.patient_ptr)) ** 2
+    assert np.mean(within > 1e-12) > 0.5
