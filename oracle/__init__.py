@@ -8,6 +8,7 @@ library; only the seeded input generator feeds both.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from typing import Optional, Tuple
@@ -37,6 +38,10 @@ class _Problem(ctypes.Structure):
                 ("offset", ctypes.c_void_p), ("count", ctypes.c_void_p),
                 ("col_ptr", ctypes.c_void_p), ("row_idx", ctypes.c_void_p),
                 ("weight", ctypes.c_void_p), ("value", ctypes.c_void_p)]
+
+
+class _Groups(ctypes.Structure):
+    _fields_ = [("n_classes", ctypes.c_int32), ("class_of", ctypes.c_void_p), ("class_var", ctypes.c_double)]
 
 
 class _Result(ctypes.Structure):
@@ -70,6 +75,15 @@ def lib():
                               ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                               ctypes.POINTER(_Result), ctypes.c_void_p, ctypes.c_void_p]
         L.ora_ccd.restype = ctypes.c_int
+        G = ctypes.POINTER(_Groups)
+        L.ora_log_prior_grouped.argtypes = [ctypes.c_double, G, ctypes.c_int32, ctypes.c_void_p]
+        L.ora_log_prior_grouped.restype = ctypes.c_double
+        L.ora_newton_step_grouped.argtypes = [ctypes.c_double] * 6
+        L.ora_newton_step_grouped.restype = ctypes.c_double
+        L.ora_ccd_grouped.argtypes = [P, ctypes.c_double, G, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                      ctypes.POINTER(_Result), ctypes.c_void_p, ctypes.c_void_p]
+        L.ora_ccd_grouped.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -197,3 +211,125 @@ def bootstrap(prob, prior_kind: int, var: float, weights, max_sweeps: int, crite
     betas = np.array([f["beta"] for f in fits])
     lo, hi, p_hat = bootstrap_summary(betas, level)
     return {"beta": betas, "sweeps": np.array([f["sweeps"] for f in fits]), "lo": lo, "hi": hi, "p_hat": p_hat}
+
+
+def cv_predictive_loglik(prob, folds, n_folds: int, prior_kind: int, var: float, max_sweeps: int,
+                         criterion: int = CRIT_REL_LOGPOST, tol: float = 1e-10, beta0=None):
+    """Section 2.5: sum over folds of Eq. 2 over the fold's patients at the
+    MAP fitted on the other folds.  beta0: optional [n_folds, J] start points.
+    Returns (predictive log-likelihood, [n_folds, J] fold betas)."""
+    folds = np.asarray(folds)
+    total, betas = 0.0, []
+    for f in range(n_folds):
+        train = (folds != f).astype(np.int32)
+        held = (folds == f).astype(np.int32)
+        r = ccd(prob, prior_kind, var, max_sweeps, criterion, tol, weight=train,
+                beta0=None if beta0 is None else beta0[f])
+        total += loglik(prob, r["beta"], weight=held)
+        betas.append(r["beta"])
+    return total, np.array(betas)
+
+
+def cv_search(prob, folds, n_folds: int, prior_kind: int, var_start: float, bracket_step: float, log10_tol: float,
+              max_evals: int, max_sweeps: int, criterion: int = CRIT_REL_LOGPOST, tol: float = 1e-10,
+              warm_start: bool = True):
+    """Bracketing and golden-section search of the predictive log-likelihood
+    over t = log10(variance) (Section 2.5 suggests an initial bracketing and
+    an intervaled line search in place of a fixed grid):
+    evaluate t0 and t0 + s; walk on by s in the rising direction until a
+    value falls (the bracket); then golden-section steps inside the bracket,
+    each new point in the larger part at (3 - sqrt 5)/2 of it from the best
+    point, until the bracket is narrower than log10_tol.  Each evaluation
+    starts every fold from its fit at the nearest evaluated variance (in
+    log) when warm_start is set.  Returns dict(variance, pred_loglik [per
+    evaluation], best, bracketed)."""
+    evals_t, evals_f, evals_beta = [], [], []
+
+    def f_at(t):
+        if len(evals_t) >= max_evals:
+            raise StopIteration
+        b0 = None
+        if warm_start and evals_t:
+            near = min(range(len(evals_t)), key=lambda e: abs(evals_t[e] - t))
+            b0 = evals_beta[near]
+        v, B = cv_predictive_loglik(prob, folds, n_folds, prior_kind, 10.0 ** t, max_sweeps, criterion, tol, b0)
+        evals_t.append(t)
+        evals_f.append(v)
+        evals_beta.append(B)
+        return v
+
+    s = math.log10(bracket_step)
+    bracketed = False
+    try:
+        a = math.log10(var_start)
+        b = a + s
+        fa, fb = f_at(a), f_at(b)
+        step = s
+        if fb < fa:
+            a, b, fa, fb = b, a, fb, fa
+            step = -s
+        while True:
+            c = b + step
+            fc = f_at(c)
+            if fc < fb:
+                bracketed = True
+                break
+            a, fa, b, fb = b, fb, c, fc
+        lo, hi = min(a, c), max(a, c)
+        g = 0.5 * (3.0 - math.sqrt(5.0))
+        while hi - lo > log10_tol:
+            x = b + g * (hi - b) if hi - b > b - lo else b - g * (b - lo)
+            fx = f_at(x)
+            if fx > fb:
+                if x > b:
+                    lo = b
+                else:
+                    hi = b
+                b, fb = x, fx
+            else:
+                if x > b:
+                    hi = x
+                else:
+                    lo = x
+    except StopIteration:
+        pass
+    var = [10.0 ** t for t in evals_t]
+    return {"variance": np.array(var), "pred_loglik": np.array(evals_f),
+            "best": int(np.argmax(evals_f)), "bracketed": bracketed}
+
+
+def _groups(class_of, class_var):
+    c = _c(class_of, np.int32)
+    return _Groups(int(c.max()) + 1 if c.size else 1, c.ctypes.data, float(class_var)), c
+
+
+def log_prior_grouped(var: float, class_of, class_var: float, beta) -> float:
+    gr, keep = _groups(class_of, class_var)
+    b = _c(beta, np.float64)
+    return lib().ora_log_prior_grouped(float(var), ctypes.byref(gr), len(b), b.ctypes.data)
+
+
+def newton_step_grouped(var, kappa, beta_j, class_sum, g, h) -> float:
+    return lib().ora_newton_step_grouped(float(var), float(kappa), float(beta_j), float(class_sum), float(g), float(h))
+
+
+def ccd_grouped(prob, var: float, class_of, class_var: float, max_sweeps: int, criterion: int = CRIT_FIXED,
+                tol: float = 0.0, beta0=None, weight=None, want_trace: bool = False):
+    """Algorithm 1 under the grouped Normal prior (see sccs_oracle.h)."""
+    P = _prob(prob, weight)
+    gr, keep = _groups(class_of, class_var)
+    J = P.J
+    beta = np.zeros(J) if beta0 is None else _c(beta0, np.float64).copy()
+    trust = np.ones(J)
+    res = _Result()
+    trace = np.zeros((max(max_sweeps, 1), J, 3)) if want_trace else None
+    lpt = np.zeros(max(max_sweeps, 1))
+    rc = lib().ora_ccd_grouped(ctypes.byref(P.s), float(var), ctypes.byref(gr), beta.ctypes.data, trust.ctypes.data,
+                               int(max_sweeps), int(criterion), float(tol), ctypes.byref(res),
+                               None if trace is None else trace.ctypes.data, lpt.ctypes.data)
+    if rc:
+        raise ValueError(f"ora_ccd_grouped failed ({rc})")
+    n = res.sweeps
+    return {"beta": beta, "trust": trust, "sweeps": n, "converged": bool(res.converged),
+            "loglik": res.loglik, "logpost": res.logpost,
+            "trace": None if trace is None else trace[:n], "logpost_trace": lpt[:n]}

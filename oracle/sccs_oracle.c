@@ -185,15 +185,66 @@ double ora_trust_clamp(double dv, double* trust_io) {
   return d;
 }
 
+/* Members of class c and kappa_c = class_var / (var + m_c class_var). */
+static double group_kappa(double var, const ora_groups* gr, int32_t J, int32_t c) {
+  int32_t m = 0;
+  for (int32_t j = 0; j < J; ++j) m += gr->class_of[j] == c;
+  return gr->class_var / (var + (double)m * gr->class_var);
+}
+
+static double group_sum(const ora_groups* gr, int32_t J, int32_t c, const double* beta) {
+  double s = 0.0;
+  for (int32_t j = 0; j < J; ++j)
+    if (gr->class_of[j] == c) s += beta[j];
+  return s;
+}
+
+double ora_log_prior_grouped(double var, const ora_groups* gr, int32_t J, const double* beta) {
+  double q = 0.0;
+  for (int32_t j = 0; j < J; ++j) q += beta[j] * beta[j];
+  for (int32_t c = 0; c < gr->n_classes; ++c) {
+    double S = group_sum(gr, J, c, beta);
+    q -= group_kappa(var, gr, J, c) * S * S;
+  }
+  return -q / (2.0 * var);
+}
+
+double ora_newton_step_grouped(double var, double kappa, double beta_j, double class_sum, double g, double h) {
+  return -(g - (beta_j - kappa * class_sum) / var) / (h - (1.0 - kappa) / var);
+}
+
+static int ccd_run(const ora_problem* p, int32_t prior_kind, double var, const ora_groups* gr, double* beta,
+                   double* trust, int32_t max_sweeps, int32_t criterion, double tol, ora_result* res, double* trace,
+                   double* logpost_trace);
+
+int ora_ccd(const ora_problem* p, int32_t prior_kind, double var, double* beta, double* trust, int32_t max_sweeps,
+            int32_t criterion, double tol, ora_result* res, double* trace, double* logpost_trace) {
+  return ccd_run(p, prior_kind, var, NULL, beta, trust, max_sweeps, criterion, tol, res, trace, logpost_trace);
+}
+
+int ora_ccd_grouped(const ora_problem* p, double var, const ora_groups* gr, double* beta, double* trust,
+                    int32_t max_sweeps, int32_t criterion, double tol, ora_result* res, double* trace,
+                    double* logpost_trace) {
+  if (!gr || !gr->class_of || gr->n_classes < 1 || !(gr->class_var >= 0.0)) return -1;
+  for (int32_t j = 0; j < p->n_cols; ++j)
+    if (gr->class_of[j] < 0 || gr->class_of[j] >= gr->n_classes) return -1;
+  return ccd_run(p, ORA_PRIOR_NORMAL, var, gr, beta, trust, max_sweeps, criterion, tol, res, trace, logpost_trace);
+}
+
+/* log prior of either kind */
+static double log_prior_of(int32_t kind, double var, const ora_groups* gr, int32_t J, const double* beta) {
+  return gr ? ora_log_prior_grouped(var, gr, J, beta) : ora_log_prior(kind, var, J, beta);
+}
+
 /* Algorithm 1 (cyclic coordinate descent), coordinates visited j = 0..J-1 in
  * order every sweep.  State: eta = X beta, w = L x exp(eta) per era and
  * den = M[w] per patient.  After a nonzero step on column j the three are
  * brought up to date (Steps 1-3 of Section 2.4): eta and w on the column's
  * rows, and den recomputed from all eras of every patient the column touches
  * (an exact recomputation rather than an increment). */
-int ora_ccd(const ora_problem* p, int32_t prior_kind, double var, double* beta,
-            double* trust, int32_t max_sweeps, int32_t criterion, double tol,
-            ora_result* res, double* trace, double* logpost_trace) {
+static int ccd_run(const ora_problem* p, int32_t prior_kind, double var, const ora_groups* gr, double* beta,
+                   double* trust, int32_t max_sweeps, int32_t criterion, double tol, ora_result* res, double* trace,
+                   double* logpost_trace) {
   if (check_problem(p) || !beta || !trust || !res || max_sweeps < 0) return -1;
   if ((prior_kind == ORA_PRIOR_NORMAL || prior_kind == ORA_PRIOR_LAPLACE) && !(var > 0.0)) return -1;
   int64_t K = p->n_rows, N = p->n_patients;
@@ -246,7 +297,7 @@ int ora_ccd(const ora_problem* p, int32_t prior_kind, double var, double* beta,
   if (criterion == ORA_CRIT_REL_LOGPOST) {
     double L;
     ora_loglik(p, beta, &L);
-    lp_prev = L + ora_log_prior(prior_kind, var, J, beta);
+    lp_prev = L + log_prior_of(prior_kind, var, gr, J, beta);
   }
   int32_t sweep = 0, converged = 0;
   while (sweep < max_sweeps) {
@@ -284,7 +335,13 @@ int ora_ccd(const ora_problem* p, int32_t prior_kind, double var, double* beta,
         }
       }
       double g = ytx[j] - G, h = -H;
-      double dv = ora_newton_step(prior_kind, var, beta[j], g, h);
+      double dv;
+      if (gr) {   /* the class sum at the current beta, recomputed at every visit */
+        int32_t c = gr->class_of[j];
+        dv = ora_newton_step_grouped(var, group_kappa(var, gr, J, c), beta[j], group_sum(gr, J, c, beta), g, h);
+      } else {
+        dv = ora_newton_step(prior_kind, var, beta[j], g, h);
+      }
       double db = ora_trust_clamp(dv, &trust[j]);
       if (trace) {
         double* tr = trace + ((size_t)sweep * (size_t)J + (size_t)j) * 3;
@@ -310,7 +367,7 @@ int ora_ccd(const ora_problem* p, int32_t prior_kind, double var, double* beta,
     ++sweep;
     double L;
     ora_loglik(p, beta, &L);
-    double lp = L + ora_log_prior(prior_kind, var, J, beta);
+    double lp = L + log_prior_of(prior_kind, var, gr, J, beta);
     if (logpost_trace) logpost_trace[sweep - 1] = lp;
     if (criterion == ORA_CRIT_REL_LOGPOST) {
       if (fabs(lp - lp_prev) < tol * fabs(lp)) { converged = 1; }
@@ -327,7 +384,7 @@ int ora_ccd(const ora_problem* p, int32_t prior_kind, double var, double* beta,
   res->sweeps = sweep;
   res->converged = converged;
   res->loglik = L;
-  res->logpost = L + ora_log_prior(prior_kind, var, J, beta);
+  res->logpost = L + log_prior_of(prior_kind, var, gr, J, beta);
   free(eta); free(eta_prev); free(w); free(pid); free(den); free(num); free(num2); free(wn); free(ytx);
   free(touched);
   return 0;

@@ -63,6 +63,31 @@ int ora_grad_hess(const ora_problem* p, const double* beta, int32_t j, double* g
 double ora_newton_step(int32_t kind, double var, double beta_j, double g, double h);
 double ora_trust_clamp(double dv, double* trust_io);
 
+/* Grouped ("hierarchical") Normal prior, one of the richer priors Section 4
+ * proposes to borrow strength across drugs of one class: drug j of class
+ * c = class_of[j] has beta_j = mu_c + b_j with b_j ~ N(0, var) and the class
+ * mean mu_c ~ N(0, class_var).  Integrating mu_c out, a class of m drugs
+ * has covariance var I + class_var 1 1', whose inverse is
+ * (I - kappa_c 1 1') / var with kappa_c = class_var / (var + m class_var). */
+typedef struct ora_groups {
+  int32_t n_classes;
+  const int32_t* class_of;  /* [J] in [0, n_classes) */
+  double class_var;         /* >= 0; 0 gives the independent Normal prior */
+} ora_groups;
+
+/* log p(beta) of the grouped prior, constants dropped:
+ * -sum_c (sum_{j in c} beta_j^2 - kappa_c S_c^2) / (2 var), S_c = sum_{j in c} beta_j. */
+double ora_log_prior_grouped(double var, const ora_groups* gr, int32_t J, const double* beta);
+
+/* Eq. 4 under the grouped prior: d log p / d beta_j = -(beta_j - kappa S)/var,
+ * d2 log p / d beta_j^2 = -(1 - kappa)/var, with S the class sum at beta. */
+double ora_newton_step_grouped(double var, double kappa, double beta_j, double class_sum, double g, double h);
+
+/* Algorithm 1 under the grouped prior (arguments as ora_ccd). */
+int ora_ccd_grouped(const ora_problem* p, double var, const ora_groups* gr, double* beta_io, double* trust_io,
+                    int32_t max_sweeps, int32_t criterion, double tol, ora_result* res, double* trace,
+                    double* logpost_trace);
+
 /* Algorithm 1.  beta_io/trust_io ([J]) hold the start point (warm start) and
  * receive the result.  criterion/tol select the stopping rule; at most
  * max_sweeps cycles run.  trace (nullable) receives g, h, delta-beta of every

@@ -732,3 +732,107 @@ def test_valued_generator_shapes():
     within = np.bincount(pid, weights=age ** 2) / np.diff(prob.patient_ptr) - \
         (np.bincount(pid, weights=age) / np.diff(prob.patient_ptr)) ** 2
     assert np.mean(within > 1e-12) > 0.5
+
+
+# ---------------------------------------------------------------- prior-variance search (Section 2.5)
+
+def test_cv_search_finds_the_grid_maximum(oracle_lib):
+    """The bracketing + golden-section search ends within its tolerance of
+    the maximum that a brute-force scan of the predictive log-likelihood on a
+    fine log10 grid finds; its bracket holds that maximum; each reported
+    value equals a direct evaluation."""
+    prob = synth.zipf_problem("zipf_small", 1500, 12, 0.15, seed_path=(8, 7))
+    folds = synth.cv_folds(prob.n_patients, 4, seed=3)
+    for kind in (1, 2):
+        r = oracle_lib.cv_search(prob, folds, 4, kind, 1e-2, 10.0, 0.05, 40, 400, tol=1e-12)
+        assert r["bracketed"]
+        grid = np.linspace(-3.0, 2.0, 101)
+        vals = [oracle_lib.cv_predictive_loglik(prob, folds, 4, kind, 10.0 ** t, 400, tol=1e-12)[0] for t in grid]
+        t_best = grid[int(np.argmax(vals))]
+        t_found = np.log10(r["variance"][r["best"]])
+        assert abs(t_found - t_best) <= 0.05 + 0.05        # search tolerance + grid spacing
+        assert r["pred_loglik"][r["best"]] >= max(vals) - 1e-6 * abs(max(vals))
+        k = len(r["variance"]) // 2
+        direct = oracle_lib.cv_predictive_loglik(prob, folds, 4, kind, r["variance"][k], 400, tol=1e-12)[0]
+        assert abs(direct - r["pred_loglik"][k]) <= 1e-8 * abs(direct)
+
+
+def test_cv_predictive_loglik_is_the_heldout_sum(oracle_lib):
+    """Definition check: with two folds the predictive log-likelihood is
+    L(beta_A; fold B) + L(beta_B; fold A), each beta fitted on the other
+    fold alone."""
+    prob = small(31, n_patients=200, n_cols=4, p=0.25)
+    folds = (np.arange(prob.n_patients) % 2).astype(np.int32)
+    pl, B = oracle_lib.cv_predictive_loglik(prob, folds, 2, 1, 0.5, 200, tol=1e-13)
+    bA = oracle_lib.ccd(prob, 1, 0.5, 200, oracle_lib.CRIT_REL_LOGPOST, 1e-13, weight=(folds == 1).astype(np.int32))["beta"]
+    bB = oracle_lib.ccd(prob, 1, 0.5, 200, oracle_lib.CRIT_REL_LOGPOST, 1e-13, weight=(folds == 0).astype(np.int32))["beta"]
+    expect = float(np.real(defn.loglik(prob, bA, weight=(folds == 0)))) + \
+        float(np.real(defn.loglik(prob, bB, weight=(folds == 1))))
+    assert abs(pl - expect) <= 1e-10 * abs(expect)
+
+
+# ---------------------------------------------------------------- grouped prior (Section 4)
+
+def _class_precision(class_of, var, class_var):
+    """The prior precision matrix: the inverse of var I + class_var 1 1' within
+    each class, inverted numerically (not by the closed form the oracle uses)."""
+    J = len(class_of)
+    Q = np.zeros((J, J))
+    for c in np.unique(class_of):
+        idx = np.flatnonzero(class_of == c)
+        S = var * np.eye(len(idx)) + class_var * np.ones((len(idx), len(idx)))
+        Q[np.ix_(idx, idx)] = np.linalg.inv(S)
+    return Q
+
+
+def test_grouped_prior_map_matches_full_newton(oracle_lib):
+    """MAP under beta ~ N(0, blockdiag(var I + class_var 1 1')): full
+    multivariate Newton with the numerically inverted prior covariance
+    against CCD under the grouped prior; stationarity g = Q beta."""
+    prob = small(41, n_patients=400, n_cols=8, p=0.2)
+    class_of = np.array([0, 0, 1, 1, 1, 2, 0, 2], dtype=np.int32)
+    var, cvar = 0.3, 0.8
+    Q = _class_precision(class_of, var, cvar)
+    X = defn.dense_x(prob)
+    b = np.zeros(prob.n_cols)
+    for _ in range(60):
+        g, H = defn.grad_hess_full(prob, b, X=X)
+        step = np.linalg.solve(H - Q, -(g - Q @ b))
+        b = b + step
+        if np.max(np.abs(step)) < 1e-15:
+            break
+    r = oracle_lib.ccd_grouped(prob, var, class_of, cvar, 3000, oracle_lib.CRIT_FIXED)
+    assert np.max(np.abs(r["beta"] - b)) < 1e-9
+    g, _ = defn.grad_hess_full(prob, r["beta"], X=X)
+    assert np.max(np.abs(g - Q @ r["beta"])) < 1e-8
+
+
+def test_grouped_log_prior_against_the_gaussian_density(oracle_lib):
+    """Differences of the log prior equal differences of -b'Qb/2 with Q the
+    numerically inverted covariance (the dropped constant cancels)."""
+    class_of = np.array([0, 1, 0, 2, 1, 0], dtype=np.int32)
+    var, cvar = 0.5, 2.0
+    Q = _class_precision(class_of, var, cvar)
+    rng = np.random.default_rng(4)
+    for _ in range(5):
+        b1, b2 = rng.normal(size=6), rng.normal(size=6)
+        d_or = oracle_lib.log_prior_grouped(var, class_of, cvar, b1) - oracle_lib.log_prior_grouped(var, class_of, cvar, b2)
+        d_ref = -0.5 * (b1 @ Q @ b1) + 0.5 * (b2 @ Q @ b2)
+        assert abs(d_or - d_ref) < 1e-12 * max(1.0, abs(d_ref))
+
+
+def test_grouped_prior_special_cases(oracle_lib):
+    """class_var = 0 is the independent Normal prior (the same steps, bit for
+    bit); a class of one drug is a Normal prior with variance
+    var + class_var."""
+    prob = small(43, n_patients=300, n_cols=6, p=0.2)
+    a = oracle_lib.ccd(prob, 1, 0.4, 15)
+    b = oracle_lib.ccd_grouped(prob, 0.4, np.array([0, 0, 1, 1, 1, 0]), 0.0, 15)
+    assert np.array_equal(a["beta"], b["beta"]) and np.array_equal(a["trust"], b["trust"])
+    singles = np.arange(prob.n_cols, dtype=np.int32)
+    c = oracle_lib.ccd_grouped(prob, 0.4, singles, 0.6, 400)
+    d = oracle_lib.ccd(prob, 1, 1.0, 400)
+    assert np.max(np.abs(c["beta"] - d["beta"])) < 1e-12
+    # hand value of one step: g = 2, h = -5, var = 0.5, kappa = 0.25, beta = 0.2, S = 1
+    dv = oracle_lib.newton_step_grouped(0.5, 0.25, 0.2, 1.0, 2.0, -5.0)
+    assert dv == pytest.approx(-(2.0 - (0.2 - 0.25) / 0.5) / (-5.0 - 0.75 / 0.5), rel=1e-15)
