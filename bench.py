@@ -350,6 +350,68 @@ def paper_fit_bench(sccs, synth, max_sweeps=1000):
     return out
 
 
+def coord_curve(sccs, synth, workload, n_workgroups, sweeps_at=(1, 2, 10), c_star=240_000):
+    """Achieved bandwidth per coordinate against its column size (one-pass
+    form, FP64, from beta = 0 under the workload's prior).  For each listed
+    sweep the device stamps the moment every column group's steps are
+    taken; a group's time is the gap to the previous group's stamp and its
+    algorithmic bytes are those of bytes_per_sweep for its columns (phase B
+    only for columns whose step was nonzero).  Reported: the curve
+    (median GB/s per power-of-two bucket of the group's nonzeros) and, over
+    the columns with at least c_star nonzeros, the nonzero-weighted
+    fraction of HBM peak (their bytes over their time)."""
+    import torch
+    if workload == "full":
+        prob, kind, var = synth.full(), sccs.PRIOR_NORMAL, 0.5
+    else:
+        prob, kind, var = synth.mid(), sccs.PRIOR_LAPLACE, 2.0
+    c, p = column_stats(prob)
+    out = {"workload": f"{workload} SCCS: {prob.n_patients} patients, {prob.n_rows} eras, J={prob.n_cols}, "
+                       f"{prob.nnz} nonzeros, FP64, one pass per column group, {n_workgroups or 'all'} workgroups",
+           "c_star": c_star, "sweeps": {}}
+    with sccs.Handle(prob, n_workgroups=n_workgroups, merge_passes=0) as h:
+        h.set_prior(kind, var)
+        beta_prev = np.zeros(prob.n_cols)
+        for s in range(1, max(sweeps_at) + 1):
+            h.sweep(1)
+            beta, _ = h.get_beta()
+            if s not in sweeps_at:
+                beta_prev = beta
+                continue
+            t, fc = h.group_times()
+            moved = beta != beta_prev
+            beta_prev = beta
+            dt = np.diff(np.concatenate([[0.0], t]))
+            ng = len(dt)
+            gc = np.array([c[fc[g]:fc[g + 1]].sum() for g in range(ng)])
+            gb = np.array([bytes_per_sweep(c[fc[g]:fc[g + 1]], p[fc[g]:fc[g + 1]], moved[fc[g]:fc[g + 1]], 0)
+                           for g in range(ng)])
+            gbs = gb / (dt * 1e-6) / 1e9
+            buckets = []
+            lo = 1
+            while lo <= gc.max():
+                sel = (gc >= lo) & (gc < 2 * lo)
+                if sel.any():
+                    buckets.append({"nnz_from": int(lo), "nnz_to": int(2 * lo - 1), "groups": int(sel.sum()),
+                                    "median_us": float(np.median(dt[sel])),
+                                    "median_GBs": float(np.median(gbs[sel])),
+                                    "sum_GBs": float(gb[sel].sum() / (dt[sel].sum() * 1e-6) / 1e9)})
+                lo *= 2
+            big = gc >= c_star
+            frac_big = float(gb[big].sum() / (dt[big].sum() * 1e-6) / 1e9 / HBM_PEAK_GBS) if big.any() else None
+            out["sweeps"][str(s)] = {
+                "sweep_ms": float(t[-1] * 1e-3), "groups": ng, "moved_columns": int(moved.sum()),
+                "groups_at_or_above_c_star": int(big.sum()),
+                "nnz_share_at_or_above_c_star": float(gc[big].sum() / gc.sum()),
+                "time_share_at_or_above_c_star": float(dt[big].sum() / dt.sum()),
+                "frac_of_peak_at_or_above_c_star": frac_big,
+                "whole_sweep_GBs": float(gb.sum() / (t[-1] * 1e-6) / 1e9),
+                "buckets": buckets}
+            print(f"[bench] coordinate curve, sweep {s}: {t[-1] * 1e-3:.2f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -369,6 +431,8 @@ def main():
     ap.add_argument("--print-sha", action="store_true", help="print the sweep kernel's source hash and exit")
     ap.add_argument("--cv-max-sweeps", type=int, default=50)
     ap.add_argument("--cv-tol", type=float, default=1e-8)
+    ap.add_argument("--coord-curve", action="store_true",
+                    help="per-coordinate achieved bandwidth against column size (mid or full workload)")
     # The single fit is bound by its chain of device-wide reductions, not by
     # bandwidth: on mid, 128 persistent workgroups (16 per XCD, half the CUs)
     # finish a sweep about 2 % sooner than one per CU, because each
@@ -400,6 +464,10 @@ def main():
         prob = synth.mid(n_patients=args.patients, n_cols=args.cols)
         best, table = sccs.tune(prob, sccs.PRIOR_LAPLACE, 2.0, n_sweeps=3)
         print(json.dumps({"tune_best": best, "candidates": table}), flush=True)
+        return
+    if args.coord_curve:
+        print(json.dumps(coord_curve(sccs, synth, args.workload, args.workgroups if args.workload == "mid" else 0)),
+              flush=True)
         return
     if args.workload == "paper":
         print(json.dumps(paper_fit_bench(sccs, synth)), flush=True)

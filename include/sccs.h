@@ -63,7 +63,7 @@ typedef int32_t sccs_status;
 #define SCCS_ERR_NUMERIC (-5)      /* non-finite g, h or beta; last finite beta kept */
 #define SCCS_ERR_SYNC (-6)         /* the device-wide reduction did not complete */
 
-enum { SCCS_PRIOR_NONE = 0, SCCS_PRIOR_NORMAL = 1, SCCS_PRIOR_LAPLACE = 2 };
+enum { SCCS_PRIOR_NONE = 0, SCCS_PRIOR_NORMAL = 1, SCCS_PRIOR_LAPLACE = 2, SCCS_PRIOR_GROUPED = 3 };
 enum { SCCS_PREC_FP64 = 0, SCCS_PREC_MIXED = 1 };
 enum { SCCS_CRIT_FIXED = 0, SCCS_CRIT_REL_LOGPOST = 1, SCCS_CRIT_ABS_DXBETA = 2 };
 
@@ -75,9 +75,19 @@ typedef struct sccs_handle sccs_handle;
  *                 ptr[0] = 0, non-decreasing, ptr[N] = n_rows.
  *   offset      [K] int32: era length l_k >= 0.
  *   count       [K] int32: events y_k >= 0; y_k > 0 requires l_k > 0.
- *   col_ptr     [J+1] int64: X in compressed column storage (values all 1).
+ *   col_ptr     [J+1] int64: X in compressed column storage.
  *   row_idx     [nnz] int32: rows of each column, strictly increasing.
  *   patient_weight [N] int32 >= 0, or NULL for all ones.
+ *   value       [nnz] double, finite: covariate values x_kj in the order of
+ *                 row_idx, or NULL for binary exposures (all stored entries
+ *                 1, the paper's drug eras).  Non-binary and dense covariates
+ *                 (Section 4: baseline measurements, doses) take the general
+ *                 form of Eqs. 7-9: g_j = sum omega y x - sum omega n A_i and
+ *                 h_j = -sum omega n (B_i - A_i^2), with A_i = M[w x X_j]_i/den_i
+ *                 and B_i = M[w x X_j^2]_i/den_i, and a step multiplies
+ *                 exp(X beta) by exp(delta x_kj) entry by entry.  A dense
+ *                 column is a column that stores every row.  The batched form
+ *                 takes binary problems only.
  * Limits: N, K, J >= 1; N < 2^28; K < 2^31; nnz < 2^31.  Patients without events
  * (n_i = 0) are accepted and carry no information (cases-only design).
  */
@@ -92,6 +102,7 @@ typedef struct sccs_problem {
   const int64_t* col_ptr;
   const int32_t* row_idx;
   const int32_t* patient_weight;
+  const double* value;
 } sccs_problem;
 
 typedef struct sccs_options {
@@ -155,8 +166,28 @@ sccs_status sccs_create(const sccs_problem* prob, const sccs_options* opts, void
 sccs_status sccs_destroy(sccs_handle* h);
 
 /* Prior of Eq. 3: kind SCCS_PRIOR_NONE / _NORMAL / _LAPLACE; variance > 0
- * (ignored for NONE).  Changes nothing else (beta and trust are kept). */
+ * (ignored for NONE).  Changes nothing else (beta and trust are kept).
+ * (SCCS_PRIOR_GROUPED is set by sccs_set_prior_grouped.) */
 sccs_status sccs_set_prior(sccs_handle* h, int32_t kind, double variance);
+
+/* Grouped Normal prior, a hierarchical prior of the kind Section 4 proposes
+ * (drugs grouped a priori into classes borrow strength from each other):
+ * drug j of class c = class_of[j] has beta_j = mu_c + b_j with
+ * b_j ~ N(0, variance) and the class mean mu_c ~ N(0, class_variance).
+ * Integrating mu_c out, a class of m drugs has covariance
+ * variance I + class_variance 1 1', so Eq. 4 takes
+ *   d log p / d beta_j = -(beta_j - kappa_c S_c) / variance,
+ *   d2 log p / d beta_j^2 = -(1 - kappa_c) / variance,
+ * with kappa_c = class_variance / (variance + m class_variance) and S_c the
+ * sum of the class's coefficients (kept on the device as steps are taken;
+ * columns of one class are stepped in column order, also inside a column
+ * group).  class_variance = 0 is the Normal prior; a class of one drug is
+ * a Normal prior of variance variance + class_variance.  class_of: [J] host
+ * int32 in [0, n_classes), 1 <= n_classes <= J; variance > 0;
+ * class_variance >= 0.  Single fits only; the merged-pass form is not used
+ * under this prior.  Changes nothing else (beta and trust are kept). */
+sccs_status sccs_set_prior_grouped(sccs_handle* h, double variance, double class_variance, int32_t n_classes,
+                                   const int32_t* class_of);
 
 /* Warm start: copy beta [J] (host) and trust [J] (host, or NULL for all
  * ones), then recompute w = L x exp(X beta) and den = M w exactly. */
@@ -199,6 +230,17 @@ sccs_status sccs_last_kernel_ms(sccs_handle* h, double* ms);
  * zero steps (until that share falls below 35 %).  ERR_STATE before any
  * sweep. */
 sccs_status sccs_pass_stats(sccs_handle* h, int32_t* passes, int32_t* rejects, int32_t* zero_steps);
+
+/* Per-coordinate timing (for achieved bandwidth against column size): after
+ * an sccs_sweep / sccs_fit launch in the one-pass-per-group form (a launch
+ * that did not use merged passes; binary covariates), t_us[g] is the time
+ * from the start of that launch's last sweep to the moment column group g's
+ * steps were taken, in microseconds of the device wall clock, for the
+ * n_groups groups; group g holds columns [first_col[g], first_col[g+1]).
+ * t_us: [max_groups]; first_col: [max_groups + 1].  SCCS_ERR_STATE if no
+ * such launch preceded; SCCS_ERR_INVALID_ARG if max_groups < n_groups
+ * (n_groups is still written).  Synchronises. */
+sccs_status sccs_group_times(sccs_handle* h, int32_t max_groups, double* t_us, int32_t* first_col, int32_t* n_groups);
 
 /* Autotuner: times candidate schedules -- workgroup counts (all compute
  * units, 3/4, 1/2, 1/4 of them) x tile sizes (16, 32, 64 nonzeros) -- on
@@ -280,6 +322,92 @@ sccs_status sccs_batch_destroy(sccs_batch* b);
 
 /* Description of the last error on b, or of the last failed create. */
 const char* sccs_batch_last_error(const sccs_batch* b);
+
+/* ------------------------------------------------------------ bootstrap
+ *
+ * Non-parametric bootstrap over patients (Section 2.5): each replicate r
+ * refits the MAP beta with patient weights omega_i = replicate_weight[r][i]
+ * (the number of times patient i was drawn when N patients are resampled
+ * with replacement; the caller draws them, so results are reproducible from
+ * the caller's generator).  The replicates run as batched fits, up to 64 per
+ * launch, one launch after another in the same workspace, each from
+ * beta = 0 with trust 1 under one prior.  Per coefficient the result is the
+ * percentile interval -- the (1 - level)/2 and (1 + level)/2 quantiles of
+ * the R estimates, by linear interpolation between order statistics
+ * (position (R - 1) q) -- and p_nonzero, the share of replicates whose MAP
+ * estimate is not exactly 0 (under the Laplace prior, the paper's estimate
+ * of the probability that beta_j != 0).  The paper reports level 0.95 over
+ * 200 replicates. */
+typedef struct sccs_bootstrap_out {
+  double* beta;        /* [R][J] each replicate's beta, or NULL */
+  double* ci_lo;       /* [J] lower percentile bound */
+  double* ci_hi;       /* [J] upper percentile bound */
+  double* p_nonzero;   /* [J] share of replicates with beta_j != 0 */
+  int32_t* sweeps;     /* [R] sweeps run per replicate, or NULL */
+  int32_t* converged;  /* [R] 1 if the replicate met the criterion, or NULL */
+} sccs_bootstrap_out;
+
+/* Device bytes sccs_bootstrap needs (a batch of min(R, 64) fits). */
+sccs_status sccs_bootstrap_query_workspace(const sccs_problem* prob, const sccs_options* opts, int32_t n_replicates,
+                                           size_t* bytes);
+
+/* Run R = n_replicates bootstrap fits and summarise them.  replicate_weight:
+ * [R][N] host int32 >= 0.  fo: criterion FIXED or REL_LOGPOST, per
+ * replicate.  level in (0, 1).  workspace as for sccs_batch_create (NULL:
+ * library-allocated for the call).  Errors as for sccs_batch_create and
+ * sccs_batch_run; sccs_batch_last_error(NULL) describes them.
+ * Synchronises. */
+sccs_status sccs_bootstrap(const sccs_problem* prob, const sccs_options* opts, void* workspace, size_t workspace_bytes,
+                           int32_t prior_kind, double variance, int32_t n_replicates, const int32_t* replicate_weight,
+                           const sccs_fit_opts* fo, double level, sccs_bootstrap_out* out);
+
+/* ------------------------------------------------------------ prior-variance search
+ *
+ * Cross-validated choice of the prior variance (Section 2.5): the patients
+ * are split into folds; for a variance, each fold is fitted on the other
+ * folds' patients (one batched launch, one fit per fold) and the held-out
+ * Eq. 2 of its own patients is summed over folds (the predictive
+ * log-likelihood).  Instead of a fixed grid, the search brackets the
+ * maximum and then narrows it, the refinement the paper suggests:
+ *   1. evaluate t0 = log10(var_start) and t0 + s, s = log10(bracket_step);
+ *      walk on in steps of s in the rising direction until a point is
+ *      lower than its predecessor (the bracket lo < t_best < hi);
+ *   2. golden-section search inside the bracket (the new point in the
+ *      larger part, at 0.381966 of it from the current best) until
+ *      hi - lo <= log10_tol.
+ * Each evaluation may start every fold from that fold's fit at the nearest
+ * variance evaluated so far (warm_start), with trust bounds reset to 1.
+ * The search stops early when max_evals evaluations ran (then bracketed may
+ * be 0: the maximum lies beyond the walked range). */
+#define SCCS_CV_MAX_EVALS 64
+typedef struct sccs_cv_opts {
+  int32_t prior_kind;     /* SCCS_PRIOR_NORMAL or SCCS_PRIOR_LAPLACE */
+  int32_t n_folds;        /* 2..64 */
+  const int32_t* fold;    /* [N] fold of each patient, in [0, n_folds) */
+  double var_start;       /* > 0 */
+  double bracket_step;    /* > 1, factor between bracketing evaluations */
+  double log10_tol;       /* > 0, final bracket width in log10(variance) */
+  int32_t max_evals;      /* 3..SCCS_CV_MAX_EVALS */
+  int32_t warm_start;     /* 1 = start folds from the nearest evaluated variance */
+  sccs_fit_opts fit;      /* per fold fit: FIXED or REL_LOGPOST */
+} sccs_cv_opts;
+
+typedef struct sccs_cv_result {
+  int32_t n_evals;                          /* evaluations run */
+  int32_t best;                             /* index of the largest predictive log-likelihood */
+  int32_t bracketed;                        /* 1 if an interior maximum was bracketed */
+  double variance[SCCS_CV_MAX_EVALS];       /* evaluated variances, in order */
+  double pred_loglik[SCCS_CV_MAX_EVALS];    /* their predictive log-likelihoods */
+} sccs_cv_result;
+
+/* Device bytes sccs_cv_search needs (a batch of n_folds fits). */
+sccs_status sccs_cv_query_workspace(const sccs_problem* prob, const sccs_options* opts, int32_t n_folds, size_t* bytes);
+
+/* Run the search; workspace as for sccs_batch_create (NULL:
+ * library-allocated for the call).  Errors as for the batched form;
+ * sccs_batch_last_error(NULL) describes them.  Synchronises. */
+sccs_status sccs_cv_search(const sccs_problem* prob, const sccs_options* opts, void* workspace, size_t workspace_bytes,
+                           const sccs_cv_opts* co, sccs_cv_result* out);
 
 #ifdef __cplusplus
 }

@@ -14,6 +14,7 @@
 #include "sccs_device.hpp"
 #include "sccs_kernels.hpp"
 #include "sccs_batch.hpp"
+#include "sccs_valued.hpp"
 #include "sccs_layout.hpp"
 
 using namespace sccs;
@@ -21,6 +22,7 @@ using namespace sccs;
 struct sccs_handle {
   std::string err;
   int32_t N = 0, J = 0, G = 0, T = 0, prec = 0;
+  int32_t device = 0;   // HIP device current at sccs_create
   int64_t K = 0, nnz = 0;
   hipStream_t stream = nullptr;
   void* ws = nullptr;
@@ -47,6 +49,10 @@ struct sccs_handle {
   int32_t passes = 0, rejects = 0, zero_steps = 0;  // schedule statistics of the last sweep launch
   bool swept = false;
   bool use_merge = false;          // the next sweep launch takes the merged-pass form
+  bool valued = false;             // covariate values: k_ccd_val / k_diag_val
+  bool last_merged = false;        // the last sweep launch used the merged-pass form
+  int32_t n_classes = 0;           // grouped prior: classes (their sums take n_classes doubles of LDS)
+  double class_var = 0.0;
 };
 
 static thread_local std::string g_create_error;
@@ -69,6 +75,10 @@ struct Carver {
 struct Plan {
   uint2* rp;
   int32_t *tile_start, *own, *gcol, *pb, *pptr, *era_ptr, *era_col, *offset, *count, *weight;
+  double *val, *era_val;
+  int32_t* pclass;
+  double* pkappa;
+  uint64_t* group_ticks;
   uint32_t* gdesc;
   uint64_t* moved;
   int64_t* col_ptr;
@@ -79,7 +89,7 @@ struct Plan {
   Ctrl* ctrl;
 };
 
-size_t carve(void* base, const Layout& L, int prec, bool has_weight, Plan& P) {
+size_t carve(void* base, const Layout& L, int prec, bool has_weight, bool has_val, Plan& P) {
   Carver c(base);
   P.rp = c.take<uint2>((size_t)L.nnz + 1);
   P.tile_start = c.take<int32_t>((size_t)L.tiles_cap);
@@ -94,13 +104,18 @@ size_t carve(void* base, const Layout& L, int prec, bool has_weight, Plan& P) {
   P.offset = c.take<int32_t>((size_t)L.K);
   P.count = c.take<int32_t>((size_t)L.K);
   P.weight = has_weight ? c.take<int32_t>((size_t)L.N) : nullptr;
+  P.val = has_val ? c.take<double>((size_t)L.nnz + 1) : nullptr;
+  P.pclass = c.take<int32_t>((size_t)L.J);
+  P.group_ticks = c.take<uint64_t>((size_t)L.J + 1);
+  P.pkappa = c.take<double>((size_t)L.J);
+  P.era_val = has_val ? c.take<double>((size_t)L.nnz + 1) : nullptr;
   P.col_ptr = c.take<int64_t>((size_t)L.J + 1);
   P.w = prec == SCCS_PREC_FP64 ? (void*)c.take<double>((size_t)L.K) : (void*)c.take<float>((size_t)L.K);
   P.pat = c.take<double2>((size_t)L.N);
   P.ytx = c.take<double>((size_t)L.J);
   P.beta = c.take<double>((size_t)L.J);
   P.trust = c.take<double>((size_t)L.J);
-  const size_t n1 = (size_t)2 * kMaxWorkgroups * kSlotWords, n2 = (size_t)2 * kReplicas * kGroups * kSlotWords;
+  const size_t n1 = kSlots1Words, n2 = (size_t)2 * kReplicas * kGroups * kSlotWords;
   P.slots = c.take<uint64_t>(kSlotClasses * kSlots1PerClass);
   P.slots2 = c.take<uint64_t>(kSlotClasses * kSlots2PerClass);
   P.oslots = c.take<uint64_t>(n1);
@@ -153,8 +168,14 @@ sccs_status pick_workgroups(const sccs_options* o, int32_t& G, std::string& err)
 }
 
 // The sweep kernel in its merged-pass form, or in the one-pass-per-group
-// form, which carries less state per pass.
-const void* ccd_kernel(int prec, int mode, bool merge = false) {
+// form, which carries less state per pass; problems with covariate values
+// take the valued sweep (no merged passes) and its diagnostic kernel.
+const void* ccd_kernel(int prec, int mode, bool merge = false, bool valued = false) {
+  if (valued) {
+    if (mode == kModeSweep) return prec == SCCS_PREC_FP64 ? (const void*)k_ccd_val<double> : (const void*)k_ccd_val<float>;
+    if (mode == kModeGradHess)
+      return prec == SCCS_PREC_FP64 ? (const void*)k_diag_val<double> : (const void*)k_diag_val<float>;
+  }
   if (mode == kModeSweep) {
     if (merge) return prec == SCCS_PREC_FP64 ? (const void*)k_ccd<double, true> : (const void*)k_ccd<float, true>;
     return prec == SCCS_PREC_FP64 ? (const void*)k_ccd<double, false> : (const void*)k_ccd<float, false>;
@@ -213,6 +234,14 @@ sccs_status read_ctrl(sccs_handle* h) {
   return SCCS_OK;
 }
 
+// Dynamic LDS of a sweep or diagnostic launch: beta, trust, the sweep-start
+// beta, the patient bitmaps and the moved bits, then the class sums of the
+// grouped prior when it is in use.
+size_t ssum_offset(const sccs_handle* h) { return (h->lds_bytes + 7) / 8; }   // in doubles
+size_t launch_lds(const sccs_handle* h, int prior_kind) {
+  return prior_kind == SCCS_PRIOR_GROUPED ? ssum_offset(h) * 8 + (size_t)h->n_classes * 8 : h->lds_bytes;
+}
+
 sccs_status launch(sccs_handle* h, int mode, int n_sweeps, int criterion, double tol, int want_obj, int diag_j) {
   KArgs a = h->args;
   if (mode == kModeGradHess) {
@@ -225,6 +254,7 @@ sccs_status launch(sccs_handle* h, int mode, int n_sweeps, int criterion, double
   a.var = h->var;
   a.inv_var = 1.0 / h->var;
   a.lambda = (a.prior_kind == SCCS_PRIOR_LAPLACE) ? std::sqrt(2.0 / h->var) : 0.0;
+  a.n_classes = a.prior_kind == SCCS_PRIOR_GROUPED ? h->n_classes : 0;
   a.n_sweeps = n_sweeps;
   a.criterion = criterion;
   a.tol = tol;
@@ -235,12 +265,14 @@ sccs_status launch(sccs_handle* h, int mode, int n_sweeps, int criterion, double
   void* params[] = {&a};
   HIPCHK(h, hipMemsetAsync(&h->args.ctrl->status, 0, sizeof(int32_t), h->stream));
   HIPCHK(h, hipEventRecord(h->ev0, h->stream));
-  const bool merge = a.merge && h->use_merge;
-  if (mode == kModeSweep)   // the mirror holds the state after the previous launch
+  const bool merge = a.merge && h->use_merge && !h->valued && a.prior_kind != SCCS_PRIOR_GROUPED;
+  if (mode == kModeSweep) {   // the mirror holds the state after the previous launch
     for (int c = 0; c < kSlotClasses; ++c) h->gseq0[c] = h->h_ctrl->gseq[c];
+    h->last_merged = merge;
+  }
   h->last_mode = mode;
-  HIPCHK(h, hipLaunchCooperativeKernel(ccd_kernel(h->prec, mode, merge), dim3(h->G), dim3(kBlock), params,
-                                        (unsigned)h->lds_bytes, h->stream));
+  HIPCHK(h, hipLaunchCooperativeKernel(ccd_kernel(h->prec, mode, merge, h->valued), dim3(h->G), dim3(kBlock), params,
+                                        (unsigned)launch_lds(h, a.prior_kind), h->stream));
   HIPCHK(h, hipEventRecord(h->ev1, h->stream));
   h->timed = true;
   return SCCS_OK;
@@ -298,7 +330,8 @@ sccs_status sccs_query_workspace(const sccs_problem* prob, const sccs_options* o
   Layout L;
   layout_dims(prob, G, opts && opts->tile_nnz ? opts->tile_nnz : kTile, L);
   Plan P;
-  *bytes = carve(nullptr, L, opts ? opts->precision : SCCS_PREC_FP64, prob->patient_weight != nullptr, P);
+  *bytes = carve(nullptr, L, opts ? opts->precision : SCCS_PREC_FP64, prob->patient_weight != nullptr,
+                 prob->value != nullptr, P);
   return SCCS_OK;
 }
 
@@ -342,8 +375,9 @@ sccs_status sccs_create(const sccs_problem* prob, const sccs_options* opts_in, v
     return SCCS_ERR_INVALID_ARG;
   }
   const bool has_w = prob->patient_weight != nullptr;
+  const bool has_v = prob->value != nullptr;
   Plan P;
-  size_t need = carve(nullptr, L, opts.precision, has_w, P);
+  size_t need = carve(nullptr, L, opts.precision, has_w, has_v, P);
   if (workspace && workspace_bytes < need) {
     delete h;
     g_create_error = "workspace too small";
@@ -351,7 +385,13 @@ sccs_status sccs_create(const sccs_problem* prob, const sccs_options* opts_in, v
   }
   h->N = L.N; h->J = L.J; h->G = G; h->T = L.n_tiles(); h->K = L.K; h->nnz = L.nnz;
   h->prec = opts.precision;
+  h->valued = has_v;
   h->stream = (hipStream_t)opts.stream;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    g_create_error = "hipGetDevice failed";
+    return SCCS_ERR_HIP;
+  }
   h->refresh_period = opts.refresh_period >= 0 ? opts.refresh_period : (opts.precision == SCCS_PREC_MIXED ? 1 : 0);
   {
     int32_t maxrange = 1;
@@ -393,13 +433,14 @@ sccs_status sccs_create(const sccs_problem* prob, const sccs_options* opts_in, v
 
   // occupancy: every workgroup must be resident at once
   for (const void* k : {ccd_kernel(h->prec, kModeSweep, false), ccd_kernel(h->prec, kModeSweep, true),
-                         ccd_kernel(h->prec, kModeObjective)}) {
+                         ccd_kernel(h->prec, kModeObjective), ccd_kernel(h->prec, kModeSweep, false, true),
+                         ccd_kernel(h->prec, kModeGradHess, false, true)}) {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kBlock, h->lds_bytes) != hipSuccess || per_cu < 1)
       return bail("the persistent kernel cannot be resident (registers or LDS)", SCCS_ERR_HIP);
   }
 
-  carve(h->ws, L, opts.precision, has_w, P);
+  carve(h->ws, L, opts.precision, has_w, has_v, P);
   hipStream_t s = h->stream;
   auto cp = [&](void* dst, const void* src, size_t bytes) {
     return bytes == 0 || hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s) == hipSuccess;
@@ -412,7 +453,8 @@ sccs_status sccs_create(const sccs_problem* prob, const sccs_options* opts_in, v
             cp(P.era_col, L.era_col.data(), L.era_col.size() * 4) &&
             cp(P.offset, prob->offset, (size_t)L.K * 4) && cp(P.count, prob->count, (size_t)L.K * 4) &&
             cp(P.col_ptr, prob->col_ptr, ((size_t)L.J + 1) * 8) &&
-            (!has_w || cp(P.weight, prob->patient_weight, (size_t)L.N * 4));
+            (!has_w || cp(P.weight, prob->patient_weight, (size_t)L.N * 4)) &&
+            (!has_v || (cp(P.val, L.val.data(), L.val.size() * 8) && cp(P.era_val, L.era_val.data(), L.era_val.size() * 8)));
   if (!ok) return bail("copy of the problem to the device failed", SCCS_ERR_HIP);
   std::vector<double> ones((size_t)L.J, 1.0);
   ok = hipMemsetAsync(P.beta, 0, (size_t)L.J * 8, s) == hipSuccess && cp(P.trust, ones.data(), (size_t)L.J * 8) &&
@@ -420,7 +462,7 @@ sccs_status sccs_create(const sccs_problem* prob, const sccs_options* opts_in, v
   if (!ok) return bail("state initialisation failed", SCCS_ERR_HIP);
   // reduction slots start with the tag that reductions 0 and 1 do not expect
   {
-    const size_t n1 = (size_t)2 * kMaxWorkgroups * kSlotWords, n2 = (size_t)2 * kReplicas * kGroups * kSlotWords;
+    const size_t n1 = kSlots1Words, n2 = (size_t)2 * kReplicas * kGroups * kSlotWords;
     hipLaunchKernelGGL(k_fill_u64, dim3(64), dim3(256), 0, s, P.slots, kSlotClasses * kSlots1PerClass, kSign);
     hipLaunchKernelGGL(k_fill_u64, dim3(16), dim3(256), 0, s, P.slots2, kSlotClasses * kSlots2PerClass, kSign);
     hipLaunchKernelGGL(k_fill_u64, dim3(16), dim3(256), 0, s, P.oslots, n1, kSign);
@@ -437,6 +479,8 @@ sccs_status sccs_create(const sccs_problem* prob, const sccs_options* opts_in, v
   a.rp = P.rp; a.tile_start = P.tile_start; a.own = P.own; a.gcol = P.gcol; a.n_groups = L.n_groups;
   a.pb = P.pb; a.pptr = P.pptr;
   a.era_ptr = P.era_ptr; a.era_col = P.era_col; a.offset = P.offset; a.w = P.w; a.pat = P.pat;
+  a.val = P.val; a.era_val = P.era_val;
+  a.pclass = P.pclass; a.pkappa = P.pkappa; a.group_ticks = P.group_ticks; a.n_classes = 0; a.ssum_off = (int32_t)ssum_offset(h);
   a.ytx = P.ytx; a.beta = P.beta; a.trust = P.trust; a.slots = P.slots; a.slots2 = P.slots2;
   a.oslots = P.oslots; a.oslots2 = P.oslots2;
   a.ctrl = P.ctrl; a.N = L.N; a.J = L.J; a.G = G; a.nbits = h->nbits;
@@ -464,7 +508,7 @@ sccs_status sccs_set_prior(sccs_handle* h, int32_t kind, double variance) {
   sccs_status st = usable(h);
   if (st) return st;
   if (kind != SCCS_PRIOR_NONE && kind != SCCS_PRIOR_NORMAL && kind != SCCS_PRIOR_LAPLACE) {
-    h->err = "unknown prior kind";
+    h->err = kind == SCCS_PRIOR_GROUPED ? "the grouped prior is set by sccs_set_prior_grouped" : "unknown prior kind";
     return SCCS_ERR_INVALID_ARG;
   }
   if (kind != SCCS_PRIOR_NONE && !(variance > 0.0 && std::isfinite(variance))) {
@@ -473,6 +517,49 @@ sccs_status sccs_set_prior(sccs_handle* h, int32_t kind, double variance) {
   }
   h->prior_kind = kind;
   h->var = kind == SCCS_PRIOR_NONE ? 1.0 : variance;
+  return SCCS_OK;
+}
+
+sccs_status sccs_set_prior_grouped(sccs_handle* h, double variance, double class_variance, int32_t n_classes,
+                                   const int32_t* class_of) {
+  sccs_status st = usable(h);
+  if (st) return st;
+  if (!(variance > 0.0 && std::isfinite(variance)) || !(class_variance >= 0.0 && std::isfinite(class_variance))) {
+    h->err = "grouped prior: variance must be positive and class_variance >= 0, both finite";
+    return SCCS_ERR_INVALID_ARG;
+  }
+  if (!class_of || n_classes < 1 || n_classes > h->J) {
+    h->err = "grouped prior: class_of must be given and 1 <= n_classes <= n_cols";
+    return SCCS_ERR_INVALID_ARG;
+  }
+  std::vector<int32_t> members((size_t)n_classes, 0);
+  for (int32_t j = 0; j < h->J; ++j) {
+    if (class_of[j] < 0 || class_of[j] >= n_classes) {
+      h->err = "grouped prior: class_of values must be in [0, n_classes)";
+      return SCCS_ERR_INVALID_ARG;
+    }
+    ++members[class_of[j]];
+  }
+  // the class sums live in LDS next to beta and trust
+  {
+    const size_t lds = ssum_offset(h) * 8 + (size_t)n_classes * 8;
+    int per_cu = 0;
+    const void* k = ccd_kernel(h->prec, kModeSweep, false, h->valued);
+    if (lds > 160 * 1024 || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kBlock, lds) != hipSuccess ||
+        per_cu < 1) {
+      h->err = "grouped prior: too many classes for the LDS budget";
+      return SCCS_ERR_INVALID_ARG;
+    }
+  }
+  std::vector<double> kappa((size_t)n_classes);
+  for (int32_t c = 0; c < n_classes; ++c) kappa[c] = class_variance / (variance + (double)members[c] * class_variance);
+  HIPCHK(h, hipMemcpyAsync((void*)h->args.pclass, class_of, (size_t)h->J * 4, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync((void*)h->args.pkappa, kappa.data(), (size_t)n_classes * 8, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  h->prior_kind = SCCS_PRIOR_GROUPED;
+  h->var = variance;
+  h->class_var = class_variance;
+  h->n_classes = n_classes;
   return SCCS_OK;
 }
 
@@ -580,6 +667,26 @@ sccs_status sccs_pass_stats(sccs_handle* h, int32_t* passes, int32_t* rejects, i
   *passes = h->passes;
   *rejects = h->rejects;
   *zero_steps = h->zero_steps;
+  return SCCS_OK;
+}
+
+sccs_status sccs_group_times(sccs_handle* h, int32_t max_groups, double* t_us, int32_t* first_col, int32_t* n_groups) {
+  if (!h || !t_us || !first_col || !n_groups) return SCCS_ERR_INVALID_ARG;
+  if (!h->swept || h->last_mode != kModeSweep || h->last_merged || h->valued) {
+    h->err = "group times need a preceding sccs_sweep / sccs_fit launch in the one-pass-per-group form";
+    return SCCS_ERR_STATE;
+  }
+  const int32_t NG = (int32_t)h->gcol.size() - 1;
+  *n_groups = NG;
+  if (max_groups < NG) { h->err = "max_groups is smaller than the number of column groups"; return SCCS_ERR_INVALID_ARG; }
+  std::vector<uint64_t> ticks((size_t)NG + 1);
+  HIPCHK(h, hipMemcpyAsync(ticks.data(), h->args.group_ticks, ticks.size() * 8, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  int khz = 0;
+  HIPCHK(h, hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h->device));
+  if (khz <= 0) { h->err = "wall-clock rate unknown"; return SCCS_ERR_HIP; }
+  for (int32_t g = 0; g < NG; ++g) t_us[g] = (double)(int64_t)(ticks[g] - ticks[NG]) * 1e3 / khz;
+  for (int32_t g = 0; g <= NG; ++g) first_col[g] = h->gcol[g];
   return SCCS_OK;
 }
 

@@ -36,7 +36,8 @@ constexpr int kPollSleep = SCCS_POLL_SLEEP;
 // number, so that every reduction on a slot array writes and reads the same
 // number of words.
 constexpr int kSlotClasses = kMaxGroup + 1;
-constexpr size_t kSlots1PerClass = (size_t)2 * kMaxWorkgroups * kSlotWords;  // level 1, both parities
+constexpr size_t kSlots1Words = (size_t)2 * kMaxWorkgroups * kSlotWords;  // one level-1 array, both parities
+constexpr size_t kSlots1PerClass = kSlots1Words;
 constexpr size_t kSlots2PerClass = (size_t)2 * kReplicas * kGroups * kSlotWords;
 
 // Control block shared by all workgroups of a launch (device memory).
@@ -67,6 +68,8 @@ struct KArgs {
   const int32_t* pptr;        // [N+1]
   const int32_t* era_ptr;     // [K+1]
   const int32_t* era_col;     // [nnz]
+  const double* val;          // [nnz] covariate values in rp order, NULL for binary exposures
+  const double* era_val;      // [nnz] covariate values in era_col order, NULL for binary exposures
   const int32_t* offset;      // [K]
   void* w;                    // [K] double (FP64) or float (mixed)
   double2* pat;               // [N] (den_i, omega_i n_i)
@@ -93,6 +96,17 @@ struct KArgs {
   int32_t nbits;              // words of each per-workgroup patient bitmap (LDS)
   int32_t mv_words;           // 32-bit words of the moved-column bitmap (LDS copy of moved)
   int32_t merge;              // merge the next group into a pass when predicted independent
+  // grouped Normal prior (prior_kind SCCS_PRIOR_GROUPED): class of each
+  // column, kappa_c = class_var / (var + m_c class_var) per class, and the
+  // offset (in doubles) of the per-class sums in the dynamic LDS area
+  const int32_t* pclass;      // [J]
+  const double* pkappa;       // [n_classes]
+  int32_t n_classes;
+  int32_t ssum_off;
+  // one-pass form: wall-clock ticks at the moment each group's steps were
+  // taken in the current sweep ([n_groups]) and at the sweep's start
+  // ([n_groups]); written by workgroup 0
+  uint64_t* group_ticks;      // [n_groups + 1]
 };
 
 enum { kModeSweep = 0, kModeGradHess = 1, kModeObjective = 2 };

@@ -175,7 +175,7 @@ __device__ bool allreduce2_wave(uint64_t* s1, uint64_t* s2, uint32_t seq, int G,
   const int lane = threadIdx.x & 63, b = blockIdx.x;
   const uint32_t par = seq & 1u, tag = (seq >> 1) & 1u;
   const int ng = G < kGroups ? G : kGroups;
-  uint64_t* L1 = s1 + (size_t)par * kMaxWorkgroups * kSlotWords;
+  uint64_t* L1 = s1 + (size_t)par * (kSlots1Words / 2);
   uint64_t* L2 = s2 + (size_t)par * kReplicas * kGroups * kSlotWords;
   if (lane == 0) {
 #pragma unroll
@@ -311,6 +311,48 @@ __device__ double prior_step(int kind, double inv_var, double lambda, double b, 
   return 0.0;
 }
 
+// Steps of a column group's m columns under the grouped Normal prior
+// (called by the whole poller wave; gg, hh and the results are those of
+// lane c for column j0 + c).  Columns of one class are coupled through the
+// class sum, so the lanes take their steps one after another, in column
+// order, each seeing the class sums the steps before it left (the order of
+// Algorithm 1).
+__device__ __forceinline__ void grouped_steps(const KArgs& a, int j0, int m, bool okr, double gg, double hh,
+                                              double* sbeta, double* strust, double* ssum, double& d, int& bad) {
+  const int lane = threadIdx.x & 63;
+  for (int c = 0; c < m; ++c) {
+    if (lane == c) {
+      bad = !(isfinite(gg) && isfinite(hh));
+      if (okr && !bad) {
+        const int j = j0 + c, k = a.pclass[j];
+        const double bj = sbeta[j], tr = strust[j], kap = a.pkappa[k];
+        const double dv = -(gg - (bj - kap * ssum[k]) / a.var) / (hh - (1.0 - kap) / a.var);
+        d = fmin(fmax(dv, -tr), tr);
+        strust[j] = fmax(2.0 * fabs(d), 0.5 * tr);
+        const double nb = bj + d;
+        if (!isfinite(nb)) {
+          bad = 1;
+          d = 0.0;
+        } else {
+          sbeta[j] = nb;
+          ssum[k] += d;
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// Class sums of the grouped prior from beta, in column order (thread 0;
+// every workgroup forms the same bits).  Caller synchronises.
+__device__ __forceinline__ void class_sums(const KArgs& a, const double* sbeta, double* ssum) {
+  if (threadIdx.x == 0) {
+    for (int c = 0; c < a.n_classes; ++c) ssum[c] = 0.0;
+    for (int j = 0; j < a.J; ++j) ssum[a.pclass[j]] += sbeta[j];
+  }
+}
+
 // ------------------------------------------------------------ precision traits
 
 template <typename WT>
@@ -325,6 +367,9 @@ struct Prec<double> {
 template <>
 struct Prec<float> {
   // exp in FP32 after an FP64 range reduction eta = n ln2 + r, |r| <= ln2/2
+  // (Cody and Waite's two-constant reduction, with ln2 split into a high
+  // part whose low bits are zero, so that n times it is exact, and the
+  // remainder -- the split fdlibm uses for its exp)
   __device__ static float weight(int32_t l, double eta) {
     double n = rint(eta * 1.4426950408889634);
     double r = fma(-n, 6.93147180369123816490e-01, eta);
@@ -855,7 +900,10 @@ __device__ __forceinline__ void refresh_range(const KArgs& a, const double* beta
     double den = 0.0;
     for (int k = a.pptr[i]; k < a.pptr[i + 1]; ++k) {
       double eta = 0.0;
-      for (int c = a.era_ptr[k]; c < a.era_ptr[k + 1]; ++c) eta += beta[(size_t)a.era_col[c] * stride];
+      if (a.era_val)
+        for (int c = a.era_ptr[k]; c < a.era_ptr[k + 1]; ++c) eta += a.era_val[c] * beta[(size_t)a.era_col[c] * stride];
+      else
+        for (int c = a.era_ptr[k]; c < a.era_ptr[k + 1]; ++c) eta += beta[(size_t)a.era_col[c] * stride];
       WT wk = Prec<WT>::weight(a.offset[k], eta);
       w[k] = wk;
       den += (double)wk;
@@ -885,7 +933,7 @@ __device__ __forceinline__ bool objective(const KArgs& a, const double* sbeta, c
       double de = 0.0;
       for (int c = a.era_ptr[k]; c < a.era_ptr[k + 1]; ++c) {
         int jj = a.era_col[c];
-        de += sbeta[jj] - sprev[jj];
+        de += a.era_val ? a.era_val[c] * (sbeta[jj] - sprev[jj]) : sbeta[jj] - sprev[jj];
       }
       loc[2] += fabs(de);
     }
@@ -895,8 +943,13 @@ __device__ __forceinline__ bool objective(const KArgs& a, const double* sbeta, c
   for (int j = tid; j < a.J; j += kBlock) {
     double bj = sbeta[j];
     bl[0] += bj * a.ytx[j];
-    if (a.prior_kind == SCCS_PRIOR_NORMAL) bl[1] -= bj * bj / (2.0 * a.var);
+    if (a.prior_kind == SCCS_PRIOR_NORMAL || a.prior_kind == SCCS_PRIOR_GROUPED) bl[1] -= bj * bj / (2.0 * a.var);
     else if (a.prior_kind == SCCS_PRIOR_LAPLACE) bl[1] -= a.lambda * fabs(bj);
+  }
+  // grouped prior: + kappa_c S_c^2 / (2 var) per class (S_c kept in LDS)
+  if (a.prior_kind == SCCS_PRIOR_GROUPED) {
+    const double* ssum = (const double*)(&sbeta[0]) + a.ssum_off;
+    for (int c = tid; c < a.n_classes; c += kBlock) bl[1] += a.pkappa[c] * ssum[c] * ssum[c] / (2.0 * a.var);
   }
   double part[4];
   block_sum<4>(loc, part, red);
@@ -938,6 +991,10 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
   uint32_t oseq = a.ctrl->oseq;
   int since_refresh = a.ctrl->since_refresh;
   __syncthreads();
+  if (a.prior_kind == SCCS_PRIOR_GROUPED) {
+    class_sums(a, sbeta, lds_dyn + a.ssum_off);
+    __syncthreads();
+  }
 
   const int p0 = a.pb[b], p1 = a.pb[b + 1];
   const int NG = a.n_groups;
@@ -960,6 +1017,7 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
   unsigned* bits1 = bits0 + a.nbits;                  // patients of odd passes
   uint32_t* s_mv = bits1 + a.nbits;                   // moved-column bits (identical in every workgroup)
   for (int i = tid; i < a.mv_words; i += kBlock) s_mv[i] = a.moved[i];
+  double* ssum = lds_dyn + a.ssum_off;                // grouped prior: class sums (set up above)
   __shared__ uint32_t s_nn[1 + kPassGroups];   // merged passes: the pass after next (groups, descriptors), for the poller
   // poller lane 0: rejected merges and coordinate visits with an exactly
   // zero step in this launch
@@ -1327,6 +1385,8 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
         int m = gc1 - j0;
         double ytx_cur = lane < m ? a.ytx[j0 + lane] : 0.0;
         __syncthreads();
+        const bool stamp = b == 0 && lane == 0;
+        if (stamp) a.group_ticks[NG] = wall_clock64();
         for (int g = 0; g < NG; ++g) {
           const bool has_next = g + 1 < NG;
           const int gc3 = g + 3 <= NG ? ld_idx(a.gcol + g + 3) : gc2;
@@ -1377,7 +1437,9 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
             }
           double d = 0.0;
           int bad = 0;
-          if (lane < m) {
+          if (a.prior_kind == SCCS_PRIOR_GROUPED) {
+            grouped_steps(a, j0, m, okr, ytx_cur - Gc, -Hc, sbeta, strust, ssum, d, bad);
+          } else if (lane < m) {
             const double gg = ytx_cur - Gc, hh = -Hc;
             bad = !(isfinite(gg) && isfinite(hh));
             if (okr && !bad) {
@@ -1406,6 +1468,7 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
           }
           n_zero += okr ? m - __popcll(moved) : 0;
           mv_val = (uint32_t)moved;
+          if (stamp) a.group_ticks[g] = wall_clock64();
           __syncthreads();
 #pragma unroll
           for (int c = 0; c < kMaxGroup; ++c)
@@ -1487,6 +1550,10 @@ __global__ void __launch_bounds__(kBlock) k_diag(KArgs a) {
   __syncthreads();
   const int p0 = a.pb[b], p1 = a.pb[b + 1];
   if (a.mode == kModeObjective) {
+    if (a.prior_kind == SCCS_PRIOR_GROUPED) {
+      class_sums(a, sbeta, lds_dyn + a.ssum_off);
+      __syncthreads();
+    }
     double o3[3];
     bool ok = objective(a, sbeta, sbeta, p0, p1, oseq++, o3, red, bc, bci);
     if (b == 0 && tid == 0 && ok) { a.ctrl->loglik = o3[0]; a.ctrl->logpost = o3[1]; }

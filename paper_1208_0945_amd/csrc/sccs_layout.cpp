@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cmath>
 #include <cstdio>
 #include <limits>
 #include <thread>
@@ -95,6 +96,9 @@ sccs_status validate_problem(const sccs_problem* p, std::string& err) {
   if (p->patient_weight)
     for (int64_t i = 0; i < N; ++i)
       if (p->patient_weight[i] < 0) return fail(err, "patient_weight must be >= 0", i);
+  if (p->value)
+    for (int64_t e = 0; e < p->nnz; ++e)
+      if (!std::isfinite(p->value[e])) return fail(err, "covariate values must be finite", e);
   return SCCS_OK;
 }
 
@@ -208,8 +212,10 @@ void build_layout(const sccs_problem* p, int32_t G, Layout& L, int32_t tile_nnz,
       bstart[(size_t)g * G + b + 1] = bstart[(size_t)g * G + b] + n;
     }
 
-  // (row, patient | column-in-group) in group order
+  // (row, patient | column-in-group) in group order, and the covariate
+  // values in the same order
   L.rp.resize((size_t)nnz * 2);
+  if (p->value) L.val.resize((size_t)nnz);
   parallel_ranges(NG, [&](int64_t glo, int64_t ghi) {
     for (int64_t g = glo; g < ghi; ++g)
       for (int32_t b = 0; b < G; ++b) {
@@ -220,6 +226,7 @@ void build_layout(const sccs_problem* p, int32_t G, Layout& L, int32_t tile_nnz,
             const int32_t r = p->row_idx[e];
             L.rp[2 * pos] = (uint32_t)r;
             L.rp[2 * pos + 1] = (uint32_t)era_pid[r] | c;
+            if (p->value) L.val[(size_t)pos] = p->value[e];
           }
         }
       }
@@ -285,9 +292,14 @@ void build_layout(const sccs_problem* p, int32_t G, Layout& L, int32_t tile_nnz,
   for (int64_t e = 0; e < nnz; ++e) L.era_ptr[(size_t)p->row_idx[e] + 1]++;
   for (int64_t k = 0; k < K; ++k) L.era_ptr[k + 1] += L.era_ptr[k];
   L.era_col.resize((size_t)nnz);
+  if (p->value) L.era_val.resize((size_t)nnz);
   std::vector<int32_t> fill(L.era_ptr.begin(), L.era_ptr.end() - 1);
   for (int32_t j = 0; j < J; ++j)
-    for (int64_t e = p->col_ptr[j]; e < p->col_ptr[j + 1]; ++e) L.era_col[(size_t)fill[p->row_idx[e]]++] = j;
+    for (int64_t e = p->col_ptr[j]; e < p->col_ptr[j + 1]; ++e) {
+      const int32_t slot = fill[p->row_idx[e]]++;
+      L.era_col[(size_t)slot] = j;
+      if (p->value) L.era_val[(size_t)slot] = p->value[e];
+    }
 }
 
 }  // namespace sccs
@@ -306,7 +318,7 @@ void host_ytx(const sccs_problem* p, const int32_t* weight, std::vector<double>&
       for (int64_t e = p->col_ptr[j]; e < p->col_ptr[j + 1]; ++e) {
         const int32_t r = p->row_idx[e];
         const double om = weight ? (double)weight[era_pid[r]] : 1.0;
-        s += om * (double)p->count[r];
+        s += p->value ? om * (double)p->count[r] * p->value[e] : om * (double)p->count[r];
       }
       ytx[j] = s;
     }

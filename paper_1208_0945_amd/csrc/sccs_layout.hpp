@@ -58,6 +58,8 @@ struct Layout {
   std::vector<int32_t> pptr;        // [N+1] patient_ptr as int32
   std::vector<int32_t> era_ptr;     // [K+1] compressed row storage of X
   std::vector<int32_t> era_col;     // [nnz]
+  std::vector<double> val;          // [nnz] covariate values in rp order (empty: binary)
+  std::vector<double> era_val;      // [nnz] covariate values in era_col order (empty: binary)
   int32_t n_tiles() const { return (int32_t)tile_start.size() - 1; }
   int32_t max_tiles_per_wg = 0;     // over all (column, workgroup) pairs
 };
@@ -81,8 +83,9 @@ inline void layout_dims(const sccs_problem* p, int32_t G, int32_t tile_nnz, Layo
 // columns.  The problem must have been validated.
 void build_layout(const sccs_problem* p, int32_t G, Layout& L, int32_t tile_nnz = kTile, int32_t max_group = 1);
 
-// Y'X_j with patient weights (NULL = 1), summed on the host; the terms are
-// integers, so the sum is exact in any order.
+// Y'X_j with patient weights (NULL = 1), summed on the host in compressed
+// column order; for binary problems the terms are integers, so the sum is
+// exact in any order.
 void host_ytx(const sccs_problem* p, const int32_t* weight, std::vector<double>& ytx);
 
 }  // namespace sccs

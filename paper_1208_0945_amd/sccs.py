@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libsccs.so")
 
 OK, NOT_CONVERGED = 0, 1
 ERR_INVALID_ARG, ERR_WORKSPACE, ERR_HIP, ERR_STATE, ERR_NUMERIC, ERR_SYNC = -1, -2, -3, -4, -5, -6
-PRIOR_NONE, PRIOR_NORMAL, PRIOR_LAPLACE = 0, 1, 2
+PRIOR_NONE, PRIOR_NORMAL, PRIOR_LAPLACE, PRIOR_GROUPED = 0, 1, 2, 3
 PREC_FP64, PREC_MIXED = 0, 1
 CRIT_FIXED, CRIT_REL_LOGPOST, CRIT_ABS_DXBETA = 0, 1, 2
 
@@ -28,7 +28,9 @@ EXPORTS = ("sccs_default_options", "sccs_query_workspace", "sccs_create", "sccs_
            "sccs_set_prior", "sccs_set_beta", "sccs_get_beta", "sccs_sweep", "sccs_fit",
            "sccs_grad_hess", "sccs_objective", "sccs_last_kernel_ms", "sccs_pass_stats", "sccs_last_error",
            "sccs_batch_query_workspace", "sccs_batch_create", "sccs_batch_run", "sccs_batch_get",
-           "sccs_batch_heldout", "sccs_batch_last_kernel_ms", "sccs_batch_destroy", "sccs_batch_last_error", "sccs_tune")
+           "sccs_batch_heldout", "sccs_batch_last_kernel_ms", "sccs_batch_destroy", "sccs_batch_last_error", "sccs_tune",
+           "sccs_bootstrap_query_workspace", "sccs_bootstrap",
+           "sccs_cv_query_workspace", "sccs_cv_search", "sccs_set_prior_grouped", "sccs_group_times")
 
 
 class SccsError(RuntimeError):
@@ -42,7 +44,8 @@ class Problem_(ctypes.Structure):
                 ("n_cols", ctypes.c_int32), ("nnz", ctypes.c_int64),
                 ("patient_ptr", ctypes.c_void_p), ("offset", ctypes.c_void_p),
                 ("count", ctypes.c_void_p), ("col_ptr", ctypes.c_void_p),
-                ("row_idx", ctypes.c_void_p), ("patient_weight", ctypes.c_void_p)]
+                ("row_idx", ctypes.c_void_p), ("patient_weight", ctypes.c_void_p),
+                ("value", ctypes.c_void_p)]
 
 
 class Options_(ctypes.Structure):
@@ -66,6 +69,22 @@ class TuneResult_(ctypes.Structure):
     _fields_ = [("n_candidates", ctypes.c_int32), ("best", ctypes.c_int32),
                 ("n_workgroups", ctypes.c_int32 * 16), ("tile_nnz", ctypes.c_int32 * 16),
                 ("ms_per_sweep", ctypes.c_double * 16)]
+
+
+class BootstrapOut_(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_void_p), ("ci_lo", ctypes.c_void_p), ("ci_hi", ctypes.c_void_p),
+                ("p_nonzero", ctypes.c_void_p), ("sweeps", ctypes.c_void_p), ("converged", ctypes.c_void_p)]
+
+
+class CvOpts_(ctypes.Structure):
+    _fields_ = [("prior_kind", ctypes.c_int32), ("n_folds", ctypes.c_int32), ("fold", ctypes.c_void_p),
+                ("var_start", ctypes.c_double), ("bracket_step", ctypes.c_double), ("log10_tol", ctypes.c_double),
+                ("max_evals", ctypes.c_int32), ("warm_start", ctypes.c_int32), ("fit", FitOpts_)]
+
+
+class CvResult_(ctypes.Structure):
+    _fields_ = [("n_evals", ctypes.c_int32), ("best", ctypes.c_int32), ("bracketed", ctypes.c_int32),
+                ("variance", ctypes.c_double * 64), ("pred_loglik", ctypes.c_double * 64)]
 
 
 class FitResult_(ctypes.Structure):
@@ -126,6 +145,7 @@ def lib() -> ctypes.CDLL:
                                   ctypes.c_size_t, ctypes.POINTER(H)]
         L.sccs_destroy.argtypes = [H]
         L.sccs_set_prior.argtypes = [H, ctypes.c_int32, ctypes.c_double]
+        L.sccs_set_prior_grouped.argtypes = [H, ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_void_p]
         L.sccs_set_beta.argtypes = [H, ctypes.c_void_p, ctypes.c_void_p]
         L.sccs_get_beta.argtypes = [H, ctypes.c_void_p, ctypes.c_void_p]
         L.sccs_sweep.argtypes = [H, ctypes.c_int32, dp]
@@ -135,6 +155,7 @@ def lib() -> ctypes.CDLL:
         L.sccs_last_kernel_ms.argtypes = [H, dp]
         ip = ctypes.POINTER(ctypes.c_int32)
         L.sccs_pass_stats.argtypes = [H, ip, ip, ip]
+        L.sccs_group_times.argtypes = [H, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ip]
         L.sccs_last_error.argtypes = [H]
         L.sccs_last_error.restype = ctypes.c_char_p
         L.sccs_batch_query_workspace.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
@@ -150,6 +171,16 @@ def lib() -> ctypes.CDLL:
                                 ctypes.c_int32, ctypes.POINTER(Options_), ctypes.POINTER(TuneResult_)]
         L.sccs_batch_last_error.argtypes = [H]
         L.sccs_batch_last_error.restype = ctypes.c_char_p
+        L.sccs_bootstrap_query_workspace.argtypes = [ctypes.POINTER(Problem_), ctypes.POINTER(Options_),
+                                                     ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+        L.sccs_bootstrap.argtypes = [ctypes.POINTER(Problem_), ctypes.POINTER(Options_), ctypes.c_void_p,
+                                     ctypes.c_size_t, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                     ctypes.c_void_p, ctypes.POINTER(FitOpts_), ctypes.c_double,
+                                     ctypes.POINTER(BootstrapOut_)]
+        L.sccs_cv_query_workspace.argtypes = [ctypes.POINTER(Problem_), ctypes.POINTER(Options_), ctypes.c_int32,
+                                              ctypes.POINTER(ctypes.c_size_t)]
+        L.sccs_cv_search.argtypes = [ctypes.POINTER(Problem_), ctypes.POINTER(Options_), ctypes.c_void_p,
+                                     ctypes.c_size_t, ctypes.POINTER(CvOpts_), ctypes.POINTER(CvResult_)]
         for name in EXPORTS:
             if name not in ("sccs_default_options", "sccs_last_error", "sccs_batch_last_error"):
                 getattr(L, name).restype = ctypes.c_int32
@@ -171,12 +202,15 @@ class ProblemArrays:
         self.col_ptr = _arr(prob.col_ptr, np.int64)
         self.row_idx = _arr(prob.row_idx, np.int32)
         self.weight = None if weight is None else _arr(weight, np.int32)
+        v = getattr(prob, "value", None)
+        self.value = None if v is None else _arr(v, np.float64)
         self.n_cols = int(prob.n_cols)
         self.s = Problem_(int(prob.n_patients), int(self.patient_ptr[-1]), self.n_cols,
                           int(self.col_ptr[-1]), self.patient_ptr.ctypes.data, self.offset.ctypes.data,
                           self.count.ctypes.data, self.col_ptr.ctypes.data,
                           self.row_idx.ctypes.data if self.row_idx.size else None,
-                          None if self.weight is None else self.weight.ctypes.data)
+                          None if self.weight is None else self.weight.ctypes.data,
+                          None if self.value is None or not self.value.size else self.value.ctypes.data)
 
 
 def options(precision: int = PREC_FP64, n_workgroups: int = 0, refresh_period: int = -1,
@@ -268,6 +302,13 @@ class Handle:
     def set_prior(self, kind: int, variance: float = 1.0):
         self._check(lib().sccs_set_prior(self.h, int(kind), float(variance)))
 
+    def set_prior_grouped(self, variance: float, class_variance: float, class_of):
+        """Grouped Normal prior: drugs of one class share a class mean with
+        variance class_variance, each drug varies around it with variance."""
+        c = _arr(class_of, np.int32)
+        n = int(c.max()) + 1 if c.size else 1
+        self._check(lib().sccs_set_prior_grouped(self.h, float(variance), float(class_variance), n, c.ctypes.data))
+
     def set_beta(self, beta, trust=None):
         b = _arr(beta, np.float64)
         t = None if trust is None else _arr(trust, np.float64)
@@ -315,6 +356,17 @@ class Handle:
         p, r, z = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         self._check(lib().sccs_pass_stats(self.h, ctypes.byref(p), ctypes.byref(r), ctypes.byref(z)))
         return p.value, r.value, z.value
+
+    def group_times(self):
+        """(microseconds from the last sweep's start to each column group's
+        step, first column of each group) of the last one-pass launch."""
+        n = ctypes.c_int32()
+        cap = self.J
+        t = np.zeros(cap)
+        fc = np.zeros(cap + 1, dtype=np.int32)
+        self._check(lib().sccs_group_times(self.h, cap, t.ctypes.data, fc.ctypes.data, ctypes.byref(n)))
+        k = n.value
+        return t[:k], fc[:k + 1]
 
 
 def tune(prob, prior_kind: int, variance: float, n_sweeps: int = 2, precision: int = PREC_FP64, weight=None):
@@ -425,3 +477,73 @@ class Batch:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def bootstrap(prob, prior_kind: int, variance: float, weights, criterion: int = CRIT_REL_LOGPOST,
+              max_sweeps: int = 100, tol: float = 1e-8, level: float = 0.95, precision: int = PREC_FP64,
+              n_workgroups: int = 0, stream=None) -> dict:
+    """sccs_bootstrap: one fit per row of weights ([R, N] patient
+    multiplicities), percentile intervals and the share of nonzero estimates.
+    Returns dict(beta [R, J], lo, hi, p_nonzero, sweeps, converged)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    W = _arr(weights, np.int32)
+    R = int(W.shape[0])
+    P = ProblemArrays(prob)
+    if W.ndim != 2 or W.shape[1] != int(prob.n_patients):
+        raise ValueError("weights must be [n_replicates, n_patients]")
+    o = options(precision, n_workgroups, -1, stream.cuda_stream)
+    L = lib()
+    n = ctypes.c_size_t()
+    st = L.sccs_bootstrap_query_workspace(ctypes.byref(P.s), ctypes.byref(o), R, ctypes.byref(n))
+    if st != OK:
+        raise SccsError(st, L.sccs_batch_last_error(None).decode())
+    ws = torch.empty(int(n.value) + 256, dtype=torch.uint8, device="cuda")
+    ptr = (ws.data_ptr() + 255) & ~255
+    J = P.n_cols
+    beta = np.zeros((R, J))
+    lo, hi, pnz = np.zeros(J), np.zeros(J), np.zeros(J)
+    sw, cv = np.zeros(R, dtype=np.int32), np.zeros(R, dtype=np.int32)
+    out = BootstrapOut_(beta.ctypes.data, lo.ctypes.data, hi.ctypes.data, pnz.ctypes.data, sw.ctypes.data,
+                        cv.ctypes.data)
+    fo = FitOpts_(int(criterion), int(max_sweeps), float(tol))
+    st = L.sccs_bootstrap(ctypes.byref(P.s), ctypes.byref(o), ptr, int(n.value), int(prior_kind), float(variance), R,
+                          W.ctypes.data, ctypes.byref(fo), float(level), ctypes.byref(out))
+    if st != OK:
+        raise SccsError(st, L.sccs_batch_last_error(None).decode())
+    del ws
+    return {"beta": beta, "lo": lo, "hi": hi, "p_nonzero": pnz, "sweeps": sw, "converged": cv.astype(bool)}
+
+
+def cv_search(prob, folds, n_folds: int, prior_kind: int, var_start: float = 0.01, bracket_step: float = 10.0,
+              log10_tol: float = 0.05, max_evals: int = 30, warm_start: bool = True,
+              criterion: int = CRIT_REL_LOGPOST, max_sweeps: int = 100, tol: float = 1e-10,
+              precision: int = PREC_FP64, n_workgroups: int = 0, stream=None) -> dict:
+    """sccs_cv_search: bracketing and golden-section search of the
+    cross-validated predictive log-likelihood over the prior variance.
+    Returns dict(variance, pred_loglik [per evaluation], best, bracketed)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    P = ProblemArrays(prob)
+    fold = _arr(folds, np.int32)
+    o = options(precision, n_workgroups, -1, stream.cuda_stream)
+    L = lib()
+    n = ctypes.c_size_t()
+    st = L.sccs_cv_query_workspace(ctypes.byref(P.s), ctypes.byref(o), int(n_folds), ctypes.byref(n))
+    if st != OK:
+        raise SccsError(st, L.sccs_batch_last_error(None).decode())
+    ws = torch.empty(int(n.value) + 256, dtype=torch.uint8, device="cuda")
+    ptr = (ws.data_ptr() + 255) & ~255
+    co = CvOpts_(int(prior_kind), int(n_folds), fold.ctypes.data, float(var_start), float(bracket_step),
+                 float(log10_tol), int(max_evals), int(bool(warm_start)),
+                 FitOpts_(int(criterion), int(max_sweeps), float(tol)))
+    r = CvResult_()
+    st = L.sccs_cv_search(ctypes.byref(P.s), ctypes.byref(o), ptr, int(n.value), ctypes.byref(co), ctypes.byref(r))
+    if st != OK:
+        raise SccsError(st, L.sccs_batch_last_error(None).decode())
+    del ws
+    k = r.n_evals
+    return {"variance": np.array(r.variance[:k]), "pred_loglik": np.array(r.pred_loglik[:k]),
+            "best": int(r.best), "bracketed": bool(r.bracketed)}

@@ -135,3 +135,12 @@ def test_batch_specs_validated_on_host():
     other = synth.tiny(n_patients=30, n_cols=5, seed=2)
     assert _batch_query([p, other], [sccs.FitSpec(0, ok_link)]) == sccs.ERR_INVALID_ARG  # J differs
     assert _batch_query([p], [sccs.FitSpec(0, ok_link)] * 65) == sccs.ERR_INVALID_ARG    # > 64 fits
+
+
+def test_covariate_values_must_be_finite():
+    prob = synth.valued(n_patients=60, n_drugs=3, n_dose=1, n_dense=1, seed=1)
+    assert _query(prob) != sccs.ERR_INVALID_ARG      # valid (ERR_HIP without a GPU)
+    bad = prob.value.copy()
+    bad[5] = np.nan
+    import dataclasses
+    assert _query(dataclasses.replace(prob, value=bad)) == sccs.ERR_INVALID_ARG

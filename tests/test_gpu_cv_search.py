@@ -1,0 +1,54 @@
+"""Cross-validated prior-variance search (sccs_cv_search, Section 2.5)
+against the oracle's search.
+
+Both sides bracket the maximum of the predictive log-likelihood on a log10
+grid and then narrow it by golden-section steps.  Every evaluation's
+predictive log-likelihood (the held-out Eq. 2 summed over folds at the fold
+fits) must agree to 1e-9 relative, so both take the same decisions and
+evaluate the same variances.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1208_0945_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sccs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1208_0945_amd import sccs as s
+    s.lib()
+    return s
+
+
+@pytest.mark.parametrize("kind,var_start,warm", [(2, 1e-2, True), (1, 10.0, True), (2, 1e-2, False)])
+def test_cv_search_matches_oracle(sccs, kind, var_start, warm):
+    prob = synth.zipf_problem("zipf_small", 4000, 40, 0.1, seed_path=(8, 3))
+    folds = synth.cv_folds(prob.n_patients, 5, seed=1)
+    kw = dict(var_start=var_start, bracket_step=10.0, log10_tol=0.1, max_evals=20, warm_start=warm)
+    ref = oracle.cv_search(prob, folds, 5, kind, max_sweeps=300, tol=1e-11, **kw)
+    got = sccs.cv_search(prob, folds, 5, kind, max_sweeps=300, tol=1e-11, **kw)
+    print("variances", got["variance"], "best", got["best"], "bracketed", got["bracketed"])
+    assert len(got["variance"]) == len(ref["variance"])
+    assert np.allclose(got["variance"], ref["variance"], rtol=1e-12, atol=0)
+    assert np.max(np.abs(got["pred_loglik"] - ref["pred_loglik"]) / np.abs(ref["pred_loglik"])) <= 1e-9
+    assert got["best"] == ref["best"] and got["bracketed"] == ref["bracketed"]
+    assert got["bracketed"]
+
+
+def test_cv_search_budget_and_errors(sccs):
+    prob = synth.tiny(n_patients=400, n_cols=8, seed=2)
+    folds = synth.cv_folds(prob.n_patients, 3, seed=2)
+    r = sccs.cv_search(prob, folds, 3, 2, var_start=1e-3, max_evals=3)
+    assert len(r["variance"]) == 3
+    with pytest.raises(sccs.SccsError):
+        sccs.cv_search(prob, folds, 3, 0)          # prior none has no variance to choose
+    bad = folds.copy()
+    bad[0] = 7
+    with pytest.raises(sccs.SccsError):
+        sccs.cv_search(prob, bad, 3, 2)

@@ -478,3 +478,30 @@ def test_autotuner_picks_a_candidate_and_its_schedule_is_exact(sccs):
     ref = oracle.ccd(prob, 2, 2.0, 5)
     beta, _ = run_gpu(sccs, prob, 2, 2.0, 5, **best)
     assert rel_inf(beta, ref["beta"]) <= FP64_TOL
+
+
+def test_group_times_cover_the_sweep(sccs):
+    """sccs_group_times after a one-pass launch: one stamp per column group,
+    non-decreasing, inside the kernel's own time; refused after a merged-pass
+    launch and for valued problems."""
+    prob = zipf_small()
+    with sccs.Handle(prob, n_workgroups=64, merge_passes=0) as h:
+        h.set_prior(sccs.PRIOR_LAPLACE, 2.0)
+        h.sweep(2)
+        t, fc = h.group_times()
+        ms = h.last_kernel_ms()
+    assert fc[0] == 0 and fc[-1] == prob.n_cols and np.all(np.diff(fc) >= 1)
+    assert len(t) == len(fc) - 1 and np.all(t > 0) and np.all(np.diff(t) >= 0)
+    assert t[-1] * 1e-3 <= ms
+    with sccs.Handle(prob) as h:
+        h.set_prior(sccs.PRIOR_LAPLACE, 2.0)
+        h.sweep(1)          # first launch: one pass per group
+        h.group_times()
+        h.sweep(30)
+        zero_share = h.pass_stats()[2] / (30 * prob.n_cols)
+        h.sweep(1)          # merged passes once most steps were zero
+        if zero_share >= 0.5:
+            with pytest.raises(sccs.SccsError):
+                h.group_times()
+        else:
+            h.group_times()
