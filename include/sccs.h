@@ -202,6 +202,23 @@ sccs_status sccs_get_beta(sccs_handle* h, double* beta, double* trust);
  * after the last sweep is written there (synchronises).  Needs a prior. */
 sccs_status sccs_sweep(sccs_handle* h, int32_t n_sweeps, double* logpost);
 
+/* Allocation-free variant of sccs_sweep, for callers that cannot allocate
+ * device memory or call allocating routines (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation).  It runs the same
+ * sweeps with the same kernels and results, but the device-wide reduction
+ * slots and the control block of the launch live in a static device array
+ * inside the library (480 KiB per device, slots for up to 256 workgroups,
+ * held until the process ends) instead of the handle's workspace; the
+ * handle's state (beta, trust, exp(X beta), den) is in its workspace as
+ * always.  Needs n_sweeps >= 1 and the handle's device current
+ * (SCCS_ERR_STATE otherwise); a handle with more workgroups than the array
+ * holds gets SCCS_ERR_INVALID_ARG.  All handles on one device share the
+ * array and each call re-initialises it: calls that overlap on one device
+ * (other streams, other threads) race and must be serialised by the
+ * caller.  Synchronises the stream; sccs_pass_stats and
+ * sccs_last_kernel_ms report on it as on sccs_sweep. */
+sccs_status sccs_sweep_static(sccs_handle* h, int32_t n_sweeps, double* logpost);
+
 /* Run cycles until the criterion holds or max_sweeps cycles ran, in one
  * device launch; the stop test is evaluated on the device after every
  * sweep.  Returns SCCS_OK if converged, SCCS_NOT_CONVERGED otherwise (or an

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -300,6 +301,82 @@ sccs_status reset_moved(sccs_handle* h) {
                      (size_t)h->mv_words / 2, ~0ull);
   HIPCHK(h, hipGetLastError());
   return SCCS_OK;
+}
+
+// ------------------------------------------------ allocation-free sweep
+//
+// sccs_sweep_static runs the sweep kernel with its device-wide reduction
+// slots and its control block in `scratch`, a file-scope device array, in
+// place of the handle's workspace copies.  The array holds one set of slots
+// for up to kMaxWorkgroups workgroups (every reduction class of the sweep and
+// the objective) plus one control block: 480 KiB, held by every device the
+// library runs on until the process ends.  Every call on a device shares
+// that device's copy; each call first refills it (tags, sequence numbers),
+// so calls that overlap on one device race.
+constexpr size_t kScrSlots1 = (size_t)kSlotClasses * kSlots1PerClass;
+constexpr size_t kScrSlots2 = (size_t)kSlotClasses * kSlots2PerClass;
+constexpr size_t kScrO1 = kSlots1Words;
+constexpr size_t kScrO2 = (size_t)2 * kReplicas * kGroups * kSlotWords;
+constexpr size_t kScrTagWords = kScrSlots1 + kScrSlots2 + kScrO1 + kScrO2;   // filled with the start tag
+constexpr size_t kScrCtrlWords = (sizeof(Ctrl) + 255) / 256 * 32;
+constexpr size_t kScratchWords = kScrTagWords + kScrCtrlWords;
+constexpr int32_t kScratchMaxWorkgroups = kMaxWorkgroups;
+static_assert(kScrSlots1 % 32 == 0 && kScrSlots2 % 32 == 0 && kScrO1 % 32 == 0 && kScrO2 % 32 == 0,
+              "every part of the scratch array starts on a 256-byte boundary");
+
+static __device__ __align__(256) uint64_t scratch[kScratchWords];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint64_t* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array (the array's name is only a
+// host-side stand-in); looked up once per device, with that device current.
+sccs_status scratch_address(int dev, uint64_t** out, std::string& err) {
+  if (dev < 0 || dev >= kMaxDevices) { err = "device index beyond the scratch table"; return SCCS_ERR_STATE; }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return SCCS_ERR_HIP;
+    }
+    g_scratch_ptr[dev] = (uint64_t*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SCCS_OK;
+}
+
+// Start of a static sweep: every slot word gets the tag that reductions 0 and
+// 1 do not expect, and the scratch control block starts from the handle's
+// state with every sequence number at zero (a fill kernel, not a memset, so
+// that the sequence can be captured in a graph).
+__global__ void k_scratch_prep(uint64_t* slots, size_t n, Ctrl* sc, const Ctrl* hc) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    slots[i] = kSign;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    Ctrl c{};
+    c.since_refresh = hc->since_refresh;
+    *sc = c;
+  }
+}
+
+// End of a static sweep: results go back to the handle's control block; the
+// handle keeps its own sequence numbers (its own slots were not touched).
+__global__ void k_scratch_post(const Ctrl* sc, Ctrl* hc) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  uint32_t n = 0;
+  for (int c = 0; c < kSlotClasses; ++c) n += sc->gseq[c];
+  hc->passes = (int32_t)n;
+  hc->status = sc->status;
+  hc->sweeps = sc->sweeps;
+  hc->converged = sc->converged;
+  hc->since_refresh = sc->since_refresh;
+  hc->loglik = sc->loglik;
+  hc->logpost = sc->logpost;
+  hc->rejects = sc->rejects;
+  hc->zero_steps = sc->zero_steps;
 }
 
 }  // namespace
@@ -609,6 +686,79 @@ sccs_status sccs_sweep(sccs_handle* h, int32_t n_sweeps, double* logpost) {
   if (st) return st;
   st = read_ctrl(h);
   if (st) return st;
+  if (logpost) *logpost = h->h_ctrl->logpost;
+  return SCCS_OK;
+}
+
+sccs_status sccs_sweep_static(sccs_handle* h, int32_t n_sweeps, double* logpost) {
+  sccs_status st = usable(h);
+  if (st) return st;
+  if (h->prior_kind < 0) { h->err = "set a prior before sweeping"; return SCCS_ERR_STATE; }
+  if (n_sweeps < 1) { h->err = "n_sweeps must be >= 1"; return SCCS_ERR_INVALID_ARG; }
+  if (h->G > kScratchMaxWorkgroups) {
+    h->err = "the static scratch array holds reduction slots for at most 256 workgroups";
+    return SCCS_ERR_INVALID_ARG;
+  }
+  int dev = -1;
+  HIPCHK(h, hipGetDevice(&dev));
+  if (dev != h->device) { h->err = "make the handle's device current before sccs_sweep_static"; return SCCS_ERR_STATE; }
+  uint64_t* base = nullptr;
+  st = scratch_address(dev, &base, h->err);
+  if (st) return st;
+  KArgs a = h->args;
+  a.slots = base;
+  a.slots2 = base + kScrSlots1;
+  a.oslots = a.slots2 + kScrSlots2;
+  a.oslots2 = a.oslots + kScrO1;
+  a.ctrl = (Ctrl*)(base + kScrTagWords);
+  a.prior_kind = h->prior_kind;
+  a.var = h->var;
+  a.inv_var = 1.0 / h->var;
+  a.lambda = (a.prior_kind == SCCS_PRIOR_LAPLACE) ? std::sqrt(2.0 / h->var) : 0.0;
+  a.n_classes = a.prior_kind == SCCS_PRIOR_GROUPED ? h->n_classes : 0;
+  a.n_sweeps = n_sweeps;
+  a.criterion = SCCS_CRIT_FIXED;
+  a.tol = 0.0;
+  a.refresh_period = h->refresh_period;
+  a.want_objective = logpost != nullptr;
+  a.mode = kModeSweep;
+  a.diag_j = 0;
+  hipLaunchKernelGGL(k_scratch_prep, dim3(64), dim3(256), 0, h->stream, base, kScrTagWords, a.ctrl,
+                     (const Ctrl*)h->args.ctrl);
+  HIPCHK(h, hipGetLastError());
+  void* params[] = {&a};
+  const bool merge = a.merge && h->use_merge && !h->valued && a.prior_kind != SCCS_PRIOR_GROUPED;
+  HIPCHK(h, hipEventRecord(h->ev0, h->stream));
+  HIPCHK(h, hipLaunchCooperativeKernel(ccd_kernel(h->prec, kModeSweep, merge, h->valued), dim3(h->G), dim3(kBlock), params,
+                                        (unsigned)launch_lds(h, a.prior_kind), h->stream));
+  HIPCHK(h, hipEventRecord(h->ev1, h->stream));
+  h->timed = true;
+  hipLaunchKernelGGL(k_scratch_post, dim3(1), dim3(64), 0, h->stream, (const Ctrl*)a.ctrl, h->args.ctrl);
+  HIPCHK(h, hipGetLastError());
+  // the handle's control block kept its own sequence numbers, so the host
+  // mirror stays valid for the next sccs_sweep
+  HIPCHK(h, hipMemcpyAsync(h->h_ctrl, h->args.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  h->last_mode = -1;
+  h->passes = h->h_ctrl->passes;
+  h->rejects = h->h_ctrl->rejects;
+  h->zero_steps = h->h_ctrl->zero_steps;
+  h->swept = true;
+  {
+    const double visits = (double)h->J * (h->h_ctrl->sweeps > 0 ? h->h_ctrl->sweeps : 1);
+    const double zf = h->zero_steps / visits;
+    if (!h->use_merge && zf >= 0.5) h->use_merge = true;
+    else if (h->use_merge && zf < 0.35) h->use_merge = false;
+  }
+  if (h->h_ctrl->status == SCCS_ERR_SYNC) {
+    h->failed = true;
+    h->err = "device-wide reduction timed out (workgroups not co-resident?)";
+    return SCCS_ERR_SYNC;
+  }
+  if (h->h_ctrl->status == SCCS_ERR_NUMERIC) {
+    h->err = "non-finite gradient, Hessian or coefficient; last finite beta kept";
+    return SCCS_ERR_NUMERIC;
+  }
   if (logpost) *logpost = h->h_ctrl->logpost;
   return SCCS_OK;
 }

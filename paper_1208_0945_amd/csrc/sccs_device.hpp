@@ -49,7 +49,7 @@ struct Ctrl {
   int32_t sweeps;      // sweeps run by the last launch
   int32_t converged;
   int32_t since_refresh;
-  int32_t pad;
+  int32_t passes;      // reductions run by the last sccs_sweep_static launch
   double loglik, logpost;
   double g, h;         // diagnostic output
   uint32_t gseq[kSlotClasses];  // single fit: sequence number of each reduction class

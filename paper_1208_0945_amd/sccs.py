@@ -29,7 +29,7 @@ EXPORTS = ("sccs_default_options", "sccs_query_workspace", "sccs_create", "sccs_
            "sccs_grad_hess", "sccs_objective", "sccs_last_kernel_ms", "sccs_pass_stats", "sccs_last_error",
            "sccs_batch_query_workspace", "sccs_batch_create", "sccs_batch_run", "sccs_batch_get",
            "sccs_batch_heldout", "sccs_batch_last_kernel_ms", "sccs_batch_destroy", "sccs_batch_last_error", "sccs_tune",
-           "sccs_bootstrap_query_workspace", "sccs_bootstrap",
+           "sccs_sweep_static", "sccs_bootstrap_query_workspace", "sccs_bootstrap",
            "sccs_cv_query_workspace", "sccs_cv_search", "sccs_set_prior_grouped", "sccs_group_times")
 
 
@@ -149,6 +149,7 @@ def lib() -> ctypes.CDLL:
         L.sccs_set_beta.argtypes = [H, ctypes.c_void_p, ctypes.c_void_p]
         L.sccs_get_beta.argtypes = [H, ctypes.c_void_p, ctypes.c_void_p]
         L.sccs_sweep.argtypes = [H, ctypes.c_int32, dp]
+        L.sccs_sweep_static.argtypes = [H, ctypes.c_int32, dp]
         L.sccs_fit.argtypes = [H, ctypes.POINTER(FitOpts_), ctypes.POINTER(FitResult_)]
         L.sccs_grad_hess.argtypes = [H, ctypes.c_int32, dp, dp]
         L.sccs_objective.argtypes = [H, dp, dp]
@@ -327,6 +328,13 @@ class Handle:
             return lp.value
         self._check(lib().sccs_sweep(self.h, int(n), None))
         return None
+
+    def sweep_static(self, n: int = 1, want_logpost: bool = False) -> Optional[float]:
+        """sccs_sweep_static: the same sweeps with the reduction scratch taken
+        from the library's static device array (no allocation)."""
+        lp = ctypes.c_double()
+        self._check(lib().sccs_sweep_static(self.h, int(n), ctypes.byref(lp) if want_logpost else None))
+        return lp.value if want_logpost else None
 
     def fit(self, criterion: int = CRIT_REL_LOGPOST, max_sweeps: int = 100, tol: float = 1e-8) -> dict:
         fo = FitOpts_(int(criterion), int(max_sweeps), float(tol))
