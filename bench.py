@@ -76,12 +76,12 @@ def bytes_per_sweep_library(c, p, active, precision):
     return float(a + b)
 
 
-def run_form(sccs, prob, precision, steps, warmup, c, p, n_workgroups=0, late=0):
+def run_form(sccs, prob, precision, steps, warmup, c, p, n_workgroups=0, late=0, refresh_period=-1):
     """warmup sweeps, then beta reset to 0 (exact state recomputation) and
     `steps` timed sweeps from beta = 0, one launch each; then `late` more
     sweeps timed on their own (the fit continuing toward convergence)."""
     import torch
-    h = sccs.Handle(prob, precision=precision, n_workgroups=n_workgroups)
+    h = sccs.Handle(prob, precision=precision, n_workgroups=n_workgroups, refresh_period=refresh_period)
     h.set_prior(sccs.PRIOR_LAPLACE, 2.0)
     for _ in range(warmup):
         h.sweep(1)
@@ -200,7 +200,7 @@ def copy_calibration(n_bytes: int = 1 << 30, reps: int = 3):
     print(json.dumps({"copy_calibration_bytes_each_way": n_bytes, "reps": reps}), flush=True)
 
 
-def batched_outcomes_bench(sccs, synth, steps, precision):
+def batched_outcomes_bench(sccs, synth, steps, precision, engine=0):
     """64 outcomes over one J = 1000 vocabulary, patient counts log-uniform
     10k..2M, Laplace lambda = 1: one launch runs `steps` sweeps of all 64."""
     t0 = time.perf_counter()
@@ -212,7 +212,7 @@ def batched_outcomes_bench(sccs, synth, steps, precision):
     specs = [sccs.FitSpec(f, [(sccs.PRIOR_LAPLACE, 2.0)]) for f in range(len(probs))]
     stats = [column_stats(p) for p in probs]
     t0 = time.perf_counter()
-    with sccs.Batch(probs, specs, precision=precision) as b:
+    with sccs.Batch(probs, specs, precision=precision, engine=engine) as b:
         print(f"[bench] batch set up in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
         b.run(sccs.CRIT_FIXED, max_sweeps=1)            # warm-up launch (the chains restart from its beta)
         t0 = time.perf_counter()
@@ -226,35 +226,50 @@ def batched_outcomes_bench(sccs, synth, steps, precision):
             "achieved_GBs_upper": tot / (ms * 1e-3) / 1e9,
             "dtype": "f64" if precision == 0 else "mixed",
             "config": {"workload": "64 outcomes, J=1000 Zipf(1.1), N log-uniform 1e4..2e6, Laplace lambda=1",
+                       "engine": ["partitioned", "lockstep"][engine],
                        "n_patients_total": int(sum(p.n_patients for p in probs)),
                        "nnz_total": int(sum(p.nnz for p in probs))}}
 
 
-def cv_bench(sccs, synth, precision, max_sweeps, tol, n_folds=10, n_grid=16):
+def cv_bench(sccs, synth, precision, max_sweeps, tol, n_folds=10, n_grid=16, engine=0):
     """The mid problem under 10-fold patient-level cross-validation x 16
     Laplace variances logspace(-3, 1): 10 fold chains walk the grid upward
-    with warm starts, all in one launch; then the held-out log-likelihood
-    (Eq. 2 over the held-out patients) of every (fold, variance) fit."""
+    with warm starts (partitioned engine: one launch per variance, the folds
+    on disjoint workgroup ranges; lockstep engine: one launch for the whole
+    grid); then the held-out log-likelihood (Eq. 2 over the held-out
+    patients) of every (fold, variance) fit."""
     prob = synth.mid()
     folds = synth.cv_folds(prob.n_patients, n_folds)
     grid = synth.prior_grid(n_grid)
     specs = [sccs.FitSpec(0, [(sccs.PRIOR_LAPLACE, float(v)) for v in grid], weight=(folds != k).astype(np.int32))
              for k in range(n_folds)]
-    with sccs.Batch([prob], specs, precision=precision) as b:
+    with sccs.Batch([prob], specs, precision=precision, engine=engine) as b:
         t0 = time.perf_counter()
         b.run(sccs.CRIT_REL_LOGPOST, max_sweeps=max_sweeps, tol=tol)
         wall = time.perf_counter() - t0
         ms = b.last_kernel_ms()
         res = [[b.get(k, l) for l in range(n_grid)] for k in range(n_folds)]
         heldout = np.array([[b.heldout(k, l) for l in range(n_grid)] for k in range(n_folds)])
-    sweeps = sum(r[1]["sweeps"] for row in res for r in row)
+    sw = np.array([[r[1]["sweeps"] for r in row] for row in res])   # [fold, variance]
+    sweeps = int(sw.sum())
+    # sweeps on the critical path: lockstep, the longest fold chain; partitioned,
+    # per variance the slowest fold (each variance is one launch)
+    critical = int(sw.sum(axis=1).max()) if engine == 1 else int(sw.max(axis=0).sum())
+    c, p = column_stats(prob)
+    phase_a = bytes_per_sweep(c, p, np.zeros(len(c), bool), precision)   # every visit's gathers
     mean = heldout.mean(axis=0)
-    return {"metric": "batched CV: fit-sweeps/s (10 folds x 16 Laplace variances, warm starts, one launch)",
-            "value": sweeps / wall, "unit": "fit-sweeps/s", "kernel_ms": ms, "total_fit_sweeps": int(sweeps),
+    return {"metric": "batched CV: fit-sweeps/s (10 folds x 16 Laplace variances, warm starts)",
+            "value": sweeps / wall, "unit": "fit-sweeps/s", "kernel_ms": ms, "wall_s": wall,
+            "total_fit_sweeps": sweeps, "critical_path_sweeps": critical,
+            "ms_per_critical_sweep": ms / max(critical, 1),
+            # phase A of all folds in every critical-path sweep (a fold that
+            # finished early is counted too; phase B is left out)
+            "achieved_GBs_phase_a": n_folds * phase_a / (ms / max(critical, 1) * 1e-3) / 1e9,
             "dtype": "f64" if precision == 0 else "mixed",
             "best_variance": float(grid[int(np.argmax(mean))]),
             "heldout_loglik_mean_by_variance": [float(x) for x in mean],
             "config": {"workload": f"mid SCCS ({prob.n_patients} patients, J={prob.n_cols}) x 10 folds x 16 variances",
+                       "engine": ["partitioned", "lockstep"][engine],
                        "max_sweeps_per_link": max_sweeps, "tol": tol}}
 
 
@@ -430,6 +445,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--print-sha", action="store_true", help="print the sweep kernel's source hash and exit")
     ap.add_argument("--cv-max-sweeps", type=int, default=50)
+    ap.add_argument("--batch-engine", type=int, choices=[0, 1], default=0,
+                    help="batched workloads: 0 fits on disjoint workgroup ranges, 1 all fits in lockstep")
     ap.add_argument("--cv-tol", type=float, default=1e-8)
     ap.add_argument("--coord-curve", action="store_true",
                     help="per-coordinate achieved bandwidth against column size (mid or full workload)")
@@ -440,6 +457,9 @@ def main():
     ap.add_argument("--workgroups", type=int, default=128)
     # the mixed form (one pass per group throughout) is fastest on every CU
     ap.add_argument("--mixed-workgroups", type=int, default=0)
+    # sweeps between exact recomputations of the FP32 weights in the mixed
+    # form (-1: the library's default, every sweep)
+    ap.add_argument("--mixed-refresh", type=int, default=-1)
     args = ap.parse_args()
     if args.print_sha:
         print(kernel_source_sha())
@@ -458,7 +478,7 @@ def main():
         return
     if args.workload == "outcomes":
         for prec in ((1,) if args.mixed_only else (0, 1)):
-            print(json.dumps(batched_outcomes_bench(sccs, synth, args.steps, prec)), flush=True)
+            print(json.dumps(batched_outcomes_bench(sccs, synth, args.steps, prec, args.batch_engine)), flush=True)
         return
     if args.tune:
         prob = synth.mid(n_patients=args.patients, n_cols=args.cols)
@@ -476,8 +496,8 @@ def main():
         print(json.dumps(full_bench(sccs, synth, args.steps, refit=not args.no_cpu)), flush=True)
         return
     if args.workload == "cv":
-        print(json.dumps(cv_bench(sccs, synth, 1 if args.mixed_only else 0, args.cv_max_sweeps, args.cv_tol)),
-              flush=True)
+        print(json.dumps(cv_bench(sccs, synth, 1 if args.mixed_only else 0, args.cv_max_sweeps, args.cv_tol,
+                                  engine=args.batch_engine)), flush=True)
         return
 
     t0 = time.perf_counter()
@@ -540,7 +560,8 @@ def main():
                               "achieved_GBs": float(np.mean(lt["bytes"])) / (lms * 1e-3) / 1e9,
                               "schedule": sched(lt)}
     if not args.no_mixed:
-        mx = run_form(sccs, prob, 1, args.steps, args.warmup, c, p, args.mixed_workgroups)
+        mx = run_form(sccs, prob, 1, args.steps, args.warmup, c, p, args.mixed_workgroups,
+                      refresh_period=args.mixed_refresh)
         err = float(np.max(np.abs(mx["beta"] - fp["beta"])) / max(np.max(np.abs(fp["beta"])), 1e-300))
         mms = float(np.mean(mx["kernel_ms"]))
         out["mixed"] = {"value": args.steps / mx["wall_s"], "unit": "sweeps/s",
@@ -548,6 +569,7 @@ def main():
                         "achieved_GBs": float(np.mean(mx["bytes"])) / (mms * 1e-3) / 1e9,
                         "rel_err_vs_fp64_gpu": err,
                         "n_workgroups": args.mixed_workgroups,
+                        "refresh_period": args.mixed_refresh,
                         "sweeps_compared": f"1..{args.steps} from beta = 0"}
         print(f"[bench] mixed done: {out['mixed']['value']:.1f} sweeps/s, rel err {err:.2e}",
               file=sys.stderr, flush=True)

@@ -116,9 +116,9 @@ typedef struct sccs_options {
                               independent Newton steps and are visited with one device-wide
                               reduction, up to max_group columns at a time (results equal
                               those of visiting them one by one, up to summation order);
-                              0 = 4, else 1..4 (1 = one column per reduction).  The batched
-                              form groups columns only when all its fits share one problem,
-                              with at most 64 / n_fits columns per group. */
+                              0 = 4, else 1..4 (1 = one column per reduction).  The lockstep
+                              batched engine groups columns only when all its fits share one
+                              problem, with at most 64 / n_fits columns per group. */
   int32_t merge_passes;    /* single fit: 1 = let up to 3 consecutive column groups (5 columns
                               at most) share one reduction when every earlier column of the
                               pass that shares a patient with a later group took a zero step
@@ -129,6 +129,13 @@ typedef struct sccs_options {
                               follow one where most steps were zero (see sccs_pass_stats);
                               0 = off.  Default 1. */
   void* stream;            /* hipStream_t */
+  int32_t batch_engine;    /* batched form: 0 = partitioned (default): each fit runs the single-fit
+                              sweep (with column groups up to max_group) on its own range of the
+                              launch's workgroups; up to 32 fits per launch, taken in decreasing
+                              order of nonzeros, the workgroups shared out in multiples of 8 in
+                              proportion to nonzeros; one launch per prior link and per 32 fits.
+                              1 = lockstep: all fits on all workgroups in one launch, one
+                              device-wide reduction per coordinate (or column group) for all */
 } sccs_options;
 
 typedef struct sccs_fit_opts {
@@ -283,10 +290,13 @@ const char* sccs_last_error(const sccs_handle* h);
 
 /* ------------------------------------------------------------ batched form
  *
- * F <= 64 independent fits advanced in lockstep by one persistent launch
- * (Section 2.5: cross-validation over a prior grid and bootstrap replicates
- * need many fits; different outcomes over one drug vocabulary likewise).
- * All problems of a batch share n_cols.  Per coordinate, one device-wide
+ * F <= 64 independent fits on one device (Section 2.5: cross-validation
+ * over a prior grid and bootstrap replicates need many fits; different
+ * outcomes over one drug vocabulary likewise).  All problems of a batch
+ * share n_cols.  Two engines (sccs_options.batch_engine): partitioned, where
+ * each fit runs the single-fit sweep on its own range of workgroups and
+ * stops on its own, one launch per prior link; or lockstep, where one
+ * persistent launch runs every chain and, per coordinate, one device-wide
  * reduction carries the partial sums of all fits.  Each fit walks a chain
  * of priors in order: link l starts from the beta where link l-1 ended
  * (warm start, Section 2.5), with every trust bound reset to 1, and ends
@@ -331,7 +341,8 @@ sccs_status sccs_batch_get(sccs_batch* b, int32_t fit, int32_t link, double* bet
  * SCCS_ERR_STATE if the fit has no patient weights or the link has not run. */
 sccs_status sccs_batch_heldout(sccs_batch* b, int32_t fit, int32_t link, double* loglik);
 
-/* Device time of the last sccs_batch_run launch (ms). */
+/* Device time of the last sccs_batch_run (ms): its launch (lockstep), or
+ * the sum of its sweep launches (partitioned). */
 sccs_status sccs_batch_last_kernel_ms(sccs_batch* b, double* ms);
 
 /* NULL-safe. */
@@ -339,6 +350,17 @@ sccs_status sccs_batch_destroy(sccs_batch* b);
 
 /* Description of the last error on b, or of the last failed create. */
 const char* sccs_batch_last_error(const sccs_batch* b);
+
+/* Autotuner of the batched form: times the same candidate launch shapes as
+ * sccs_tune -- workgroup counts (all compute units, 3/4, 1/2, 1/4) x tile
+ * sizes (16, 32, 64 nonzeros) -- on this batch of problems and fits, each
+ * for n_sweeps sweeps (every fit's first link, FIXED) after one warm-up
+ * sweep, on temporary library-allocated batches of base's engine; returns
+ * the fastest as options and the per-candidate timings (ms per sweep of the
+ * whole batch).
+ * Synchronises; allocates and frees device memory. */
+sccs_status sccs_batch_tune(const sccs_problem* probs, int32_t n_probs, const sccs_fit_spec* fits, int32_t n_fits,
+                            const sccs_options* base, int32_t n_sweeps, sccs_options* best, sccs_tune_result* result);
 
 /* ------------------------------------------------------------ bootstrap
  *
@@ -382,7 +404,7 @@ sccs_status sccs_bootstrap(const sccs_problem* prob, const sccs_options* opts, v
  *
  * Cross-validated choice of the prior variance (Section 2.5): the patients
  * are split into folds; for a variance, each fold is fitted on the other
- * folds' patients (one batched launch, one fit per fold) and the held-out
+ * folds' patients (one batched run, one fit per fold) and the held-out
  * Eq. 2 of its own patients is summed over folds (the predictive
  * log-likelihood).  Instead of a fixed grid, the search brackets the
  * maximum and then narrows it, the refinement the paper suggests:

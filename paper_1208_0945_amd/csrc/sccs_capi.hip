@@ -151,6 +151,10 @@ sccs_status check_options(const sccs_options* o, std::string& err) {
     err = "options.merge_passes must be 0 or 1";
     return SCCS_ERR_INVALID_ARG;
   }
+  if (o->batch_engine != 0 && o->batch_engine != 1) {
+    err = "options.batch_engine must be 0 (partitioned) or 1 (lockstep)";
+    return SCCS_ERR_INVALID_ARG;
+  }
   return SCCS_OK;
 }
 
@@ -393,6 +397,7 @@ void sccs_default_options(sccs_options* o) {
   o->max_group = 0;
   o->merge_passes = 1;
   o->stream = nullptr;
+  o->batch_engine = 0;
 }
 
 sccs_status sccs_query_workspace(const sccs_problem* prob, const sccs_options* opts, size_t* bytes) {

@@ -107,6 +107,9 @@ struct KArgs {
   // taken in the current sweep ([n_groups]) and at the sweep's start
   // ([n_groups]); written by workgroup 0
   uint64_t* group_ticks;      // [n_groups + 1]
+  // first workgroup of this fit in the launch: several single fits can share
+  // one launch, fit f on workgroups [b0, b0 + G) (0 for a launch of one fit)
+  int32_t b0;
 };
 
 enum { kModeSweep = 0, kModeGradHess = 1, kModeObjective = 2 };

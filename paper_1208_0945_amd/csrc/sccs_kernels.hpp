@@ -153,7 +153,8 @@ __device__ __forceinline__ bool poll_tagged(const uint64_t* src, bool active, ui
   }
 }
 
-// Device-wide sum of NV non-negative doubles per workgroup, in two levels:
+// Device-wide sum of NV non-negative doubles per workgroup (member b of G;
+// several fits can share a launch, each on a range of workgroups), in two levels:
 // the workgroups form ng = min(8, G) groups (b mod ng, which follows the
 // round-robin placement of workgroups on the eight XCDs); the leader of a
 // group (workgroup g < ng) sums its members' tagged slots in member order and
@@ -171,8 +172,8 @@ __device__ __forceinline__ bool poll_tagged(const uint64_t* src, bool active, ui
 // waited on.)
 template <int NV>
 __device__ bool allreduce2_wave(uint64_t* s1, uint64_t* s2, uint32_t seq, int G, Ctrl* ctrl,
-                                const double* part, double* out) {
-  const int lane = threadIdx.x & 63, b = blockIdx.x;
+                                const double* part, double* out, int b) {
+  const int lane = threadIdx.x & 63;
   const uint32_t par = seq & 1u, tag = (seq >> 1) & 1u;
   const int ng = G < kGroups ? G : kGroups;
   uint64_t* L1 = s1 + (size_t)par * (kSlots1Words / 2);
@@ -212,10 +213,10 @@ __device__ bool allreduce2_wave(uint64_t* s1, uint64_t* s2, uint32_t seq, int G,
 // LDS.  Called by all threads with the partials valid in thread 0.
 template <int NV>
 __device__ bool allreduce_nonneg(uint64_t* s1, uint64_t* s2, uint32_t seq, int G, Ctrl* ctrl,
-                                 const double* part, double* out, double* lds_out, int* lds_ok) {
+                                 const double* part, double* out, double* lds_out, int* lds_ok, int b) {
   if (threadIdx.x < 64) {
     double o[NV];
-    bool ok = allreduce2_wave<NV>(s1, s2, seq, G, ctrl, part, o);
+    bool ok = allreduce2_wave<NV>(s1, s2, seq, G, ctrl, part, o, b);
     if (threadIdx.x == 0) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) lds_out[v] = o[v];
@@ -569,15 +570,109 @@ __device__ __forceinline__ void tile_b(const KArgs& a, int t, Coef cf) {
 }
 
 // ---- tiles t, t + stride, ... < t1 of one range, in order
-
-template <typename WT, int NC, bool kMark>
+//
+// kTileBatch tiles at a time: their bounds, index words, weight and patient
+// gathers are all issued before any is used, so that a wave keeps that many
+// tiles' loads in flight (a column with many tiles per workgroup is bound by
+// memory latency otherwise).  Each tile's terms are still added in tile
+// order, so every sum is the one of one tile at a time, bit for bit.  Within
+// a group, and within a pass, no two tiles of an update touch the same era
+// or patient, so loading before storing changes nothing in phase B either.
+// (The one-pass form uses kTileBatch = 4; the merged-pass form and the
+// batched kernel keep one tile at a time, B = 1: their registers are taken.)
+template <typename WT, int NC, bool kMark, int kTileBatch = 1>
 __device__ __forceinline__ void tiles_a(const KArgs& a, int t, int t1, int stride, Acc<NC>& acc,
                                         unsigned* bits = nullptr, int p0 = 0, uint32_t coff = 0) {
+  const int lane = threadIdx.x & 63;
+  const WT* __restrict__ w = (const WT*)a.w;
+  for (; kTileBatch > 1 && t + (kTileBatch - 1) * stride < t1; t += kTileBatch * stride) {
+    int e0[kTileBatch], len[kTileBatch];
+#pragma unroll
+    for (int k = 0; k < kTileBatch; ++k) {
+      e0[k] = ld_idx(a.tile_start + t + k * stride);
+      len[k] = ld_idx(a.tile_start + t + k * stride + 1) - e0[k];
+    }
+    uint2 rp[kTileBatch];
+#pragma unroll
+    for (int k = 0; k < kTileBatch; ++k)
+      rp[k] = (len[k] <= 64 && lane < len[k]) ? a.rp[e0[k] + lane] : make_uint2(0u, 0xffffffffu);
+    double wv[kTileBatch];
+    double2 pv[kTileBatch];
+    bool lead[kTileBatch];
+    int ss[kTileBatch];
+#pragma unroll
+    for (int k = 0; k < kTileBatch; ++k) {
+      lead[k] = false;
+      ss[k] = lane;
+      wv[k] = 0.0;
+      pv[k] = make_double2(1.0, 0.0);
+      if (len[k] <= 64) {
+        seg_layout(rp[k].y, lane, len[k], lead[k], ss[k]);
+        if (lane < len[k]) wv[k] = (double)w[rp[k].x];
+        if (lead[k]) pv[k] = a.pat[pid_of(rp[k].y)];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kTileBatch; ++k) {
+      if (len[k] <= 64) {
+        const double num = seg_sum_v(wv[k], lane, ss[k]);
+        if (lead[k]) {
+          acc.add(col_of(rp[k].y) + coff, num, pv[k]);
+          if (kMark) atomicOr(&bits[(pid_of(rp[k].y) - p0) >> 5], 1u << ((pid_of(rp[k].y) - p0) & 31));
+        }
+      } else {
+        tile_a<WT, NC, kMark>(a, t + k * stride, acc, bits, p0, coff);
+      }
+    }
+  }
   for (; t < t1; t += stride) tile_a<WT, NC, kMark>(a, t, acc, bits, p0, coff);
 }
 
-template <typename WT>
+template <typename WT, int kTileBatch = 1>
 __device__ __forceinline__ void tiles_b(const KArgs& a, int t, int t1, int stride, Coef cf) {
+  const int lane = threadIdx.x & 63;
+  WT* __restrict__ w = (WT*)a.w;
+  for (; kTileBatch > 1 && t + (kTileBatch - 1) * stride < t1; t += kTileBatch * stride) {
+    int e0[kTileBatch], len[kTileBatch];
+#pragma unroll
+    for (int k = 0; k < kTileBatch; ++k) {
+      e0[k] = ld_idx(a.tile_start + t + k * stride);
+      len[k] = ld_idx(a.tile_start + t + k * stride + 1) - e0[k];
+    }
+    uint2 rp[kTileBatch];
+#pragma unroll
+    for (int k = 0; k < kTileBatch; ++k)
+      rp[k] = (len[k] <= 64 && lane < len[k]) ? a.rp[e0[k] + lane] : make_uint2(0u, 0xffffffffu);
+    WT wo[kTileBatch];
+    double ed[kTileBatch], em1[kTileBatch];
+    bool upd[kTileBatch];
+#pragma unroll
+    for (int k = 0; k < kTileBatch; ++k) {
+      const bool act = len[k] <= 64 && lane < len[k];
+      const uint32_t c = act ? col_of(rp[k].y) : 0u;
+      ed[k] = cf.ed[c];
+      em1[k] = cf.em1[c];
+      upd[k] = act && em1[k] != 0.0;
+      wo[k] = upd[k] ? w[rp[k].x] : (WT)0;
+    }
+#pragma unroll
+    for (int k = 0; k < kTileBatch; ++k) {
+      if (len[k] <= 64) {
+        const WT wn = wo[k] * (WT)ed[k];
+        if (upd[k]) w[rp[k].x] = wn;
+        bool lead;
+        if (sizeof(WT) == 8) {
+          const double s = seg_sum((double)wo[k], rp[k].y, lane, len[k], lead);
+          if (lead && upd[k]) a.pat[pid_of(rp[k].y)].x += s * em1[k];
+        } else {
+          const double s = seg_sum((double)wn - (double)wo[k], rp[k].y, lane, len[k], lead);
+          if (lead && upd[k]) a.pat[pid_of(rp[k].y)].x += s;
+        }
+      } else {
+        tile_b<WT>(a, t + k * stride, cf);
+      }
+    }
+  }
   for (; t < t1; t += stride) tile_b<WT>(a, t, cf);
 }
 
@@ -619,7 +714,7 @@ struct Cache {
 };
 
 __device__ __forceinline__ void pf_range(const KArgs& a, int g, int& t0, int& t1) {
-  const size_t base = (size_t)g * (a.G + 1) + blockIdx.x;
+  const size_t base = (size_t)g * (a.G + 1) + ((int)blockIdx.x - a.b0);
   t0 = ld_idx(a.own + base);
   t1 = ld_idx(a.own + base + 1);
 }
@@ -714,7 +809,7 @@ __device__ __forceinline__ bool first_tile_stale(const Pf& p, const unsigned* bi
 
 // Phase A of the current group for one worker wave: the cached first tile
 // (validated by the caller) plus its remaining tiles.
-template <typename WT, int NC>
+template <typename WT, int NC, int B = 1>
 __device__ __forceinline__ void phase_a_cached(const KArgs& a, const Pf& p, const Cache& c, Acc<NC>& acc,
                                                unsigned* bits, int p0, uint32_t coff) {
   if (p.t < p.t1) {
@@ -727,10 +822,10 @@ __device__ __forceinline__ void phase_a_cached(const KArgs& a, const Pf& p, cons
       tile_a<WT, NC, true>(a, p.t, acc, bits, p0, coff);
     }
   }
-  tiles_a<WT, NC, true>(a, p.t + kWorkers, p.t1, kWorkers, acc, bits, p0, coff);
+  tiles_a<WT, NC, true, B>(a, p.t + kWorkers, p.t1, kWorkers, acc, bits, p0, coff);
 }
 
-template <typename WT>
+template <typename WT, int B = 1>
 __device__ __forceinline__ void phase_b_cached(const KArgs& a, const Pf& p, const Cache& c, Coef cf) {
   const int lane = threadIdx.x & 63;
   WT* __restrict__ w = (WT*)a.w;
@@ -756,7 +851,7 @@ __device__ __forceinline__ void phase_b_cached(const KArgs& a, const Pf& p, cons
       tile_b<WT>(a, p.t, cf);
     }
   }
-  tiles_b<WT>(a, p.t + kWorkers, p.t1, kWorkers, cf);
+  tiles_b<WT, B>(a, p.t + kWorkers, p.t1, kWorkers, cf);
 }
 
 // ---- passes
@@ -916,6 +1011,7 @@ __device__ __forceinline__ void refresh_range(const KArgs& a, const double* beta
 // L = sum_j beta_j Y'X_j - sum_i omega_i n_i log den_i, plus log p(beta), and
 // for the change criterion sum_k |eta_k - eta_k(sweep start)| over owned eras.
 // Called by all threads of every workgroup; results valid in all threads.
+template <bool kGrouped = true>
 __device__ __forceinline__ bool objective(const KArgs& a, const double* sbeta, const double* sprev, int p0, int p1,
                                           uint32_t oseq, double* out3, double (*red)[4], double* bc, int* bci) {
   const int tid = threadIdx.x;
@@ -947,7 +1043,7 @@ __device__ __forceinline__ bool objective(const KArgs& a, const double* sbeta, c
     else if (a.prior_kind == SCCS_PRIOR_LAPLACE) bl[1] -= a.lambda * fabs(bj);
   }
   // grouped prior: + kappa_c S_c^2 / (2 var) per class (S_c kept in LDS)
-  if (a.prior_kind == SCCS_PRIOR_GROUPED) {
+  if (kGrouped && a.prior_kind == SCCS_PRIOR_GROUPED) {
     const double* ssum = (const double*)(&sbeta[0]) + a.ssum_off;
     for (int c = tid; c < a.n_classes; c += kBlock) bl[1] += a.pkappa[c] * ssum[c] * ssum[c] / (2.0 * a.var);
   }
@@ -957,7 +1053,7 @@ __device__ __forceinline__ bool objective(const KArgs& a, const double* sbeta, c
   block_sum<2>(bl, bsum, red);
   if (tid == 0) { bc[4] = bsum[0]; bc[5] = bsum[1]; }
   double tot[4];
-  bool ok = allreduce_nonneg<4>(a.oslots, a.oslots2, oseq, a.G, a.ctrl, part, tot, bc, bci);
+  bool ok = allreduce_nonneg<4>(a.oslots, a.oslots2, oseq, a.G, a.ctrl, part, tot, bc, bci, (int)blockIdx.x - a.b0);
   out3[0] = bc[4] - (tot[0] - tot[1]);  // loglik
   out3[1] = out3[0] + bc[5];            // logpost
   out3[2] = tot[2];                     // sum |delta eta|
@@ -968,7 +1064,7 @@ __device__ __forceinline__ bool objective(const KArgs& a, const double* sbeta, c
 // ------------------------------------------------------------ persistent kernel
 
 template <typename WT, bool kMerge>
-__global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
+__device__ __forceinline__ void ccd_body(const KArgs& a) {
   extern __shared__ double lds_dyn[];
   double* sbeta = lds_dyn;              // [J]
   double* strust = lds_dyn + a.J;       // [J]
@@ -979,7 +1075,7 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
   __shared__ int bci[4];
   __shared__ double s_ed[kPassCols], s_em1[kPassCols];
 
-  const int tid = threadIdx.x, b = blockIdx.x;
+  const int tid = threadIdx.x, b = (int)blockIdx.x - a.b0;
   for (int j = tid; j < a.J; j += kBlock) {
     sbeta[j] = a.beta[j];
     strust[j] = a.trust[j];
@@ -991,7 +1087,8 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
   uint32_t oseq = a.ctrl->oseq;
   int since_refresh = a.ctrl->since_refresh;
   __syncthreads();
-  if (a.prior_kind == SCCS_PRIOR_GROUPED) {
+  // grouped prior (never run in the merged-pass form)
+  if (!kMerge && a.prior_kind == SCCS_PRIOR_GROUPED) {
     class_sums(a, sbeta, lds_dyn + a.ssum_off);
     __syncthreads();
   }
@@ -1003,7 +1100,7 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
   double lp_prev = 0.0;
   if (a.criterion == SCCS_CRIT_REL_LOGPOST) {
     double o3[3];
-    ok = objective(a, sbeta, sprev, p0, p1, oseq++, o3, red, bc, bci);
+    ok = objective<!kMerge>(a, sbeta, sprev, p0, p1, oseq++, o3, red, bc, bci);
     lp_prev = o3[1];
   }
   int sweep = 0, converged = 0;
@@ -1201,17 +1298,17 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
           for (int i = 0; i < 2 * kPassCols; ++i) tot[i] = 0.0;
           bool okr;
           switch (cls) {   // one width per slot class, fixed at compile time
-            case 0: okr = allreduce2_wave<2>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
+            case 0: okr = allreduce2_wave<2>(s1, s2, sq, a.G, a.ctrl, part, tot, b); break;
 #if SCCS_MAX_GROUP >= 2
-            case 1: okr = allreduce2_wave<4>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
+            case 1: okr = allreduce2_wave<4>(s1, s2, sq, a.G, a.ctrl, part, tot, b); break;
 #endif
 #if SCCS_MAX_GROUP >= 3
-            case 2: okr = allreduce2_wave<6>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
+            case 2: okr = allreduce2_wave<6>(s1, s2, sq, a.G, a.ctrl, part, tot, b); break;
 #endif
 #if SCCS_MAX_GROUP >= 4
-            case 3: okr = allreduce2_wave<8>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
+            case 3: okr = allreduce2_wave<8>(s1, s2, sq, a.G, a.ctrl, part, tot, b); break;
 #endif
-            default: okr = allreduce2_wave<2 * kPassCols>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
+            default: okr = allreduce2_wave<2 * kPassCols>(s1, s2, sq, a.G, a.ctrl, part, tot, b); break;
           }
 
           double Gc = 0.0, Hc = 0.0;
@@ -1340,7 +1437,7 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
           acc.zero();
           if (!c_cur.valid || (g > 0 && prev_moved && first_tile_stale(pf_cur, bits_prev, p0)))
             gather_first<WT>(a, pf_cur, c_cur);
-          phase_a_cached<WT>(a, pf_cur, c_cur, acc, bits_cur, p0, 0u);
+          phase_a_cached<WT, kMaxGroup, 4>(a, pf_cur, c_cur, acc, bits_cur, p0, 0u);
           double loc[2 * kMaxGroup], part[2 * kMaxGroup];
 #pragma unroll
           for (int i = 0; i < kMaxGroup; ++i) {
@@ -1369,7 +1466,7 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
           if (!bci[0]) { ok = false; break; }
           if (bci[1]) { status = SCCS_ERR_NUMERIC; ok = false; break; }
           prev_moved = __builtin_amdgcn_readfirstlane(bci[2]) != 0;
-          if (prev_moved) phase_b_cached<WT>(a, pf_cur, c_cur, cf);
+          if (prev_moved) phase_b_cached<WT, 4>(a, pf_cur, c_cur, cf);
           __syncthreads();
           pf_cur = pf_next;
           pf_next = pf_next2;
@@ -1418,14 +1515,14 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
           for (int i = 0; i < 2 * kMaxGroup; ++i) tot[i] = 0.0;
           bool okr;
           switch (m) {   // one width per slot class, fixed at compile time
-            case 1: okr = allreduce2_wave<2>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
+            case 1: okr = allreduce2_wave<2>(s1, s2, sq, a.G, a.ctrl, part, tot, b); break;
 #if SCCS_MAX_GROUP >= 2
-            case 2: okr = allreduce2_wave<4>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
+            case 2: okr = allreduce2_wave<4>(s1, s2, sq, a.G, a.ctrl, part, tot, b); break;
 #endif
 #if SCCS_MAX_GROUP >= 3
-            case 3: okr = allreduce2_wave<6>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
+            case 3: okr = allreduce2_wave<6>(s1, s2, sq, a.G, a.ctrl, part, tot, b); break;
 #endif
-            default: okr = allreduce2_wave<2 * kMaxGroup>(s1, s2, sq, a.G, a.ctrl, part, tot); break;
+            default: okr = allreduce2_wave<2 * kMaxGroup>(s1, s2, sq, a.G, a.ctrl, part, tot, b); break;
           }
 
           double Gc = 0.0, Hc = 0.0;
@@ -1495,7 +1592,7 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
     const bool need_obj = (a.criterion != SCCS_CRIT_FIXED) || (a.want_objective && sweep == a.n_sweeps);
     if (need_obj) {
       double o3[3];
-      if (!objective(a, sbeta, sprev, p0, p1, oseq++, o3, red, bc, bci)) { ok = false; break; }
+      if (!objective<!kMerge>(a, sbeta, sprev, p0, p1, oseq++, o3, red, bc, bci)) { ok = false; break; }
       L = o3[0];
       P = o3[1];
       if (a.criterion == SCCS_CRIT_REL_LOGPOST) {
@@ -1534,6 +1631,21 @@ __global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
   }
 }
 
+template <typename WT, bool kMerge>
+__global__ void __launch_bounds__(kBlock) k_ccd(KArgs a) {
+  ccd_body<WT, kMerge>(a);
+}
+
+// Several independent single fits in one cooperative launch: workgroup x
+// runs fit fit_of_block[x] as that fit's workgroup x - b0 of G (its own
+// layout for G workgroups, its own state, reduction slots and control
+// block), so each fit advances, and stops, on its own.
+template <typename WT, bool kMerge>
+__global__ void __launch_bounds__(kBlock) k_ccd_multi(const KArgs* __restrict__ fits,
+                                                      const int32_t* __restrict__ fit_of_block) {
+  ccd_body<WT, kMerge>(fits[fit_of_block[blockIdx.x]]);
+}
+
 // Diagnostics: g_j, h_j of column diag_j (column diag_c of group diag_g) at
 // the current beta (mode 1), or the objective (mode 2).  Same ownership and
 // reductions as the sweep kernel.
@@ -1544,7 +1656,7 @@ __global__ void __launch_bounds__(kBlock) k_diag(KArgs a) {
   __shared__ double red[kWaves][4];
   __shared__ double bc[8];
   __shared__ int bci[4];
-  const int tid = threadIdx.x, b = blockIdx.x;
+  const int tid = threadIdx.x, b = (int)blockIdx.x - a.b0;
   for (int j = tid; j < a.J; j += kBlock) sbeta[j] = a.beta[j];
   uint32_t seq = a.ctrl->gseq[0], oseq = a.ctrl->oseq;   // one column: reduction class 0
   __syncthreads();
@@ -1572,11 +1684,40 @@ __global__ void __launch_bounds__(kBlock) k_diag(KArgs a) {
       }
     block_sum<2>(loc, part2, red);
     double tot[2];
-    bool ok = allreduce_nonneg<2>(a.slots, a.slots2, seq++, a.G, a.ctrl, part2, tot, bc, bci);
+    bool ok = allreduce_nonneg<2>(a.slots, a.slots2, seq++, a.G, a.ctrl, part2, tot, bc, bci, b);
     if (b == 0 && tid == 0 && ok) { a.ctrl->g = a.ytx[a.diag_j] - tot[0]; a.ctrl->h = -tot[1]; }
   }
   __syncthreads();
   if (b == 0 && tid == 0) { a.ctrl->gseq[0] = seq; a.ctrl->oseq = oseq; }
+}
+
+// Held-out log-likelihood of one fit (Eq. 2 over its weight-0 patients):
+// block partials of -sum_i hn_i log den_i over a fixed grid, then one block
+// adds them in block order and beta'Y'X(held out) (fixed order throughout).
+constexpr int kHoBlocks = 64;
+__global__ void __launch_bounds__(256) k_heldout_part(const double2* pat, const double* hn, int N, double* part) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < N; i += kHoBlocks * 256)
+    if (hn[i] != 0.0) s -= hn[i] * log(pat[i].x);
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+__global__ void __launch_bounds__(256) k_heldout_final(const double* part, const double* beta, const double* ytx_ho,
+                                                       int J, double* out) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int j = threadIdx.x; j < J; j += 256) s += beta[j] * ytx_ho[j];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = (red[0] + red[1]) + (red[2] + red[3]);
+    for (int b = 0; b < kHoBlocks; ++b) t += part[b];
+    *out = t;
+  }
 }
 
 // ------------------------------------------------------------ setup kernels
@@ -1643,6 +1784,8 @@ template __global__ void k_ccd<double, false>(KArgs);
 template __global__ void k_ccd<double, true>(KArgs);
 template __global__ void k_ccd<float, false>(KArgs);
 template __global__ void k_ccd<float, true>(KArgs);
+template __global__ void k_ccd_multi<double, false>(const KArgs*, const int32_t*);
+template __global__ void k_ccd_multi<float, false>(const KArgs*, const int32_t*);
 template __global__ void k_diag<double>(KArgs);
 template __global__ void k_diag<float>(KArgs);
 template __global__ void k_refresh<double>(KArgs);

@@ -174,7 +174,7 @@ __device__ __forceinline__ void val_group_step(const KArgs& a, const AccV<kMaxGr
 #pragma unroll
     for (int i = 0; i < NV; ++i) tot[i] = 0.0;
     const bool okr = allreduce2_wave<NV>(a.slots + (M - 1) * kSlots1PerClass, a.slots2 + (M - 1) * kSlots2PerClass,
-                                         seq, a.G, a.ctrl, part, tot);
+                                         seq, a.G, a.ctrl, part, tot, (int)blockIdx.x - a.b0);
     double Gp = 0.0, Gn = 0.0, Hc = 0.0;
 #pragma unroll
     for (int c = 0; c < M; ++c)
@@ -230,7 +230,7 @@ __global__ void __launch_bounds__(kBlock) k_ccd_val(KArgs a) {
   __shared__ int bci[4];
   __shared__ double s_d[kMaxGroup];
 
-  const int tid = threadIdx.x, b = blockIdx.x, wave = tid >> 6;
+  const int tid = threadIdx.x, b = (int)blockIdx.x - a.b0, wave = tid >> 6;
   for (int j = tid; j < a.J; j += kBlock) {
     sbeta[j] = a.beta[j];
     strust[j] = a.trust[j];
@@ -350,7 +350,7 @@ __global__ void __launch_bounds__(kBlock) k_diag_val(KArgs a) {
   __shared__ double red[kWaves][4];
   __shared__ double bc[8];
   __shared__ int bci[4];
-  const int tid = threadIdx.x, b = blockIdx.x;
+  const int tid = threadIdx.x, b = (int)blockIdx.x - a.b0;
   uint32_t seq = a.ctrl->gseq[0];
   AccV<kMaxGroup> acc;
   acc.zero();
@@ -366,7 +366,7 @@ __global__ void __launch_bounds__(kBlock) k_diag_val(KArgs a) {
     }
   block_sum<kValWords>(loc, part, red);
   double tot[kValWords];
-  const bool ok = allreduce_nonneg<kValWords>(a.slots, a.slots2, seq++, a.G, a.ctrl, part, tot, bc, bci);
+  const bool ok = allreduce_nonneg<kValWords>(a.slots, a.slots2, seq++, a.G, a.ctrl, part, tot, bc, bci, b);
   if (b == 0 && tid == 0 && ok) {
     a.ctrl->g = a.ytx[a.diag_j] - (tot[0] - tot[1]);
     a.ctrl->h = -tot[2];

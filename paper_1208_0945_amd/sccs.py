@@ -30,7 +30,8 @@ EXPORTS = ("sccs_default_options", "sccs_query_workspace", "sccs_create", "sccs_
            "sccs_batch_query_workspace", "sccs_batch_create", "sccs_batch_run", "sccs_batch_get",
            "sccs_batch_heldout", "sccs_batch_last_kernel_ms", "sccs_batch_destroy", "sccs_batch_last_error", "sccs_tune",
            "sccs_sweep_static", "sccs_bootstrap_query_workspace", "sccs_bootstrap",
-           "sccs_cv_query_workspace", "sccs_cv_search", "sccs_set_prior_grouped", "sccs_group_times")
+           "sccs_cv_query_workspace", "sccs_cv_search", "sccs_set_prior_grouped", "sccs_group_times",
+           "sccs_batch_tune")
 
 
 class SccsError(RuntimeError):
@@ -52,7 +53,7 @@ class Options_(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("n_workgroups", ctypes.c_int32),
                 ("refresh_period", ctypes.c_int32), ("tile_nnz", ctypes.c_int32),
                 ("max_group", ctypes.c_int32), ("merge_passes", ctypes.c_int32),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("batch_engine", ctypes.c_int32)]
 
 
 class FitOpts_(ctypes.Structure):
@@ -172,6 +173,9 @@ def lib() -> ctypes.CDLL:
                                 ctypes.c_int32, ctypes.POINTER(Options_), ctypes.POINTER(TuneResult_)]
         L.sccs_batch_last_error.argtypes = [H]
         L.sccs_batch_last_error.restype = ctypes.c_char_p
+        L.sccs_batch_tune.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                                      ctypes.POINTER(Options_), ctypes.c_int32, ctypes.POINTER(Options_),
+                                      ctypes.POINTER(TuneResult_)]
         L.sccs_bootstrap_query_workspace.argtypes = [ctypes.POINTER(Problem_), ctypes.POINTER(Options_),
                                                      ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
         L.sccs_bootstrap.argtypes = [ctypes.POINTER(Problem_), ctypes.POINTER(Options_), ctypes.c_void_p,
@@ -216,7 +220,7 @@ class ProblemArrays:
 
 def options(precision: int = PREC_FP64, n_workgroups: int = 0, refresh_period: int = -1,
             stream: Optional[int] = None, tile_nnz: int = 0, max_group: int = 0,
-            merge_passes: int = 1) -> Options_:
+            merge_passes: int = 1, batch_engine: int = 0) -> Options_:
     o = Options_()
     lib().sccs_default_options(ctypes.byref(o))
     o.precision = precision
@@ -226,6 +230,7 @@ def options(precision: int = PREC_FP64, n_workgroups: int = 0, refresh_period: i
     o.max_group = max_group
     o.merge_passes = merge_passes
     o.stream = stream
+    o.batch_engine = batch_engine
     return o
 
 
@@ -393,6 +398,24 @@ def tune(prob, prior_kind: int, variance: float, n_sweeps: int = 2, precision: i
     return {"n_workgroups": best.n_workgroups, "tile_nnz": best.tile_nnz}, table
 
 
+def batch_tune(probs, specs, n_sweeps: int = 2, precision: int = PREC_FP64, engine: int = 0):
+    """Run the batched form's autotuner; returns (best options dict, candidate table)."""
+    import torch
+    P = [ProblemArrays(p) for p in probs]
+    parr = (Problem_ * len(P))(*[q.s for q in P])
+    sarr = (FitSpec_ * len(specs))(*[s.struct() for s in specs])
+    o = options(precision, 0, -1, torch.cuda.current_stream().cuda_stream, batch_engine=engine)
+    best = Options_()
+    r = TuneResult_()
+    st = lib().sccs_batch_tune(ctypes.addressof(parr), len(P), ctypes.addressof(sarr), len(specs), ctypes.byref(o),
+                               int(n_sweeps), ctypes.byref(best), ctypes.byref(r))
+    if st != OK:
+        raise SccsError(st, lib().sccs_batch_last_error(None).decode())
+    table = [{"n_workgroups": r.n_workgroups[k], "tile_nnz": r.tile_nnz[k], "ms_per_sweep": r.ms_per_sweep[k]}
+             for k in range(r.n_candidates)]
+    return {"n_workgroups": best.n_workgroups, "tile_nnz": best.tile_nnz}, table
+
+
 class FitSpec:
     """One fit of a batch: a problem index, a chain of (prior kind, variance)
     links visited with warm starts, and optional patient weights."""
@@ -412,7 +435,8 @@ class Batch:
     """Many fits in one persistent launch (sccs_batch_*)."""
 
     def __init__(self, probs, specs, precision: int = PREC_FP64, n_workgroups: int = 0,
-                 refresh_period: int = -1, stream=None, tile_nnz: int = 0, max_group: int = 0):
+                 refresh_period: int = -1, stream=None, tile_nnz: int = 0, max_group: int = 0,
+                 engine: int = 0):
         import torch
         if stream is None:
             stream = torch.cuda.current_stream()
@@ -422,7 +446,8 @@ class Batch:
         parr = (Problem_ * len(self._probs))(*[P.s for P in self._probs])
         sarr = (FitSpec_ * len(self._specs))(*[s.struct() for s in self._specs])
         self._parr, self._sarr = parr, sarr
-        o = options(precision, n_workgroups, refresh_period, stream.cuda_stream, tile_nnz, max_group)
+        o = options(precision, n_workgroups, refresh_period, stream.cuda_stream, tile_nnz, max_group,
+                    batch_engine=engine)
         L = lib()
         n = ctypes.c_size_t()
         st = L.sccs_batch_query_workspace(ctypes.addressof(parr), len(self._probs), ctypes.addressof(sarr),
@@ -489,7 +514,7 @@ class Batch:
 
 def bootstrap(prob, prior_kind: int, variance: float, weights, criterion: int = CRIT_REL_LOGPOST,
               max_sweeps: int = 100, tol: float = 1e-8, level: float = 0.95, precision: int = PREC_FP64,
-              n_workgroups: int = 0, stream=None) -> dict:
+              n_workgroups: int = 0, stream=None, engine: int = 0) -> dict:
     """sccs_bootstrap: one fit per row of weights ([R, N] patient
     multiplicities), percentile intervals and the share of nonzero estimates.
     Returns dict(beta [R, J], lo, hi, p_nonzero, sweeps, converged)."""
@@ -501,7 +526,7 @@ def bootstrap(prob, prior_kind: int, variance: float, weights, criterion: int = 
     P = ProblemArrays(prob)
     if W.ndim != 2 or W.shape[1] != int(prob.n_patients):
         raise ValueError("weights must be [n_replicates, n_patients]")
-    o = options(precision, n_workgroups, -1, stream.cuda_stream)
+    o = options(precision, n_workgroups, -1, stream.cuda_stream, batch_engine=engine)
     L = lib()
     n = ctypes.c_size_t()
     st = L.sccs_bootstrap_query_workspace(ctypes.byref(P.s), ctypes.byref(o), R, ctypes.byref(n))
@@ -527,7 +552,7 @@ def bootstrap(prob, prior_kind: int, variance: float, weights, criterion: int = 
 def cv_search(prob, folds, n_folds: int, prior_kind: int, var_start: float = 0.01, bracket_step: float = 10.0,
               log10_tol: float = 0.05, max_evals: int = 30, warm_start: bool = True,
               criterion: int = CRIT_REL_LOGPOST, max_sweeps: int = 100, tol: float = 1e-10,
-              precision: int = PREC_FP64, n_workgroups: int = 0, stream=None) -> dict:
+              precision: int = PREC_FP64, n_workgroups: int = 0, stream=None, engine: int = 0) -> dict:
     """sccs_cv_search: bracketing and golden-section search of the
     cross-validated predictive log-likelihood over the prior variance.
     Returns dict(variance, pred_loglik [per evaluation], best, bracketed)."""
@@ -536,7 +561,7 @@ def cv_search(prob, folds, n_folds: int, prior_kind: int, var_start: float = 0.0
         stream = torch.cuda.current_stream()
     P = ProblemArrays(prob)
     fold = _arr(folds, np.int32)
-    o = options(precision, n_workgroups, -1, stream.cuda_stream)
+    o = options(precision, n_workgroups, -1, stream.cuda_stream, batch_engine=engine)
     L = lib()
     n = ctypes.c_size_t()
     st = L.sccs_cv_query_workspace(ctypes.byref(P.s), ctypes.byref(o), int(n_folds), ctypes.byref(n))

@@ -1,5 +1,7 @@
-"""GPU parity of the batched form: several fits advanced in lockstep in one
-persistent launch, each checked against the FP64 oracle run fit by fit.
+"""GPU parity of the batched form, each fit checked against the FP64 oracle
+run fit by fit, under both engines: fits on disjoint workgroup ranges of one
+launch (each running the single-fit sweep), and all fits advanced in
+lockstep on every workgroup.
 
 Configurations mirror the batched workloads at reduced size: independent
 outcomes over one shared drug vocabulary with uneven patient counts, and
@@ -27,6 +29,13 @@ def sccs():
     return s
 
 
+@pytest.fixture(params=[0, 1], ids=["partitioned", "lockstep"])
+def engine(request):
+    """Both engines of the batched form: fits on disjoint workgroup ranges
+    (0), or all fits in lockstep on every workgroup (1)."""
+    return request.param
+
+
 def rel_inf(a, b):
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
 
@@ -37,10 +46,10 @@ def outcomes(n_fits, n_cols=60, lo=2000, hi=30000, seed=0):
 
 
 @pytest.mark.parametrize("n_fits,n_workgroups", [(1, 0), (5, 0), (20, 0), (5, 7)])
-def test_outcomes_fixed_sweeps_match_oracle(sccs, n_fits, n_workgroups):
+def test_outcomes_fixed_sweeps_match_oracle(sccs, engine, n_fits, n_workgroups):
     probs = outcomes(n_fits)
     with sccs.Batch(probs, [sccs.FitSpec(f, [(sccs.PRIOR_LAPLACE, 2.0)]) for f in range(n_fits)],
-                    n_workgroups=n_workgroups) as b:
+                    n_workgroups=n_workgroups, engine=engine) as b:
         b.run(sccs.CRIT_FIXED, max_sweeps=6)
         for f, p in enumerate(probs):
             beta, res = b.get(f, 0)
@@ -50,24 +59,25 @@ def test_outcomes_fixed_sweeps_match_oracle(sccs, n_fits, n_workgroups):
             assert abs(res["logpost"] - ref["logpost"]) <= 1e-10 * abs(ref["logpost"])
 
 
-def test_sixty_four_fits_and_limit(sccs):
-    """The maximum batch (64 fits over 8 small problems, 8 fits per wave),
-    every fit against the oracle; a 65th fit is rejected."""
+def test_sixty_four_fits_and_limit(sccs, engine):
+    """The maximum batch (64 fits over 8 small problems; two launches of 32
+    fits in the partitioned engine), every fit against the oracle; a 65th
+    fit is rejected."""
     probs = outcomes(8, n_cols=24, lo=500, hi=4000, seed=5)
     specs = [sccs.FitSpec(f % 8, [(sccs.PRIOR_NORMAL, 0.25 * (1 + f // 8))]) for f in range(64)]
-    with sccs.Batch(probs, specs) as b:
+    with sccs.Batch(probs, specs, engine=engine) as b:
         b.run(sccs.CRIT_FIXED, max_sweeps=3)
         for f in range(64):
             ref = oracle.ccd(probs[f % 8], oracle.PRIOR_NORMAL, 0.25 * (1 + f // 8), 3)
             beta, _ = b.get(f)
             assert rel_inf(beta, ref["beta"]) <= FP64_TOL, f
     with pytest.raises(sccs.SccsError):
-        sccs.Batch(probs, specs + [specs[0]])
+        sccs.Batch(probs, specs + [specs[0]], engine=engine)
 
 
-def test_outcomes_to_convergence(sccs):
+def test_outcomes_to_convergence(sccs, engine):
     probs = outcomes(6, seed=3)
-    with sccs.Batch(probs, [sccs.FitSpec(f, [(sccs.PRIOR_NORMAL, 0.5)]) for f in range(6)]) as b:
+    with sccs.Batch(probs, [sccs.FitSpec(f, [(sccs.PRIOR_NORMAL, 0.5)]) for f in range(6)], engine=engine) as b:
         b.run(sccs.CRIT_REL_LOGPOST, max_sweeps=300, tol=1e-10)
         for f, p in enumerate(probs):
             beta, res = b.get(f, 0)
@@ -76,7 +86,7 @@ def test_outcomes_to_convergence(sccs):
             assert rel_inf(beta, ref["beta"]) <= 1e-7
 
 
-def test_cv_folds_with_warm_started_prior_path(sccs):
+def test_cv_folds_with_warm_started_prior_path(sccs, engine):
     """10 folds x a 4-step Laplace variance path (ascending, warm starts).
     Each link runs a fixed number of sweeps so the trajectory is compared
     exactly; the oracle replays the same warm-start chain."""
@@ -85,7 +95,7 @@ def test_cv_folds_with_warm_started_prior_path(sccs):
     grid = [0.01, 0.1, 1.0, 10.0]
     specs = [sccs.FitSpec(0, [(sccs.PRIOR_LAPLACE, v) for v in grid], weight=(folds != k).astype(np.int32))
              for k in range(10)]
-    with sccs.Batch([prob], specs) as b:
+    with sccs.Batch([prob], specs, engine=engine) as b:
         b.run(sccs.CRIT_FIXED, max_sweeps=4)
         for k in range(10):
             w = (folds != k).astype(np.int32)
@@ -101,13 +111,13 @@ def test_cv_folds_with_warm_started_prior_path(sccs):
                 assert abs(b.heldout(k, l) - ho) <= 1e-8 * abs(ho), (k, l)
 
 
-def test_bootstrap_replicates(sccs):
+def test_bootstrap_replicates(sccs, engine):
     """Bootstrap replicates as integer patient multiplicities (Section 2.5);
     the out-of-bag patients (weight 0) form each replicate's held-out set."""
     prob = synth.zipf_problem("boot", 3000, 30, 0.1, seed_path=(9, 3))
     wts = synth.bootstrap_weights(prob.n_patients, 6, seed=4)
     specs = [sccs.FitSpec(0, [(sccs.PRIOR_NORMAL, 0.5)], weight=w) for w in wts]
-    with sccs.Batch([prob], specs) as b:
+    with sccs.Batch([prob], specs, engine=engine) as b:
         b.run(sccs.CRIT_FIXED, max_sweeps=5)
         for r, w in enumerate(wts):
             ref = oracle.ccd(prob, oracle.PRIOR_NORMAL, 0.5, 5, weight=w)
@@ -119,7 +129,7 @@ def test_bootstrap_replicates(sccs):
 
 
 @pytest.mark.parametrize("n_reps,max_group", [(20, 0), (20, 1), (6, 2)])
-def test_bootstrap_column_groups(sccs, n_reps, max_group):
+def test_bootstrap_column_groups(sccs, engine, n_reps, max_group):
     """Replicates of one problem share its column groups: 20 replicates give
     groups of up to 3 columns (2 F m <= 128 words), 6 replicates up to the
     requested width; every replicate against the oracle, and the grouped run
@@ -127,10 +137,10 @@ def test_bootstrap_column_groups(sccs, n_reps, max_group):
     prob = synth.zipf_problem("bootg", 4000, 40, 0.03, seed_path=(9, 5))
     wts = synth.bootstrap_weights(prob.n_patients, n_reps, seed=6)
     specs = [sccs.FitSpec(0, [(sccs.PRIOR_LAPLACE, 2.0)], weight=w) for w in wts]
-    with sccs.Batch([prob], specs, max_group=max_group) as b:
+    with sccs.Batch([prob], specs, max_group=max_group, engine=engine) as b:
         b.run(sccs.CRIT_FIXED, max_sweeps=6)
         got = [b.get(r)[0] for r in range(n_reps)]
-    with sccs.Batch([prob], specs, max_group=1) as b:
+    with sccs.Batch([prob], specs, max_group=1, engine=engine) as b:
         b.run(sccs.CRIT_FIXED, max_sweeps=6)
         plain = [b.get(r)[0] for r in range(n_reps)]
     for r in range(n_reps):
@@ -141,10 +151,10 @@ def test_bootstrap_column_groups(sccs, n_reps, max_group):
         assert np.array_equal(got[r] == 0.0, ref["beta"] == 0.0)
 
 
-def test_batch_mixed_precision(sccs):
+def test_batch_mixed_precision(sccs, engine):
     probs = outcomes(4, seed=5)
     with sccs.Batch(probs, [sccs.FitSpec(f, [(sccs.PRIOR_LAPLACE, 2.0)]) for f in range(4)],
-                    precision=sccs.PREC_MIXED) as b:
+                    precision=sccs.PREC_MIXED, engine=engine) as b:
         b.run(sccs.CRIT_FIXED, max_sweeps=10)
         for f, p in enumerate(probs):
             beta, _ = b.get(f, 0)
@@ -152,26 +162,41 @@ def test_batch_mixed_precision(sccs):
             assert rel_inf(beta, ref["beta"]) <= 1e-6
 
 
-def test_batch_rejects_bad_specs(sccs):
+def test_batch_rejects_bad_specs(sccs, engine):
     probs = outcomes(2)
     with pytest.raises(sccs.SccsError):
-        sccs.Batch(probs, [sccs.FitSpec(5, [(sccs.PRIOR_NORMAL, 1.0)])])
+        sccs.Batch(probs, [sccs.FitSpec(5, [(sccs.PRIOR_NORMAL, 1.0)])], engine=engine)
     with pytest.raises(sccs.SccsError):
-        sccs.Batch(probs, [sccs.FitSpec(0, [(sccs.PRIOR_NORMAL, -1.0)])])
+        sccs.Batch(probs, [sccs.FitSpec(0, [(sccs.PRIOR_NORMAL, -1.0)])], engine=engine)
     other = synth.tiny(n_cols=7)
     with pytest.raises(sccs.SccsError):
-        sccs.Batch([probs[0], other], [sccs.FitSpec(0, [(sccs.PRIOR_NORMAL, 1.0)])])
+        sccs.Batch([probs[0], other], [sccs.FitSpec(0, [(sccs.PRIOR_NORMAL, 1.0)])], engine=engine)
 
 
-def test_heldout_needs_weights_and_a_run(sccs):
+def test_heldout_needs_weights_and_a_run(sccs, engine):
     """No weights: no held-out set.  Weights without a 0: empty set, L = 0."""
     prob = synth.tiny()
     ones = np.ones(prob.n_patients, dtype=np.int32)
     specs = [sccs.FitSpec(0, [(sccs.PRIOR_NORMAL, 1.0)]), sccs.FitSpec(0, [(sccs.PRIOR_NORMAL, 1.0)], weight=ones)]
-    with sccs.Batch([prob], specs) as b:
+    with sccs.Batch([prob], specs, engine=engine) as b:
         with pytest.raises(sccs.SccsError):
             b.heldout(1, 0)            # link has not run
         b.run(sccs.CRIT_FIXED, max_sweeps=2)
         with pytest.raises(sccs.SccsError):
             b.heldout(0, 0)            # no weights
         assert b.heldout(1, 0) == 0.0
+
+
+def test_batch_autotuner_picks_a_candidate_and_its_schedule_is_exact(sccs, engine):
+    """sccs_batch_tune times launch shapes on the batch itself; the batch
+    run with the chosen shape still matches the oracle fit by fit."""
+    probs = outcomes(6, n_cols=40, lo=3000, hi=20000, seed=3)
+    specs = [sccs.FitSpec(f, [(sccs.PRIOR_LAPLACE, 2.0)]) for f in range(len(probs))]
+    best, table = sccs.batch_tune(probs, specs, n_sweeps=2, engine=engine)
+    assert len(table) >= 6 and all(t["ms_per_sweep"] > 0 for t in table)
+    assert any(t["n_workgroups"] == best["n_workgroups"] and t["tile_nnz"] == best["tile_nnz"] for t in table)
+    with sccs.Batch(probs, specs, n_workgroups=best["n_workgroups"], tile_nnz=best["tile_nnz"], engine=engine) as b:
+        b.run(sccs.CRIT_FIXED, max_sweeps=5)
+        for f, p in enumerate(probs):
+            beta, _ = b.get(f, 0)
+            assert rel_inf(beta, oracle.ccd(p, oracle.PRIOR_LAPLACE, 2.0, 5)["beta"]) <= FP64_TOL

@@ -28,6 +28,13 @@ def sccs():
     return s
 
 
+@pytest.fixture(params=[0, 1], ids=["partitioned", "lockstep"])
+def engine(request):
+    """Engine of the batched form underneath: fits on disjoint workgroup
+    ranges (0) or all fits in lockstep (1)."""
+    return request.param
+
+
 def _check(sccs, got, ref, tol):
     scale = max(float(np.max(np.abs(ref["beta"]))), 1e-300)
     err = float(np.max(np.abs(got["beta"] - ref["beta"]))) / scale
@@ -40,35 +47,37 @@ def _check(sccs, got, ref, tol):
 
 
 @pytest.mark.parametrize("kind,var", [(2, 0.05), (1, 1.0)])
-def test_bootstrap_fixed_sweeps(sccs, kind, var):
+def test_bootstrap_fixed_sweeps(sccs, engine, kind, var):
     prob = synth.tiny(n_patients=1500, n_cols=20, seed=5)
     W = synth.bootstrap_weights(prob.n_patients, 70, seed=1)
     ref = oracle.bootstrap(prob, kind, var, W, 15)
-    got = sccs.bootstrap(prob, kind, var, W, criterion=sccs.CRIT_FIXED, max_sweeps=15)
+    got = sccs.bootstrap(prob, kind, var, W, criterion=sccs.CRIT_FIXED, max_sweeps=15, engine=engine)
     assert (got["sweeps"] == 15).all()
     if kind == 2:
         assert 0.0 < ref["p_hat"].min() < 1.0 or 0.0 < ref["p_hat"].max() < 1.0   # some coefficients drop out
     _check(sccs, got, ref, 1e-9)
 
 
-def test_bootstrap_to_convergence(sccs):
+def test_bootstrap_to_convergence(sccs, engine):
     """REL_LOGPOST per replicate: the GPU runs each replicate for the oracle's
     sweep count (both stop at the first sweep whose relative change falls
     below the tolerance)."""
     prob = synth.tiny(n_patients=1500, n_cols=20, seed=5)
     W = synth.bootstrap_weights(prob.n_patients, 9, seed=4)
     ref = oracle.bootstrap(prob, 2, 0.05, W, 200, oracle.CRIT_REL_LOGPOST, 1e-10)
-    got = sccs.bootstrap(prob, 2, 0.05, W, criterion=sccs.CRIT_REL_LOGPOST, max_sweeps=200, tol=1e-10)
+    got = sccs.bootstrap(prob, 2, 0.05, W, criterion=sccs.CRIT_REL_LOGPOST, max_sweeps=200, tol=1e-10,
+                         engine=engine)
     assert got["converged"].all()
     assert np.array_equal(got["sweeps"], ref["sweeps"])
     _check(sccs, got, ref, 1e-9)
 
 
-def test_bootstrap_mixed_precision(sccs):
+def test_bootstrap_mixed_precision(sccs, engine):
     prob = synth.tiny(n_patients=1500, n_cols=20, seed=5)
     W = synth.bootstrap_weights(prob.n_patients, 12, seed=6)
     ref = oracle.bootstrap(prob, 1, 1.0, W, 15)
-    got = sccs.bootstrap(prob, 1, 1.0, W, criterion=sccs.CRIT_FIXED, max_sweeps=15, precision=1)
+    got = sccs.bootstrap(prob, 1, 1.0, W, criterion=sccs.CRIT_FIXED, max_sweeps=15, precision=1,
+                         engine=engine)
     scale = float(np.max(np.abs(ref["beta"])))
     err = float(np.max(np.abs(got["beta"] - ref["beta"]))) / scale
     print(f"mixed: max rel beta error {err:.2e}")

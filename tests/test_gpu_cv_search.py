@@ -26,13 +26,20 @@ def sccs():
     return s
 
 
+@pytest.fixture(params=[0, 1], ids=["partitioned", "lockstep"])
+def engine(request):
+    """Engine of the batched form underneath: fits on disjoint workgroup
+    ranges (0) or all fits in lockstep (1)."""
+    return request.param
+
+
 @pytest.mark.parametrize("kind,var_start,warm", [(2, 1e-2, True), (1, 10.0, True), (2, 1e-2, False)])
-def test_cv_search_matches_oracle(sccs, kind, var_start, warm):
+def test_cv_search_matches_oracle(sccs, engine, kind, var_start, warm):
     prob = synth.zipf_problem("zipf_small", 4000, 40, 0.1, seed_path=(8, 3))
     folds = synth.cv_folds(prob.n_patients, 5, seed=1)
     kw = dict(var_start=var_start, bracket_step=10.0, log10_tol=0.1, max_evals=20, warm_start=warm)
     ref = oracle.cv_search(prob, folds, 5, kind, max_sweeps=300, tol=1e-11, **kw)
-    got = sccs.cv_search(prob, folds, 5, kind, max_sweeps=300, tol=1e-11, **kw)
+    got = sccs.cv_search(prob, folds, 5, kind, max_sweeps=300, tol=1e-11, engine=engine, **kw)
     print("variances", got["variance"], "best", got["best"], "bracketed", got["bracketed"])
     assert len(got["variance"]) == len(ref["variance"])
     assert np.allclose(got["variance"], ref["variance"], rtol=1e-12, atol=0)
