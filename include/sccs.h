@@ -66,6 +66,7 @@ typedef int32_t sccs_status;
 enum { SCCS_PRIOR_NONE = 0, SCCS_PRIOR_NORMAL = 1, SCCS_PRIOR_LAPLACE = 2, SCCS_PRIOR_GROUPED = 3 };
 enum { SCCS_PREC_FP64 = 0, SCCS_PREC_MIXED = 1 };
 enum { SCCS_CRIT_FIXED = 0, SCCS_CRIT_REL_LOGPOST = 1, SCCS_CRIT_ABS_DXBETA = 2 };
+enum { SCCS_ORDER_GIVEN = 0, SCCS_ORDER_INDEPENDENT = 1 };
 
 typedef struct sccs_handle sccs_handle;
 
@@ -136,6 +137,15 @@ typedef struct sccs_options {
                               proportion to nonzeros; one launch per prior link and per 32 fits.
                               1 = lockstep: all fits on all workgroups in one launch, one
                               device-wide reduction per coordinate (or column group) for all */
+  int32_t column_order;    /* order in which a sweep visits the coordinates (Algorithm 1 cycles
+                              over the drugs in a fixed order; how the drugs are numbered is
+                              free).  SCCS_ORDER_GIVEN (default): the problem's column order.
+                              SCCS_ORDER_INDEPENDENT: the order of sccs_column_order with width
+                              max_group, under which consecutive columns share no patient far
+                              more often, so that more of them share a device-wide reduction.
+                              Betas, trust bounds, class_of and grad_hess's j stay in the
+                              problem's numbering at the ABI.  The lockstep batched engine
+                              takes SCCS_ORDER_GIVEN only. */
 } sccs_options;
 
 typedef struct sccs_fit_opts {
@@ -260,7 +270,9 @@ sccs_status sccs_pass_stats(sccs_handle* h, int32_t* passes, int32_t* rejects, i
  * that did not use merged passes; binary covariates), t_us[g] is the time
  * from the start of that launch's last sweep to the moment column group g's
  * steps were taken, in microseconds of the device wall clock, for the
- * n_groups groups; group g holds columns [first_col[g], first_col[g+1]).
+ * n_groups groups; group g holds the columns visited at positions
+ * [first_col[g], first_col[g+1]) of the sweep (sccs_get_column_order maps
+ * positions to columns).
  * t_us: [max_groups]; first_col: [max_groups + 1].  SCCS_ERR_STATE if no
  * such launch preceded; SCCS_ERR_INVALID_ARG if max_groups < n_groups
  * (n_groups is still written).  Synchronises. */
@@ -283,6 +295,20 @@ typedef struct sccs_tune_result {
 
 sccs_status sccs_tune(const sccs_problem* prob, const sccs_options* base, int32_t prior_kind, double variance,
                       int32_t n_sweeps, sccs_options* best, sccs_tune_result* result);
+
+/* The independence relabelling of a problem's columns (host only, no GPU
+ * needed): columns are visited in decreasing order of nonzeros (ties:
+ * smaller index first); each joins the first group, in creation order, that
+ * has fewer than width columns (1..4) and shares no patient with it, or opens
+ * a new group at the end.  order[k] ([n_cols], caller-owned) is the column
+ * visited k-th: the groups in creation order, each group's columns in the
+ * order they joined.  SCCS_ERR_INVALID_ARG for a malformed problem or
+ * width outside [1, 4]; sccs_last_error(NULL) describes it. */
+sccs_status sccs_column_order(const sccs_problem* prob, int32_t width, int32_t* order);
+
+/* The order in which h's sweeps visit the columns (order[k], k < n_cols):
+ * the identity under SCCS_ORDER_GIVEN. */
+sccs_status sccs_get_column_order(sccs_handle* h, int32_t* order);
 
 /* Human-readable description of the last error on this handle (or of the
  * last failed create when h is NULL).  Never NULL. */

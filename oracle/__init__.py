@@ -333,3 +333,48 @@ def ccd_grouped(prob, var: float, class_of, class_var: float, max_sweeps: int, c
     return {"beta": beta, "trust": trust, "sweeps": n, "converged": bool(res.converged),
             "loglik": res.loglik, "logpost": res.logpost,
             "trace": None if trace is None else trace[:n], "logpost_trace": lpt[:n]}
+
+
+def independent_groups(prob, width: int = 4):
+    """Column groups of the independence relabelling, as lists of columns.
+
+    Coordinate descent visits the coordinates in a fixed cyclic order
+    (Algorithm 1); the numbering of the drugs is the caller's.  This
+    numbering is built greedily: columns are taken by decreasing number of
+    nonzeros (ties: smaller index first) and each joins the earliest-opened
+    group that still has fewer than `width` columns and shares no patient
+    with any of them; if there is none it opens a new group.  Reading the
+    groups in the order they were opened, each in joining order, gives the
+    relabelling (independent_order).  Plain restatement for the tests: per
+    patient, the groups holding one of its columns are kept in a table."""
+    N, J = int(prob.n_patients), int(prob.n_cols)
+    patient_of_row = np.repeat(np.arange(N), np.diff(np.asarray(prob.patient_ptr)))
+    col_ptr = np.asarray(prob.col_ptr)
+    pats = [np.unique(patient_of_row[prob.row_idx[col_ptr[j]:col_ptr[j + 1]]]) for j in range(J)]
+    per_patient = np.zeros(N, dtype=np.int64)
+    for p in pats:
+        per_patient[p] += 1
+    table = np.full((N, max(1, int(per_patient.max(initial=0)))), -1, dtype=np.int64)
+    used = np.zeros(N, dtype=np.int64)
+    sizes = np.diff(col_ptr)
+    groups = []
+    for j in sorted(range(J), key=lambda c: (-int(sizes[c]), c)):
+        p = pats[j]
+        taken = set(np.unique(table[p]).tolist()) if len(p) else set()
+        home = None
+        for g, members in enumerate(groups):
+            if len(members) < width and g not in taken:
+                home = g
+                break
+        if home is None:
+            home = len(groups)
+            groups.append([])
+        groups[home].append(j)
+        table[p, used[p]] = home
+        used[p] += 1
+    return groups
+
+
+def independent_order(prob, width: int = 4) -> np.ndarray:
+    """The relabelling: order[k] is the column visited k-th."""
+    return np.array([j for g in independent_groups(prob, width) for j in g], dtype=np.int64)

@@ -54,6 +54,9 @@ struct sccs_handle {
   bool last_merged = false;        // the last sweep launch used the merged-pass form
   int32_t n_classes = 0;           // grouped prior: classes (their sums take n_classes doubles of LDS)
   double class_var = 0.0;
+  std::vector<int32_t> perm;       // perm[k]: the column visited k-th (empty: the given order)
+  // the internal position of each column (inverse of perm); set with perm
+  std::vector<int32_t> pos;
 };
 
 static thread_local std::string g_create_error;
@@ -149,6 +152,10 @@ sccs_status check_options(const sccs_options* o, std::string& err) {
   }
   if (o->merge_passes != 0 && o->merge_passes != 1) {
     err = "options.merge_passes must be 0 or 1";
+    return SCCS_ERR_INVALID_ARG;
+  }
+  if (o->column_order != SCCS_ORDER_GIVEN && o->column_order != SCCS_ORDER_INDEPENDENT) {
+    err = "options.column_order must be SCCS_ORDER_GIVEN or SCCS_ORDER_INDEPENDENT";
     return SCCS_ERR_INVALID_ARG;
   }
   if (o->batch_engine != 0 && o->batch_engine != 1) {
@@ -270,7 +277,7 @@ sccs_status launch(sccs_handle* h, int mode, int n_sweeps, int criterion, double
   void* params[] = {&a};
   HIPCHK(h, hipMemsetAsync(&h->args.ctrl->status, 0, sizeof(int32_t), h->stream));
   HIPCHK(h, hipEventRecord(h->ev0, h->stream));
-  const bool merge = a.merge && h->use_merge && !h->valued && a.prior_kind != SCCS_PRIOR_GROUPED;
+  const bool merge = a.merge && h->use_merge && !h->valued && a.prior_kind != SCCS_PRIOR_GROUPED && h->perm.empty();
   if (mode == kModeSweep) {   // the mirror holds the state after the previous launch
     for (int c = 0; c < kSlotClasses; ++c) h->gseq0[c] = h->h_ctrl->gseq[c];
     h->last_merged = merge;
@@ -398,6 +405,7 @@ void sccs_default_options(sccs_options* o) {
   o->merge_passes = 1;
   o->stream = nullptr;
   o->batch_engine = 0;
+  o->column_order = SCCS_ORDER_GIVEN;
 }
 
 sccs_status sccs_query_workspace(const sccs_problem* prob, const sccs_options* opts, size_t* bytes) {
@@ -438,6 +446,22 @@ sccs_status sccs_create(const sccs_problem* prob, const sccs_options* opts_in, v
 
   sccs_handle* h = new (std::nothrow) sccs_handle();
   if (!h) { g_create_error = "out of host memory"; return SCCS_ERR_INVALID_ARG; }
+  // relabelled columns: the handle works on a copy of the problem with its
+  // columns in sweep order, and maps column indices at the ABI
+  PermutedProblem pp;
+  if (opts.column_order == SCCS_ORDER_INDEPENDENT) {
+    try {
+      independent_order(prob, opts.max_group ? opts.max_group : kMaxGroup, h->perm);
+      permute_columns(prob, h->perm, pp);
+    } catch (const std::bad_alloc&) {
+      delete h;
+      g_create_error = "host out of memory while relabelling the columns";
+      return SCCS_ERR_INVALID_ARG;
+    }
+    h->pos.assign(h->perm.size(), 0);
+    for (size_t k = 0; k < h->perm.size(); ++k) h->pos[h->perm[k]] = (int32_t)k;
+    prob = &pp.p;
+  }
   Layout L;
   const int32_t tile_nnz = opts.tile_nnz ? opts.tile_nnz : kTile;
   const int32_t max_group = opts.max_group ? opts.max_group : kMaxGroup;
@@ -635,7 +659,10 @@ sccs_status sccs_set_prior_grouped(sccs_handle* h, double variance, double class
   }
   std::vector<double> kappa((size_t)n_classes);
   for (int32_t c = 0; c < n_classes; ++c) kappa[c] = class_variance / (variance + (double)members[c] * class_variance);
-  HIPCHK(h, hipMemcpyAsync((void*)h->args.pclass, class_of, (size_t)h->J * 4, hipMemcpyHostToDevice, h->stream));
+  std::vector<int32_t> cls(class_of, class_of + h->J);
+  if (!h->perm.empty())
+    for (int32_t k = 0; k < h->J; ++k) cls[k] = class_of[h->perm[k]];
+  HIPCHK(h, hipMemcpyAsync((void*)h->args.pclass, cls.data(), (size_t)h->J * 4, hipMemcpyHostToDevice, h->stream));
   HIPCHK(h, hipMemcpyAsync((void*)h->args.pkappa, kappa.data(), (size_t)n_classes * 8, hipMemcpyHostToDevice, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   h->prior_kind = SCCS_PRIOR_GROUPED;
@@ -655,10 +682,15 @@ sccs_status sccs_set_beta(sccs_handle* h, const double* beta, const double* trus
       return SCCS_ERR_INVALID_ARG;
     }
   }
-  std::vector<double> ones;
-  if (!trust) { ones.assign((size_t)h->J, 1.0); trust = ones.data(); }
-  HIPCHK(h, hipMemcpyAsync(h->args.beta, beta, (size_t)h->J * 8, hipMemcpyHostToDevice, h->stream));
-  HIPCHK(h, hipMemcpyAsync(h->args.trust, trust, (size_t)h->J * 8, hipMemcpyHostToDevice, h->stream));
+  std::vector<double> b(beta, beta + h->J), t((size_t)h->J, 1.0);
+  if (trust) t.assign(trust, trust + h->J);
+  if (!h->perm.empty())
+    for (int32_t k = 0; k < h->J; ++k) {
+      b[k] = beta[h->perm[k]];
+      t[k] = trust ? trust[h->perm[k]] : 1.0;
+    }
+  HIPCHK(h, hipMemcpyAsync(h->args.beta, b.data(), (size_t)h->J * 8, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync(h->args.trust, t.data(), (size_t)h->J * 8, hipMemcpyHostToDevice, h->stream));
   if (refresh_all(h) != SCCS_OK) return SCCS_ERR_HIP;
   h->use_merge = false;
   st = reset_moved(h);
@@ -671,9 +703,15 @@ sccs_status sccs_get_beta(sccs_handle* h, double* beta, double* trust) {
   sccs_status st = usable(h);
   if (st) return st;
   if (!beta) { h->err = "beta is NULL"; return SCCS_ERR_INVALID_ARG; }
-  HIPCHK(h, hipMemcpyAsync(beta, h->args.beta, (size_t)h->J * 8, hipMemcpyDeviceToHost, h->stream));
-  if (trust) HIPCHK(h, hipMemcpyAsync(trust, h->args.trust, (size_t)h->J * 8, hipMemcpyDeviceToHost, h->stream));
+  std::vector<double> b((size_t)h->J), t(trust ? (size_t)h->J : 0);
+  HIPCHK(h, hipMemcpyAsync(b.data(), h->args.beta, (size_t)h->J * 8, hipMemcpyDeviceToHost, h->stream));
+  if (trust) HIPCHK(h, hipMemcpyAsync(t.data(), h->args.trust, (size_t)h->J * 8, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
+  for (int32_t k = 0; k < h->J; ++k) {
+    const int32_t j = h->perm.empty() ? k : h->perm[k];
+    beta[j] = b[k];
+    if (trust) trust[j] = t[k];
+  }
   return SCCS_OK;
 }
 
@@ -732,7 +770,7 @@ sccs_status sccs_sweep_static(sccs_handle* h, int32_t n_sweeps, double* logpost)
                      (const Ctrl*)h->args.ctrl);
   HIPCHK(h, hipGetLastError());
   void* params[] = {&a};
-  const bool merge = a.merge && h->use_merge && !h->valued && a.prior_kind != SCCS_PRIOR_GROUPED;
+  const bool merge = a.merge && h->use_merge && !h->valued && a.prior_kind != SCCS_PRIOR_GROUPED && h->perm.empty();
   HIPCHK(h, hipEventRecord(h->ev0, h->stream));
   HIPCHK(h, hipLaunchCooperativeKernel(ccd_kernel(h->prec, kModeSweep, merge, h->valued), dim3(h->G), dim3(kBlock), params,
                                         (unsigned)launch_lds(h, a.prior_kind), h->stream));
@@ -794,7 +832,7 @@ sccs_status sccs_grad_hess(sccs_handle* h, int32_t j, double* g, double* hess) {
   sccs_status st = usable(h);
   if (st) return st;
   if (j < 0 || j >= h->J || !g || !hess) { h->err = "invalid column or NULL output"; return SCCS_ERR_INVALID_ARG; }
-  st = launch(h, kModeGradHess, 0, SCCS_CRIT_FIXED, 0.0, 0, j);
+  st = launch(h, kModeGradHess, 0, SCCS_CRIT_FIXED, 0.0, 0, h->pos.empty() ? j : h->pos[j]);
   if (st) return st;
   st = read_ctrl(h);
   if (st) return st;
@@ -911,6 +949,29 @@ sccs_status sccs_tune(const sccs_problem* prob, const sccs_options* base, int32_
   *best = o;
   best->n_workgroups = result->n_workgroups[result->best];
   best->tile_nnz = result->tile_nnz[result->best];
+  return SCCS_OK;
+}
+
+sccs_status sccs_column_order(const sccs_problem* prob, int32_t width, int32_t* order) {
+  std::string err;
+  if (!order) { g_create_error = "order is NULL"; return SCCS_ERR_INVALID_ARG; }
+  if (width < 1 || width > kMaxGroup) { g_create_error = "width must be in [1, 4]"; return SCCS_ERR_INVALID_ARG; }
+  sccs_status st = validate_problem(prob, err);
+  if (st) { g_create_error = err; return st; }
+  std::vector<int32_t> o;
+  try {
+    independent_order(prob, width, o);
+  } catch (const std::bad_alloc&) {
+    g_create_error = "host out of memory";
+    return SCCS_ERR_INVALID_ARG;
+  }
+  std::copy(o.begin(), o.end(), order);
+  return SCCS_OK;
+}
+
+sccs_status sccs_get_column_order(sccs_handle* h, int32_t* order) {
+  if (!h || !order) return SCCS_ERR_INVALID_ARG;
+  for (int32_t k = 0; k < h->J; ++k) order[k] = h->perm.empty() ? k : h->perm[k];
   return SCCS_OK;
 }
 

@@ -570,109 +570,15 @@ __device__ __forceinline__ void tile_b(const KArgs& a, int t, Coef cf) {
 }
 
 // ---- tiles t, t + stride, ... < t1 of one range, in order
-//
-// kTileBatch tiles at a time: their bounds, index words, weight and patient
-// gathers are all issued before any is used, so that a wave keeps that many
-// tiles' loads in flight (a column with many tiles per workgroup is bound by
-// memory latency otherwise).  Each tile's terms are still added in tile
-// order, so every sum is the one of one tile at a time, bit for bit.  Within
-// a group, and within a pass, no two tiles of an update touch the same era
-// or patient, so loading before storing changes nothing in phase B either.
-// (The one-pass form uses kTileBatch = 4; the merged-pass form and the
-// batched kernel keep one tile at a time, B = 1: their registers are taken.)
-template <typename WT, int NC, bool kMark, int kTileBatch = 1>
+
+template <typename WT, int NC, bool kMark>
 __device__ __forceinline__ void tiles_a(const KArgs& a, int t, int t1, int stride, Acc<NC>& acc,
                                         unsigned* bits = nullptr, int p0 = 0, uint32_t coff = 0) {
-  const int lane = threadIdx.x & 63;
-  const WT* __restrict__ w = (const WT*)a.w;
-  for (; kTileBatch > 1 && t + (kTileBatch - 1) * stride < t1; t += kTileBatch * stride) {
-    int e0[kTileBatch], len[kTileBatch];
-#pragma unroll
-    for (int k = 0; k < kTileBatch; ++k) {
-      e0[k] = ld_idx(a.tile_start + t + k * stride);
-      len[k] = ld_idx(a.tile_start + t + k * stride + 1) - e0[k];
-    }
-    uint2 rp[kTileBatch];
-#pragma unroll
-    for (int k = 0; k < kTileBatch; ++k)
-      rp[k] = (len[k] <= 64 && lane < len[k]) ? a.rp[e0[k] + lane] : make_uint2(0u, 0xffffffffu);
-    double wv[kTileBatch];
-    double2 pv[kTileBatch];
-    bool lead[kTileBatch];
-    int ss[kTileBatch];
-#pragma unroll
-    for (int k = 0; k < kTileBatch; ++k) {
-      lead[k] = false;
-      ss[k] = lane;
-      wv[k] = 0.0;
-      pv[k] = make_double2(1.0, 0.0);
-      if (len[k] <= 64) {
-        seg_layout(rp[k].y, lane, len[k], lead[k], ss[k]);
-        if (lane < len[k]) wv[k] = (double)w[rp[k].x];
-        if (lead[k]) pv[k] = a.pat[pid_of(rp[k].y)];
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < kTileBatch; ++k) {
-      if (len[k] <= 64) {
-        const double num = seg_sum_v(wv[k], lane, ss[k]);
-        if (lead[k]) {
-          acc.add(col_of(rp[k].y) + coff, num, pv[k]);
-          if (kMark) atomicOr(&bits[(pid_of(rp[k].y) - p0) >> 5], 1u << ((pid_of(rp[k].y) - p0) & 31));
-        }
-      } else {
-        tile_a<WT, NC, kMark>(a, t + k * stride, acc, bits, p0, coff);
-      }
-    }
-  }
   for (; t < t1; t += stride) tile_a<WT, NC, kMark>(a, t, acc, bits, p0, coff);
 }
 
-template <typename WT, int kTileBatch = 1>
+template <typename WT>
 __device__ __forceinline__ void tiles_b(const KArgs& a, int t, int t1, int stride, Coef cf) {
-  const int lane = threadIdx.x & 63;
-  WT* __restrict__ w = (WT*)a.w;
-  for (; kTileBatch > 1 && t + (kTileBatch - 1) * stride < t1; t += kTileBatch * stride) {
-    int e0[kTileBatch], len[kTileBatch];
-#pragma unroll
-    for (int k = 0; k < kTileBatch; ++k) {
-      e0[k] = ld_idx(a.tile_start + t + k * stride);
-      len[k] = ld_idx(a.tile_start + t + k * stride + 1) - e0[k];
-    }
-    uint2 rp[kTileBatch];
-#pragma unroll
-    for (int k = 0; k < kTileBatch; ++k)
-      rp[k] = (len[k] <= 64 && lane < len[k]) ? a.rp[e0[k] + lane] : make_uint2(0u, 0xffffffffu);
-    WT wo[kTileBatch];
-    double ed[kTileBatch], em1[kTileBatch];
-    bool upd[kTileBatch];
-#pragma unroll
-    for (int k = 0; k < kTileBatch; ++k) {
-      const bool act = len[k] <= 64 && lane < len[k];
-      const uint32_t c = act ? col_of(rp[k].y) : 0u;
-      ed[k] = cf.ed[c];
-      em1[k] = cf.em1[c];
-      upd[k] = act && em1[k] != 0.0;
-      wo[k] = upd[k] ? w[rp[k].x] : (WT)0;
-    }
-#pragma unroll
-    for (int k = 0; k < kTileBatch; ++k) {
-      if (len[k] <= 64) {
-        const WT wn = wo[k] * (WT)ed[k];
-        if (upd[k]) w[rp[k].x] = wn;
-        bool lead;
-        if (sizeof(WT) == 8) {
-          const double s = seg_sum((double)wo[k], rp[k].y, lane, len[k], lead);
-          if (lead && upd[k]) a.pat[pid_of(rp[k].y)].x += s * em1[k];
-        } else {
-          const double s = seg_sum((double)wn - (double)wo[k], rp[k].y, lane, len[k], lead);
-          if (lead && upd[k]) a.pat[pid_of(rp[k].y)].x += s;
-        }
-      } else {
-        tile_b<WT>(a, t + k * stride, cf);
-      }
-    }
-  }
   for (; t < t1; t += stride) tile_b<WT>(a, t, cf);
 }
 
@@ -809,7 +715,7 @@ __device__ __forceinline__ bool first_tile_stale(const Pf& p, const unsigned* bi
 
 // Phase A of the current group for one worker wave: the cached first tile
 // (validated by the caller) plus its remaining tiles.
-template <typename WT, int NC, int B = 1>
+template <typename WT, int NC>
 __device__ __forceinline__ void phase_a_cached(const KArgs& a, const Pf& p, const Cache& c, Acc<NC>& acc,
                                                unsigned* bits, int p0, uint32_t coff) {
   if (p.t < p.t1) {
@@ -822,10 +728,10 @@ __device__ __forceinline__ void phase_a_cached(const KArgs& a, const Pf& p, cons
       tile_a<WT, NC, true>(a, p.t, acc, bits, p0, coff);
     }
   }
-  tiles_a<WT, NC, true, B>(a, p.t + kWorkers, p.t1, kWorkers, acc, bits, p0, coff);
+  tiles_a<WT, NC, true>(a, p.t + kWorkers, p.t1, kWorkers, acc, bits, p0, coff);
 }
 
-template <typename WT, int B = 1>
+template <typename WT>
 __device__ __forceinline__ void phase_b_cached(const KArgs& a, const Pf& p, const Cache& c, Coef cf) {
   const int lane = threadIdx.x & 63;
   WT* __restrict__ w = (WT*)a.w;
@@ -851,7 +757,7 @@ __device__ __forceinline__ void phase_b_cached(const KArgs& a, const Pf& p, cons
       tile_b<WT>(a, p.t, cf);
     }
   }
-  tiles_b<WT, B>(a, p.t + kWorkers, p.t1, kWorkers, cf);
+  tiles_b<WT>(a, p.t + kWorkers, p.t1, kWorkers, cf);
 }
 
 // ---- passes
@@ -1437,7 +1343,7 @@ __device__ __forceinline__ void ccd_body(const KArgs& a) {
           acc.zero();
           if (!c_cur.valid || (g > 0 && prev_moved && first_tile_stale(pf_cur, bits_prev, p0)))
             gather_first<WT>(a, pf_cur, c_cur);
-          phase_a_cached<WT, kMaxGroup, 4>(a, pf_cur, c_cur, acc, bits_cur, p0, 0u);
+          phase_a_cached<WT, kMaxGroup>(a, pf_cur, c_cur, acc, bits_cur, p0, 0u);
           double loc[2 * kMaxGroup], part[2 * kMaxGroup];
 #pragma unroll
           for (int i = 0; i < kMaxGroup; ++i) {
@@ -1466,7 +1372,7 @@ __device__ __forceinline__ void ccd_body(const KArgs& a) {
           if (!bci[0]) { ok = false; break; }
           if (bci[1]) { status = SCCS_ERR_NUMERIC; ok = false; break; }
           prev_moved = __builtin_amdgcn_readfirstlane(bci[2]) != 0;
-          if (prev_moved) phase_b_cached<WT, 4>(a, pf_cur, c_cur, cf);
+          if (prev_moved) phase_b_cached<WT>(a, pf_cur, c_cur, cf);
           __syncthreads();
           pf_cur = pf_next;
           pf_next = pf_next2;

@@ -326,3 +326,96 @@ void host_ytx(const sccs_problem* p, const int32_t* weight, std::vector<double>&
 }
 
 }  // namespace sccs
+
+namespace sccs {
+
+void independent_order(const sccs_problem* p, int32_t width, std::vector<int32_t>& order) {
+  const int32_t N = p->n_patients, J = p->n_cols;
+  if (width < 1) width = 1;
+  std::vector<int32_t> era_pid((size_t)p->n_rows);
+  parallel_ranges(N, [&](int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i)
+      for (int64_t k = p->patient_ptr[i]; k < p->patient_ptr[i + 1]; ++k) era_pid[k] = (int32_t)i;
+  });
+  // distinct patients of each column, and per patient a slot for each
+  // column it appears in (the groups it has joined so far)
+  std::vector<int64_t> pat_ptr((size_t)J + 1, 0);
+  std::vector<int32_t> pats;
+  std::vector<int32_t> n_of((size_t)N, 0);
+  {
+    std::vector<int32_t> seen((size_t)N, -1);
+    for (int32_t j = 0; j < J; ++j) {
+      for (int64_t e = p->col_ptr[j]; e < p->col_ptr[j + 1]; ++e) {
+        const int32_t i = era_pid[p->row_idx[e]];
+        if (seen[i] != j) {
+          seen[i] = j;
+          pats.push_back(i);
+          ++n_of[i];
+        }
+      }
+      pat_ptr[(size_t)j + 1] = (int64_t)pats.size();
+    }
+  }
+  std::vector<int64_t> memb_ptr((size_t)N + 1, 0);
+  for (int32_t i = 0; i < N; ++i) memb_ptr[(size_t)i + 1] = memb_ptr[i] + n_of[i];
+  std::vector<int32_t> memb((size_t)memb_ptr[N]);
+  std::vector<int32_t> filled((size_t)N, 0);
+  // visiting order: decreasing nonzeros, ties by column index
+  std::vector<int32_t> visit((size_t)J);
+  for (int32_t j = 0; j < J; ++j) visit[j] = j;
+  std::stable_sort(visit.begin(), visit.end(), [&](int32_t x, int32_t y) {
+    return p->col_ptr[x + 1] - p->col_ptr[x] > p->col_ptr[y + 1] - p->col_ptr[y];
+  });
+  std::vector<std::vector<int32_t>> groups;
+  std::vector<int32_t> open;        // groups with room, in creation order
+  std::vector<int32_t> clash_mark;  // clash_mark[g] == j: group g shares a patient with column j
+  for (int32_t j : visit) {
+    for (int64_t q = pat_ptr[j]; q < pat_ptr[(size_t)j + 1]; ++q) {
+      const int32_t i = pats[q];
+      for (int64_t m = memb_ptr[i]; m < memb_ptr[i] + filled[i]; ++m) clash_mark[memb[m]] = j;
+    }
+    int32_t g = -1;
+    size_t oi = 0;
+    for (; oi < open.size(); ++oi)
+      if (clash_mark[open[oi]] != j) { g = open[oi]; break; }
+    if (g < 0) {
+      g = (int32_t)groups.size();
+      groups.emplace_back();
+      clash_mark.push_back(-1);
+      open.push_back(g);
+      oi = open.size() - 1;
+    }
+    groups[g].push_back(j);
+    if ((int32_t)groups[g].size() >= width) open.erase(open.begin() + (ptrdiff_t)oi);
+    for (int64_t q = pat_ptr[j]; q < pat_ptr[(size_t)j + 1]; ++q) {
+      const int32_t i = pats[q];
+      memb[memb_ptr[i] + filled[i]++] = g;
+    }
+  }
+  order.clear();
+  order.reserve((size_t)J);
+  for (const auto& gr : groups) order.insert(order.end(), gr.begin(), gr.end());
+}
+
+void permute_columns(const sccs_problem* src, const std::vector<int32_t>& order, PermutedProblem& out) {
+  const int32_t J = src->n_cols;
+  out.col_ptr.assign((size_t)J + 1, 0);
+  for (int32_t k = 0; k < J; ++k)
+    out.col_ptr[(size_t)k + 1] = out.col_ptr[k] + (src->col_ptr[order[k] + 1] - src->col_ptr[order[k]]);
+  out.row_idx.resize((size_t)src->nnz);
+  if (src->value) out.value.resize((size_t)src->nnz);
+  else out.value.clear();
+  parallel_ranges(J, [&](int64_t lo, int64_t hi) {
+    for (int64_t k = lo; k < hi; ++k) {
+      const int64_t s0 = src->col_ptr[order[k]], n = src->col_ptr[order[k] + 1] - s0;
+      std::copy(src->row_idx + s0, src->row_idx + s0 + n, out.row_idx.begin() + out.col_ptr[k]);
+      if (src->value) std::copy(src->value + s0, src->value + s0 + n, out.value.begin() + out.col_ptr[k]);
+    }
+  }, 1 << 30, 64);
+  out.p = *src;
+  out.p.col_ptr = out.col_ptr.data();
+  out.p.row_idx = out.row_idx.data();
+  out.p.value = src->value ? out.value.data() : nullptr;
+}
+
+}  // namespace sccs

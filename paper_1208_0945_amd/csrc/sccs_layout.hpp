@@ -83,6 +83,27 @@ inline void layout_dims(const sccs_problem* p, int32_t G, int32_t tile_nnz, Layo
 // columns.  The problem must have been validated.
 void build_layout(const sccs_problem* p, int32_t G, Layout& L, int32_t tile_nnz = kTile, int32_t max_group = 1);
 
+// Relabelling of the columns for independent coordinates.  Columns are
+// visited in decreasing order of nonzeros (ties: smaller index first); each
+// joins the first group, in creation order, that has fewer than width
+// columns and shares no patient with it, or else opens a new group at the
+// end.  order[k] is the column that takes position k: the groups in creation
+// order, each group's columns in the order they joined.  Algorithm 1 visits
+// coordinates in a fixed cyclic order; which drug is numbered first is the
+// caller's choice, and under this numbering consecutive runs of pairwise
+// patient-disjoint columns (column groups) are long.
+void independent_order(const sccs_problem* p, int32_t width, std::vector<int32_t>& order);
+
+// Copy of a problem with its columns in the order given (column k of the
+// copy is column order[k] of src); row-indexed arrays are shared with src.
+struct PermutedProblem {
+  sccs_problem p{};
+  std::vector<int64_t> col_ptr;
+  std::vector<int32_t> row_idx;
+  std::vector<double> value;
+};
+void permute_columns(const sccs_problem* src, const std::vector<int32_t>& order, PermutedProblem& out);
+
 // Y'X_j with patient weights (NULL = 1), summed on the host in compressed
 // column order; for binary problems the terms are integers, so the sum is
 // exact in any order.

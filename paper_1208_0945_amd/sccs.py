@@ -23,6 +23,7 @@ ERR_INVALID_ARG, ERR_WORKSPACE, ERR_HIP, ERR_STATE, ERR_NUMERIC, ERR_SYNC = -1, 
 PRIOR_NONE, PRIOR_NORMAL, PRIOR_LAPLACE, PRIOR_GROUPED = 0, 1, 2, 3
 PREC_FP64, PREC_MIXED = 0, 1
 CRIT_FIXED, CRIT_REL_LOGPOST, CRIT_ABS_DXBETA = 0, 1, 2
+ORDER_GIVEN, ORDER_INDEPENDENT = 0, 1
 
 EXPORTS = ("sccs_default_options", "sccs_query_workspace", "sccs_create", "sccs_destroy",
            "sccs_set_prior", "sccs_set_beta", "sccs_get_beta", "sccs_sweep", "sccs_fit",
@@ -31,7 +32,7 @@ EXPORTS = ("sccs_default_options", "sccs_query_workspace", "sccs_create", "sccs_
            "sccs_batch_heldout", "sccs_batch_last_kernel_ms", "sccs_batch_destroy", "sccs_batch_last_error", "sccs_tune",
            "sccs_sweep_static", "sccs_bootstrap_query_workspace", "sccs_bootstrap",
            "sccs_cv_query_workspace", "sccs_cv_search", "sccs_set_prior_grouped", "sccs_group_times",
-           "sccs_batch_tune")
+           "sccs_batch_tune", "sccs_column_order", "sccs_get_column_order")
 
 
 class SccsError(RuntimeError):
@@ -53,7 +54,8 @@ class Options_(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("n_workgroups", ctypes.c_int32),
                 ("refresh_period", ctypes.c_int32), ("tile_nnz", ctypes.c_int32),
                 ("max_group", ctypes.c_int32), ("merge_passes", ctypes.c_int32),
-                ("stream", ctypes.c_void_p), ("batch_engine", ctypes.c_int32)]
+                ("stream", ctypes.c_void_p), ("batch_engine", ctypes.c_int32),
+                ("column_order", ctypes.c_int32)]
 
 
 class FitOpts_(ctypes.Structure):
@@ -186,6 +188,8 @@ def lib() -> ctypes.CDLL:
                                               ctypes.POINTER(ctypes.c_size_t)]
         L.sccs_cv_search.argtypes = [ctypes.POINTER(Problem_), ctypes.POINTER(Options_), ctypes.c_void_p,
                                      ctypes.c_size_t, ctypes.POINTER(CvOpts_), ctypes.POINTER(CvResult_)]
+        L.sccs_column_order.argtypes = [ctypes.POINTER(Problem_), ctypes.c_int32, ctypes.c_void_p]
+        L.sccs_get_column_order.argtypes = [H, ctypes.c_void_p]
         for name in EXPORTS:
             if name not in ("sccs_default_options", "sccs_last_error", "sccs_batch_last_error"):
                 getattr(L, name).restype = ctypes.c_int32
@@ -220,7 +224,7 @@ class ProblemArrays:
 
 def options(precision: int = PREC_FP64, n_workgroups: int = 0, refresh_period: int = -1,
             stream: Optional[int] = None, tile_nnz: int = 0, max_group: int = 0,
-            merge_passes: int = 1, batch_engine: int = 0) -> Options_:
+            merge_passes: int = 1, batch_engine: int = 0, column_order: int = 0) -> Options_:
     o = Options_()
     lib().sccs_default_options(ctypes.byref(o))
     o.precision = precision
@@ -231,6 +235,7 @@ def options(precision: int = PREC_FP64, n_workgroups: int = 0, refresh_period: i
     o.merge_passes = merge_passes
     o.stream = stream
     o.batch_engine = batch_engine
+    o.column_order = column_order
     return o
 
 
@@ -250,7 +255,7 @@ class Handle:
 
     def __init__(self, prob, weight=None, precision: int = PREC_FP64, n_workgroups: int = 0,
                  refresh_period: int = -1, stream=None, workspace: str = "torch", tile_nnz: int = 0,
-                 max_group: int = 0, merge_passes: int = 1):
+                 max_group: int = 0, merge_passes: int = 1, column_order: int = ORDER_GIVEN):
         import torch
         self.torch = torch
         if stream is None:
@@ -258,7 +263,7 @@ class Handle:
         self.stream = stream
         P = ProblemArrays(prob, weight)
         o = options(precision, n_workgroups, refresh_period, stream.cuda_stream, tile_nnz, max_group,
-                    merge_passes)
+                    merge_passes, column_order=column_order)
         n = ctypes.c_size_t()
         L = lib()
         st = L.sccs_query_workspace(ctypes.byref(P.s), ctypes.byref(o), ctypes.byref(n))
@@ -291,8 +296,8 @@ class Handle:
             self.h = None
             self.ws = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
             return
         try:
             self.close()
@@ -370,9 +375,15 @@ class Handle:
         self._check(lib().sccs_pass_stats(self.h, ctypes.byref(p), ctypes.byref(r), ctypes.byref(z)))
         return p.value, r.value, z.value
 
+    def column_order(self) -> np.ndarray:
+        """The column each sweep position visits (identity for the given order)."""
+        out = np.zeros(self.J, dtype=np.int32)
+        self._check(lib().sccs_get_column_order(self.h, out.ctypes.data))
+        return out
+
     def group_times(self):
         """(microseconds from the last sweep's start to each column group's
-        step, first column of each group) of the last one-pass launch."""
+        step, first sweep position of each group) of the last one-pass launch."""
         n = ctypes.c_int32()
         cap = self.J
         t = np.zeros(cap)
@@ -380,6 +391,17 @@ class Handle:
         self._check(lib().sccs_group_times(self.h, cap, t.ctypes.data, fc.ctypes.data, ctypes.byref(n)))
         k = n.value
         return t[:k], fc[:k + 1]
+
+
+def column_order(prob, width: int = 4) -> np.ndarray:
+    """sccs_column_order: the independence relabelling of prob's columns
+    (order[k] is the column a sweep visits k-th).  Host only."""
+    P = ProblemArrays(prob)
+    out = np.zeros(P.n_cols, dtype=np.int32)
+    st = lib().sccs_column_order(ctypes.byref(P.s), int(width), out.ctypes.data)
+    if st != OK:
+        raise SccsError(st, lib().sccs_last_error(None).decode())
+    return out
 
 
 def tune(prob, prior_kind: int, variance: float, n_sweeps: int = 2, precision: int = PREC_FP64, weight=None):
@@ -436,7 +458,7 @@ class Batch:
 
     def __init__(self, probs, specs, precision: int = PREC_FP64, n_workgroups: int = 0,
                  refresh_period: int = -1, stream=None, tile_nnz: int = 0, max_group: int = 0,
-                 engine: int = 0):
+                 engine: int = 0, column_order: int = ORDER_GIVEN):
         import torch
         if stream is None:
             stream = torch.cuda.current_stream()
@@ -447,7 +469,7 @@ class Batch:
         sarr = (FitSpec_ * len(self._specs))(*[s.struct() for s in self._specs])
         self._parr, self._sarr = parr, sarr
         o = options(precision, n_workgroups, refresh_period, stream.cuda_stream, tile_nnz, max_group,
-                    batch_engine=engine)
+                    batch_engine=engine, column_order=column_order)
         L = lib()
         n = ctypes.c_size_t()
         st = L.sccs_batch_query_workspace(ctypes.addressof(parr), len(self._probs), ctypes.addressof(sarr),
@@ -497,8 +519,8 @@ class Batch:
             self.h = None
             self.ws = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
             return
         try:
             self.close()
@@ -514,7 +536,7 @@ class Batch:
 
 def bootstrap(prob, prior_kind: int, variance: float, weights, criterion: int = CRIT_REL_LOGPOST,
               max_sweeps: int = 100, tol: float = 1e-8, level: float = 0.95, precision: int = PREC_FP64,
-              n_workgroups: int = 0, stream=None, engine: int = 0) -> dict:
+              n_workgroups: int = 0, stream=None, engine: int = 0, column_order: int = ORDER_GIVEN) -> dict:
     """sccs_bootstrap: one fit per row of weights ([R, N] patient
     multiplicities), percentile intervals and the share of nonzero estimates.
     Returns dict(beta [R, J], lo, hi, p_nonzero, sweeps, converged)."""
@@ -526,7 +548,7 @@ def bootstrap(prob, prior_kind: int, variance: float, weights, criterion: int = 
     P = ProblemArrays(prob)
     if W.ndim != 2 or W.shape[1] != int(prob.n_patients):
         raise ValueError("weights must be [n_replicates, n_patients]")
-    o = options(precision, n_workgroups, -1, stream.cuda_stream, batch_engine=engine)
+    o = options(precision, n_workgroups, -1, stream.cuda_stream, batch_engine=engine, column_order=column_order)
     L = lib()
     n = ctypes.c_size_t()
     st = L.sccs_bootstrap_query_workspace(ctypes.byref(P.s), ctypes.byref(o), R, ctypes.byref(n))
@@ -552,7 +574,8 @@ def bootstrap(prob, prior_kind: int, variance: float, weights, criterion: int = 
 def cv_search(prob, folds, n_folds: int, prior_kind: int, var_start: float = 0.01, bracket_step: float = 10.0,
               log10_tol: float = 0.05, max_evals: int = 30, warm_start: bool = True,
               criterion: int = CRIT_REL_LOGPOST, max_sweeps: int = 100, tol: float = 1e-10,
-              precision: int = PREC_FP64, n_workgroups: int = 0, stream=None, engine: int = 0) -> dict:
+              precision: int = PREC_FP64, n_workgroups: int = 0, stream=None, engine: int = 0,
+              column_order: int = ORDER_GIVEN) -> dict:
     """sccs_cv_search: bracketing and golden-section search of the
     cross-validated predictive log-likelihood over the prior variance.
     Returns dict(variance, pred_loglik [per evaluation], best, bracketed)."""
@@ -561,7 +584,7 @@ def cv_search(prob, folds, n_folds: int, prior_kind: int, var_start: float = 0.0
         stream = torch.cuda.current_stream()
     P = ProblemArrays(prob)
     fold = _arr(folds, np.int32)
-    o = options(precision, n_workgroups, -1, stream.cuda_stream, batch_engine=engine)
+    o = options(precision, n_workgroups, -1, stream.cuda_stream, batch_engine=engine, column_order=column_order)
     L = lib()
     n = ctypes.c_size_t()
     st = L.sccs_cv_query_workspace(ctypes.byref(P.s), ctypes.byref(o), int(n_folds), ctypes.byref(n))

@@ -378,3 +378,19 @@ def subsample_patients(prob: Problem, frac: float, seed: int = 0) -> Problem:
 def random_beta(n_cols: int, scale: float, seed: int) -> np.ndarray:
     """A seeded coefficient vector for evaluating derivatives away from zero."""
     return _rng(7, seed).normal(0.0, scale, size=n_cols)
+
+
+def permute_columns(prob: Problem, order) -> Problem:
+    """The problem with its columns renumbered: column k of the result is
+    column order[k] of prob (values follow their entries); data layout only."""
+    order = np.asarray(order, dtype=np.int64)
+    lens = np.diff(prob.col_ptr)[order]
+    col_ptr = np.zeros(prob.n_cols + 1, dtype=np.int64)
+    np.cumsum(lens, out=col_ptr[1:])
+    src = np.concatenate([np.arange(prob.col_ptr[j], prob.col_ptr[j + 1]) for j in order]) if prob.nnz else \
+        np.zeros(0, dtype=np.int64)
+    return Problem(name=f"{prob.name}_perm", n_patients=prob.n_patients, patient_ptr=prob.patient_ptr,
+                   offset=prob.offset, count=prob.count, n_cols=prob.n_cols, col_ptr=col_ptr,
+                   row_idx=prob.row_idx[src].copy(), beta_true=prob.beta_true[order].copy(),
+                   seed_info=prob.seed_info + " columns permuted",
+                   value=None if prob.value is None else prob.value[src].copy())
