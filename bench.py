@@ -58,10 +58,17 @@ def bytes_per_sweep(c, p, active, precision):
         the read-modify-write of (X beta)_k (16 B), l_k (4 B) and the new w_k
         (8 B); per segment the new den_i (8 B).
     The mixed form stores w in 4 B: 8 c_j + 16 p_j and 24 c_j + 8 p_j."""
+    return phase_a_bytes(c, p, precision) + phase_b_bytes(c, p, active, precision)
+
+
+def phase_a_bytes(c, p, precision):
     wb = 8 if precision == 0 else 4
-    a = (4 + wb) * c.sum() + 16 * p.sum()
-    b = (20 + wb) * c[active].sum() + 8 * p[active].sum()
-    return float(a + b)
+    return float((4 + wb) * c.sum() + 16 * p.sum())
+
+
+def phase_b_bytes(c, p, active, precision):
+    wb = 8 if precision == 0 else 4
+    return float((20 + wb) * c[active].sum() + 8 * p[active].sum())
 
 
 def bytes_per_sweep_library(c, p, active, precision):
@@ -76,12 +83,13 @@ def bytes_per_sweep_library(c, p, active, precision):
     return float(a + b)
 
 
-def run_form(sccs, prob, precision, steps, warmup, c, p, n_workgroups=0, late=0, refresh_period=-1):
+def run_form(sccs, prob, precision, steps, warmup, c, p, n_workgroups=0, late=0, refresh_period=-1, column_order=1):
     """warmup sweeps, then beta reset to 0 (exact state recomputation) and
     `steps` timed sweeps from beta = 0, one launch each; then `late` more
     sweeps timed on their own (the fit continuing toward convergence)."""
     import torch
-    h = sccs.Handle(prob, precision=precision, n_workgroups=n_workgroups, refresh_period=refresh_period)
+    h = sccs.Handle(prob, precision=precision, n_workgroups=n_workgroups, refresh_period=refresh_period,
+                    column_order=column_order)
     h.set_prior(sccs.PRIOR_LAPLACE, 2.0)
     for _ in range(warmup):
         h.sweep(1)
@@ -200,7 +208,7 @@ def copy_calibration(n_bytes: int = 1 << 30, reps: int = 3):
     print(json.dumps({"copy_calibration_bytes_each_way": n_bytes, "reps": reps}), flush=True)
 
 
-def batched_outcomes_bench(sccs, synth, steps, precision, engine=0):
+def batched_outcomes_bench(sccs, synth, steps, precision, engine=0, column_order=1):
     """64 outcomes over one J = 1000 vocabulary, patient counts log-uniform
     10k..2M, Laplace lambda = 1: one launch runs `steps` sweeps of all 64."""
     t0 = time.perf_counter()
@@ -212,7 +220,8 @@ def batched_outcomes_bench(sccs, synth, steps, precision, engine=0):
     specs = [sccs.FitSpec(f, [(sccs.PRIOR_LAPLACE, 2.0)]) for f in range(len(probs))]
     stats = [column_stats(p) for p in probs]
     t0 = time.perf_counter()
-    with sccs.Batch(probs, specs, precision=precision, engine=engine) as b:
+    co = column_order if engine == 0 else 0   # the lockstep engine keeps the given order
+    with sccs.Batch(probs, specs, precision=precision, engine=engine, column_order=co) as b:
         print(f"[bench] batch set up in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
         b.run(sccs.CRIT_FIXED, max_sweeps=1)            # warm-up launch (the chains restart from its beta)
         t0 = time.perf_counter()
@@ -227,11 +236,12 @@ def batched_outcomes_bench(sccs, synth, steps, precision, engine=0):
             "dtype": "f64" if precision == 0 else "mixed",
             "config": {"workload": "64 outcomes, J=1000 Zipf(1.1), N log-uniform 1e4..2e6, Laplace lambda=1",
                        "engine": ["partitioned", "lockstep"][engine],
+                       "column_order": ["given", "independent"][co],
                        "n_patients_total": int(sum(p.n_patients for p in probs)),
                        "nnz_total": int(sum(p.nnz for p in probs))}}
 
 
-def cv_bench(sccs, synth, precision, max_sweeps, tol, n_folds=10, n_grid=16, engine=0):
+def cv_bench(sccs, synth, precision, max_sweeps, tol, n_folds=10, n_grid=16, engine=0, column_order=1):
     """The mid problem under 10-fold patient-level cross-validation x 16
     Laplace variances logspace(-3, 1): 10 fold chains walk the grid upward
     with warm starts (partitioned engine: one launch per variance, the folds
@@ -243,7 +253,8 @@ def cv_bench(sccs, synth, precision, max_sweeps, tol, n_folds=10, n_grid=16, eng
     grid = synth.prior_grid(n_grid)
     specs = [sccs.FitSpec(0, [(sccs.PRIOR_LAPLACE, float(v)) for v in grid], weight=(folds != k).astype(np.int32))
              for k in range(n_folds)]
-    with sccs.Batch([prob], specs, precision=precision, engine=engine) as b:
+    co = column_order if engine == 0 else 0   # the lockstep engine keeps the given order
+    with sccs.Batch([prob], specs, precision=precision, engine=engine, column_order=co) as b:
         t0 = time.perf_counter()
         b.run(sccs.CRIT_REL_LOGPOST, max_sweeps=max_sweeps, tol=tol)
         wall = time.perf_counter() - t0
@@ -270,10 +281,11 @@ def cv_bench(sccs, synth, precision, max_sweeps, tol, n_folds=10, n_grid=16, eng
             "heldout_loglik_mean_by_variance": [float(x) for x in mean],
             "config": {"workload": f"mid SCCS ({prob.n_patients} patients, J={prob.n_cols}) x 10 folds x 16 variances",
                        "engine": ["partitioned", "lockstep"][engine],
+                       "column_order": ["given", "independent"][co],
                        "max_sweeps_per_link": max_sweeps, "tol": tol}}
 
 
-def full_bench(sccs, synth, steps, refit=True):
+def full_bench(sccs, synth, steps, refit=True, column_order=1):
     """Full-scale workload, precision form against the FP64 GPU path: 10M
     patients, ~100M eras, J = 4000 Zipf drugs (p_j = 0.482 rank^-1.1),
     Normal prior variance 0.5; `steps` sweeps each; then a seeded 1% patient
@@ -284,12 +296,13 @@ def full_bench(sccs, synth, steps, refit=True):
     print(f"[bench] generated {prob.summary()} in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     out = {"metric": "full-scale SCCS: sweeps/s, FP64 and mixed, and mixed error vs the FP64 oracle",
            "config": {"workload": "full SCCS: 10M patients, J=4000 Zipf(1.1) p0=0.482, Normal var 0.5",
-                      "n_patients": prob.n_patients, "n_eras": prob.n_rows, "nnz": prob.nnz}}
+                      "n_patients": prob.n_patients, "n_eras": prob.n_rows, "nnz": prob.nnz,
+                      "column_order": ["given", "independent"][column_order]}}
     c, p = column_stats(prob)
     betas = {}
     for prec, name in ((0, "fp64"), (1, "mixed")):
         t0 = time.perf_counter()
-        with sccs.Handle(prob, precision=prec) as h:
+        with sccs.Handle(prob, precision=prec, column_order=column_order) as h:
             print(f"[bench] {name} handle set up in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
             h.set_prior(sccs.PRIOR_NORMAL, 0.5)
             h.sweep(1)
@@ -315,6 +328,7 @@ def full_bench(sccs, synth, steps, refit=True):
     print(f"[bench] oracle refit of the 1% subsample: {ref['sweeps']} sweeps", file=sys.stderr, flush=True)
     errs = {}
     for prec, name in ((0, "fp64"), (1, "mixed")):
+        # the given order: the oracle's trajectory, sweep for sweep
         with sccs.Handle(sub, precision=prec) as h:
             h.set_prior(sccs.PRIOR_NORMAL, 0.5)
             h.sweep(ref["sweeps"])
@@ -365,13 +379,14 @@ def paper_fit_bench(sccs, synth, max_sweeps=1000):
     return out
 
 
-def coord_curve(sccs, synth, workload, n_workgroups, sweeps_at=(1, 2, 10), c_star=240_000):
+def coord_curve(sccs, synth, workload, n_workgroups, sweeps_at=(1, 2, 10), c_star=240_000, column_order=1):
     """Achieved bandwidth per coordinate against its column size (one-pass
     form, FP64, from beta = 0 under the workload's prior).  For each listed
     sweep the device stamps the moment every column group's steps are
-    taken; a group's time is the gap to the previous group's stamp and its
-    algorithmic bytes are those of bytes_per_sweep for its columns (phase B
-    only for columns whose step was nonzero).  Reported: the curve
+    taken; a group's time is the gap to the previous group's stamp.  That gap
+    holds the previous group's update (phase B) and this group's gathers and
+    reduction (phase A), so its algorithmic bytes are phase A's of this
+    group's columns plus phase B's of the previous group's moved columns.  Reported: the curve
     (median GB/s per power-of-two bucket of the group's nonzeros) and, over
     the columns with at least c_star nonzeros, the nonzero-weighted
     fraction of HBM peak (their bytes over their time)."""
@@ -382,10 +397,13 @@ def coord_curve(sccs, synth, workload, n_workgroups, sweeps_at=(1, 2, 10), c_sta
         prob, kind, var = synth.mid(), sccs.PRIOR_LAPLACE, 2.0
     c, p = column_stats(prob)
     out = {"workload": f"{workload} SCCS: {prob.n_patients} patients, {prob.n_rows} eras, J={prob.n_cols}, "
-                       f"{prob.nnz} nonzeros, FP64, one pass per column group, {n_workgroups or 'all'} workgroups",
+                       f"{prob.nnz} nonzeros, FP64, one pass per column group, {n_workgroups or 'all'} workgroups, "
+                       f"{['given', 'independent'][column_order]} column order",
            "c_star": c_star, "sweeps": {}}
-    with sccs.Handle(prob, n_workgroups=n_workgroups, merge_passes=0) as h:
+    with sccs.Handle(prob, n_workgroups=n_workgroups, merge_passes=0, column_order=column_order) as h:
         h.set_prior(kind, var)
+        order = h.column_order()   # sweep position -> column
+        c, p = c[order], p[order]
         beta_prev = np.zeros(prob.n_cols)
         for s in range(1, max(sweeps_at) + 1):
             h.sweep(1)
@@ -394,13 +412,15 @@ def coord_curve(sccs, synth, workload, n_workgroups, sweeps_at=(1, 2, 10), c_sta
                 beta_prev = beta
                 continue
             t, fc = h.group_times()
-            moved = beta != beta_prev
+            moved = (beta != beta_prev)[order]
             beta_prev = beta
             dt = np.diff(np.concatenate([[0.0], t]))
             ng = len(dt)
             gc = np.array([c[fc[g]:fc[g + 1]].sum() for g in range(ng)])
-            gb = np.array([bytes_per_sweep(c[fc[g]:fc[g + 1]], p[fc[g]:fc[g + 1]], moved[fc[g]:fc[g + 1]], 0)
-                           for g in range(ng)])
+            ga = np.array([phase_a_bytes(c[fc[g]:fc[g + 1]], p[fc[g]:fc[g + 1]], 0) for g in range(ng)])
+            gbb = np.array([phase_b_bytes(c[fc[g]:fc[g + 1]], p[fc[g]:fc[g + 1]], moved[fc[g]:fc[g + 1]], 0)
+                            for g in range(ng)])
+            gb = ga + np.concatenate([[0.0], gbb[:-1]])
             gbs = gb / (dt * 1e-6) / 1e9
             buckets = []
             lo = 1
@@ -445,6 +465,9 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--print-sha", action="store_true", help="print the sweep kernel's source hash and exit")
     ap.add_argument("--cv-max-sweeps", type=int, default=50)
+    ap.add_argument("--column-order", type=int, choices=[0, 1], default=1,
+                    help="0 the problem's column order, 1 the library's independence relabelling")
+    ap.add_argument("--no-given", action="store_true", help="skip the given-order comparison run")
     ap.add_argument("--batch-engine", type=int, choices=[0, 1], default=0,
                     help="batched workloads: 0 fits on disjoint workgroup ranges, 1 all fits in lockstep")
     ap.add_argument("--cv-tol", type=float, default=1e-8)
@@ -478,7 +501,8 @@ def main():
         return
     if args.workload == "outcomes":
         for prec in ((1,) if args.mixed_only else (0, 1)):
-            print(json.dumps(batched_outcomes_bench(sccs, synth, args.steps, prec, args.batch_engine)), flush=True)
+            print(json.dumps(batched_outcomes_bench(sccs, synth, args.steps, prec, args.batch_engine,
+                                                    args.column_order)), flush=True)
         return
     if args.tune:
         prob = synth.mid(n_patients=args.patients, n_cols=args.cols)
@@ -486,18 +510,19 @@ def main():
         print(json.dumps({"tune_best": best, "candidates": table}), flush=True)
         return
     if args.coord_curve:
-        print(json.dumps(coord_curve(sccs, synth, args.workload, args.workgroups if args.workload == "mid" else 0)),
-              flush=True)
+        print(json.dumps(coord_curve(sccs, synth, args.workload, args.workgroups if args.workload == "mid" else 0,
+                                     column_order=args.column_order)), flush=True)
         return
     if args.workload == "paper":
         print(json.dumps(paper_fit_bench(sccs, synth)), flush=True)
         return
     if args.workload == "full":
-        print(json.dumps(full_bench(sccs, synth, args.steps, refit=not args.no_cpu)), flush=True)
+        print(json.dumps(full_bench(sccs, synth, args.steps, refit=not args.no_cpu, column_order=args.column_order)),
+              flush=True)
         return
     if args.workload == "cv":
         print(json.dumps(cv_bench(sccs, synth, 1 if args.mixed_only else 0, args.cv_max_sweeps, args.cv_tol,
-                                  engine=args.batch_engine)), flush=True)
+                                  engine=args.batch_engine, column_order=args.column_order)), flush=True)
         return
 
     t0 = time.perf_counter()
@@ -505,7 +530,8 @@ def main():
     print(f"[bench] generated {prob.summary()} in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     c, p = column_stats(prob)
 
-    fp = run_form(sccs, prob, 0, args.steps, args.warmup, c, p, args.workgroups, late=args.late)
+    fp = run_form(sccs, prob, 0, args.steps, args.warmup, c, p, args.workgroups, late=args.late,
+                  column_order=args.column_order)
     print(f"[bench] fp64 done: {args.steps / fp['wall_s']:.1f} sweeps/s", file=sys.stderr, flush=True)
     ms = float(np.mean(fp["kernel_ms"]))
     algo = float(np.mean(fp["bytes"]))
@@ -536,10 +562,15 @@ def main():
                                f"sweeps 1..{args.steps} from beta = 0, one sweep per step",
                    "n_patients": prob.n_patients, "n_eras": prob.n_rows, "n_cols": prob.n_cols,
                    "nnz": prob.nnz, "prior": "laplace", "variance": 2.0, "parallelism": "single GPU",
-                   "n_workgroups": args.workgroups},
+                   "n_workgroups": args.workgroups,
+                   # Algorithm 1 cycles over the drugs in a fixed order; with
+                   # "independent" the library numbers them so that runs of
+                   # consecutive drugs share no patient (same data, same sweeps)
+                   "column_order": ["given", "independent"][args.column_order]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(ms),
-                     "kernel": "k_ccd<double, *> (one-pass-per-group and merged-pass forms)", "kernel_ms_mean": ms,
+                     "kernel": ("k_ccd<double, false> (one pass per column group)" if args.column_order else
+                                "k_ccd<double, *> (one-pass-per-group and merged-pass forms)"), "kernel_ms_mean": ms,
                      "algo_bytes_per_launch": algo,
                      "byte_model": "per coordinate 12 c_j + 16 p_j, plus 28 c_j + 8 p_j when its step is "
                                    "nonzero (c_j nonzeros, p_j patients of column j)",
@@ -559,9 +590,17 @@ def main():
                               "value": args.late / lt["wall_s"], "unit": "sweeps/s", "kernel_ms_mean": lms,
                               "achieved_GBs": float(np.mean(lt["bytes"])) / (lms * 1e-3) / 1e9,
                               "schedule": sched(lt)}
+    if args.column_order and not args.no_given:
+        gv = run_form(sccs, prob, 0, args.steps, args.warmup, c, p, args.workgroups, column_order=0)
+        gms = float(np.mean(gv["kernel_ms"]))
+        out["given_order"] = {"value": args.steps / gv["wall_s"], "unit": "sweeps/s", "kernel_ms_mean": gms,
+                              "achieved_GBs": float(np.mean(gv["bytes"])) / (gms * 1e-3) / 1e9,
+                              "schedule": sched(gv),
+                              "note": "same workload and schedule, drugs visited in the problem's own order"}
+        print(f"[bench] given order: {out['given_order']['value']:.1f} sweeps/s", file=sys.stderr, flush=True)
     if not args.no_mixed:
         mx = run_form(sccs, prob, 1, args.steps, args.warmup, c, p, args.mixed_workgroups,
-                      refresh_period=args.mixed_refresh)
+                      refresh_period=args.mixed_refresh, column_order=args.column_order)
         err = float(np.max(np.abs(mx["beta"] - fp["beta"])) / max(np.max(np.abs(fp["beta"])), 1e-300))
         mms = float(np.mean(mx["kernel_ms"]))
         out["mixed"] = {"value": args.steps / mx["wall_s"], "unit": "sweeps/s",

@@ -569,7 +569,11 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchArgs A) {
   __shared__ int s_gcol[kMaxJ + 1];                    // column groups (shared by all fits)
   __shared__ double lp_prev[kMaxFits], s_var[kMaxFits], s_lam[kMaxFits], s_ivar[kMaxFits];
   __shared__ int s_link[kMaxFits], s_sw[kMaxFits], s_kind[kMaxFits], s_done[kMaxFits];
-  __shared__ int flag, bad_any, n_active, since_refresh;
+  __shared__ int flag, bad_any, n_active;
+  // sweeps since the last exact refresh: a register of every thread (all
+  // threads count the same sweeps), so that all of them take the refresh
+  // and its barrier together
+  int since_refresh = 0;
   __shared__ double red[kWaves][4];
   __shared__ int s_ixs[2][kBW][kFitsPerWave][4];        // indices of coordinates j and j + 1
   __shared__ uint2 s_ixrp[2][kBW][kFitsPerWave][64];
@@ -602,7 +606,7 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchArgs A) {
     if (!s_done[tid]) set_link(tid);
     lp_prev[tid] = 0.0;
   }
-  if (tid == 0) { since_refresh = 0; bad_any = 0; }
+  if (tid == 0) bad_any = 0;
   __syncthreads();
 
   // objective of every fit: (sum of positive, sum of negative) parts of

@@ -498,7 +498,7 @@ sccs_status sccs_create(const sccs_problem* prob, const sccs_options* opts_in, v
     g_create_error = "hipGetDevice failed";
     return SCCS_ERR_HIP;
   }
-  h->refresh_period = opts.refresh_period >= 0 ? opts.refresh_period : (opts.precision == SCCS_PREC_MIXED ? 1 : 0);
+  h->refresh_period = opts.refresh_period >= 0 ? opts.refresh_period : (opts.precision == SCCS_PREC_MIXED ? kMixedRefresh : 0);
   {
     int32_t maxrange = 1;
     for (int32_t b = 0; b < G; ++b) maxrange = std::max(maxrange, L.pb[b + 1] - L.pb[b]);

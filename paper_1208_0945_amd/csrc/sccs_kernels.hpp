@@ -170,9 +170,15 @@ __device__ __forceinline__ bool poll_tagged(const uint64_t* src, bool active, ui
 // tag that reduction s-2 left in the same word.  (NV is a compile-time
 // constant so that all polling loads of a round are issued before any is
 // waited on.)
+//
+// Both sums are balanced pairwise trees in member (group) order, so the
+// value does not depend on NV or on which of the two forms below runs: one
+// lane per member, polling its NV words (allreduce2_lanes, for 2 words, or
+// more than 8), or one lane per (member, word) pair (allreduce2_spread, for
+// 3 to 8 words), which needs fewer load instructions per polling round.
 template <int NV>
-__device__ bool allreduce2_wave(uint64_t* s1, uint64_t* s2, uint32_t seq, int G, Ctrl* ctrl,
-                                const double* part, double* out, int b) {
+__device__ bool allreduce2_lanes(uint64_t* s1, uint64_t* s2, uint32_t seq, int G, Ctrl* ctrl,
+                                 const double* part, double* out, int b) {
   const int lane = threadIdx.x & 63;
   const uint32_t par = seq & 1u, tag = (seq >> 1) & 1u;
   const int ng = G < kGroups ? G : kGroups;
@@ -207,6 +213,113 @@ __device__ bool allreduce2_wave(uint64_t* s1, uint64_t* s2, uint32_t seq, int G,
 #pragma unroll
   for (int i = 0; i < NV; ++i) out[i] = wave_sum_lo<8>(v[i]);
   return true;
+}
+
+// Poll P tagged words per lane (word p at src[p], if act[p]) until all carry
+// `tag`; decoded values in v (zeros where inactive).  Timeout and abort as
+// for poll_tagged.
+template <int P>
+__device__ __forceinline__ bool poll_words(const uint64_t* const* src, const bool* act, uint32_t tag, double* v,
+                                           Ctrl* ctrl) {
+  bool need = false;
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    v[p] = 0.0;
+    need = need || act[p];
+  }
+  long long spins = 0;
+  while (true) {
+    if (need) {
+      bool ready = true;
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        if (act[p]) {
+          const uint64_t x = load_agent(src[p]);
+          ready = ready && ((uint32_t)(x >> 63) == tag);
+          v[p] = tag_decode(x);
+        }
+      }
+      if (ready) need = false;
+    }
+    if (__ballot(need) == 0ull) return true;
+    if (++spins > kSpinLimit) {
+      if ((threadIdx.x & 63) == 0) {
+        __hip_atomic_store(&ctrl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ctrl->status, (int)SCCS_ERR_SYNC, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      return false;
+    }
+    if ((spins & 255) == 0 && load_agent_i(&ctrl->abort)) return false;
+    if (kPollSleep) __builtin_amdgcn_s_sleep(kPollSleep);
+  }
+}
+
+template <int NV>
+__device__ bool allreduce2_spread(uint64_t* s1, uint64_t* s2, uint32_t seq, int G, Ctrl* ctrl,
+                                  const double* part, double* out, int b) {
+  static_assert(NV >= 3 && NV <= 8, "three to eight words");
+  constexpr int NP = NV <= 4 ? 4 : 8;         // lanes per member: NV rounded up to a power of two
+  constexpr int MPP = 64 / NP;                // members per polling load
+  constexpr int P1 = 32 / MPP;                // loads for up to 32 members
+  static_assert(kReplicas * NP <= 64 && kGroups * NP <= 64, "one lane per (copy or group, word)");
+  const int lane = threadIdx.x & 63;
+  const int wd = lane & (NP - 1);             // this lane's word
+  const uint32_t par = seq & 1u, tag = (seq >> 1) & 1u;
+  const int ng = G < kGroups ? G : kGroups;
+  uint64_t* L1 = s1 + (size_t)par * (kSlots1Words / 2);
+  uint64_t* L2 = s2 + (size_t)par * kReplicas * kGroups * kSlotWords;
+  {   // lane v stores word v of this workgroup's slot
+    double mine = 0.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const double pv = readlane_d(part[v], 0);
+      if (wd == v) mine = pv;
+    }
+    if (lane < NV) store_agent(L1 + (size_t)b * kSlotWords + lane, tag_encode(mine, tag));
+  }
+  if (b < ng) {
+    const int nm = (G - b + ng - 1) / ng;   // members of group b: b, b + ng, ...
+    // loads in use (a power of two); lane (j, word) of load p polls member j Pa + p
+    const int Pa = nm <= MPP ? 1 : nm <= 2 * MPP ? 2 : 4;
+    const uint64_t* src[P1];
+    bool act[P1];
+#pragma unroll
+    for (int p = 0; p < P1; ++p) {
+      const int k = (lane / NP) * Pa + p;
+      act[p] = wd < NV && p < Pa && k < nm;
+      src[p] = L1 + (size_t)(act[p] ? b + k * ng : b) * kSlotWords + wd;
+    }
+    double v[P1];
+    if (!poll_words<P1>(src, act, tag, v, ctrl)) return false;
+    // the balanced tree over the members in order: the Pa consecutive
+    // members of a lane first, then across the lanes of one word
+    double sm;
+    if constexpr (P1 == 2) sm = Pa == 2 ? v[0] + v[1] : v[0];
+    else sm = Pa == 4 ? (v[0] + v[1]) + (v[2] + v[3]) : Pa == 2 ? v[0] + v[1] : v[0];
+#pragma unroll
+    for (int off = NP; off < 64; off <<= 1) sm += __shfl_xor(sm, off, 64);
+    const int r = lane / NP;   // copy r of the group total, word wd
+    if (r < kReplicas && wd < NV) store_agent(L2 + ((size_t)r * kGroups + b) * kSlotWords + wd, tag_encode(sm, tag));
+  }
+  const int rr = b % kReplicas;
+  const int gi = lane / NP;   // group gi's total, word wd
+  const uint64_t* src2[1] = {L2 + ((size_t)rr * kGroups + (gi < ng ? gi : 0)) * kSlotWords + wd};
+  const bool act2[1] = {gi < ng && wd < NV};
+  double v2[1];
+  if (!poll_words<1>(src2, act2, tag, v2, ctrl)) return false;
+  double t = v2[0];
+#pragma unroll
+  for (int off = NP; off < 64; off <<= 1) t += __shfl_xor(t, off, 64);
+#pragma unroll
+  for (int i = 0; i < NV; ++i) out[i] = readlane_d(t, i);
+  return true;
+}
+
+template <int NV>
+__device__ __forceinline__ bool allreduce2_wave(uint64_t* s1, uint64_t* s2, uint32_t seq, int G, Ctrl* ctrl,
+                                                const double* part, double* out, int b) {
+  if constexpr (NV >= 3 && NV <= 8) return allreduce2_spread<NV>(s1, s2, seq, G, ctrl, part, out, b);
+  else return allreduce2_lanes<NV>(s1, s2, seq, G, ctrl, part, out, b);
 }
 
 // Workgroup-level wrapper: wave 0 reduces, the result is broadcast through
@@ -1204,17 +1317,17 @@ __device__ __forceinline__ void ccd_body(const KArgs& a) {
           for (int i = 0; i < 2 * kPassCols; ++i) tot[i] = 0.0;
           bool okr;
           switch (cls) {   // one width per slot class, fixed at compile time
-            case 0: okr = allreduce2_wave<2>(s1, s2, sq, a.G, a.ctrl, part, tot, b); break;
+            case 0: okr = allreduce2_lanes<2>(s1, s2, sq, a.G, a.ctrl, part, tot, b); break;
 #if SCCS_MAX_GROUP >= 2
-            case 1: okr = allreduce2_wave<4>(s1, s2, sq, a.G, a.ctrl, part, tot, b); break;
+            case 1: okr = allreduce2_lanes<4>(s1, s2, sq, a.G, a.ctrl, part, tot, b); break;
 #endif
 #if SCCS_MAX_GROUP >= 3
-            case 2: okr = allreduce2_wave<6>(s1, s2, sq, a.G, a.ctrl, part, tot, b); break;
+            case 2: okr = allreduce2_lanes<6>(s1, s2, sq, a.G, a.ctrl, part, tot, b); break;
 #endif
 #if SCCS_MAX_GROUP >= 4
-            case 3: okr = allreduce2_wave<8>(s1, s2, sq, a.G, a.ctrl, part, tot, b); break;
+            case 3: okr = allreduce2_lanes<8>(s1, s2, sq, a.G, a.ctrl, part, tot, b); break;
 #endif
-            default: okr = allreduce2_wave<2 * kPassCols>(s1, s2, sq, a.G, a.ctrl, part, tot, b); break;
+            default: okr = allreduce2_lanes<2 * kPassCols>(s1, s2, sq, a.G, a.ctrl, part, tot, b); break;
           }
 
           double Gc = 0.0, Hc = 0.0;

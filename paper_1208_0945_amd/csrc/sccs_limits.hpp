@@ -33,5 +33,12 @@ constexpr int32_t kDescMaxCols = 1 << kDescColBits;
 constexpr int kDescWidthShift = kDescColBits;         // width: 3 bits
 constexpr int kDescLinkShift = kDescColBits + 3;      // link mask: kLinkCols bits
 static_assert(kDescLinkShift + kLinkCols <= 32, "pass descriptor is one 32-bit word");
+// Default sweeps between exact recomputations of w and den in the mixed
+// form: every sweep.  The FP32 multiplicative updates drift by about 2e-8
+// (relative to max |beta|) per sweep on the mid and full workloads; a
+// refresh every 10 sweeps keeps max-norm errors near 2e-7 but lets a
+// coordinate near 1e-3 drift by a few parts in 1e4, so rarer refreshes are
+// the caller's choice (refresh_period).
+constexpr int kMixedRefresh = 1;
 
 }  // namespace sccs

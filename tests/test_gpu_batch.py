@@ -162,6 +162,20 @@ def test_batch_mixed_precision(sccs, engine):
             assert rel_inf(beta, ref["beta"]) <= 1e-6
 
 
+@pytest.mark.parametrize("refresh", [0, 3])
+def test_batch_refresh_periods(sccs, engine, refresh):
+    """Exact refreshes every few sweeps (every thread of a workgroup takes
+    the refresh and its barrier together), and none at all."""
+    probs = outcomes(3, seed=6)
+    with sccs.Batch(probs, [sccs.FitSpec(f, [(sccs.PRIOR_LAPLACE, 2.0)]) for f in range(3)],
+                    precision=sccs.PREC_MIXED, refresh_period=refresh, engine=engine) as b:
+        b.run(sccs.CRIT_FIXED, max_sweeps=10)
+        for f, p in enumerate(probs):
+            beta, res = b.get(f, 0)
+            assert res["sweeps"] == 10
+            assert rel_inf(beta, oracle.ccd(p, oracle.PRIOR_LAPLACE, 2.0, 10)["beta"]) <= 1e-6
+
+
 def test_batch_rejects_bad_specs(sccs, engine):
     probs = outcomes(2)
     with pytest.raises(sccs.SccsError):
