@@ -173,9 +173,9 @@ __device__ __forceinline__ bool poll_tagged(const uint64_t* src, bool active, ui
 //
 // Both sums are balanced pairwise trees in member (group) order, so the
 // value does not depend on NV or on which of the two forms below runs: one
-// lane per member, polling its NV words (allreduce2_lanes, for 2 words, or
-// more than 8), or one lane per (member, word) pair (allreduce2_spread, for
-// 3 to 8 words), which needs fewer load instructions per polling round.
+// lane per member, polling its NV words (allreduce2_lanes, for more than 8
+// words), or one lane per (member, word) pair (allreduce2_rows, up to 8
+// words), which needs fewer load instructions per polling round.
 template <int NV>
 __device__ bool allreduce2_lanes(uint64_t* s1, uint64_t* s2, uint32_t seq, int G, Ctrl* ctrl,
                                  const double* part, double* out, int b) {
@@ -254,16 +254,34 @@ __device__ __forceinline__ bool poll_words(const uint64_t* const* src, const boo
   }
 }
 
+// Sum of the 16 lanes of each row (all lanes of a row end with the row's
+// sum, a balanced tree in lane order).
+__device__ __forceinline__ double row_sum16(double v) {
+  v = dpp_add<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v = dpp_add<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]
+  v = dpp_add<0x141, 0xf>(v);  // row_half_mirror
+  return dpp_add<0x140, 0xf>(v);  // row_mirror
+}
+// Sum of lanes 0..7 of each row in those lanes (balanced tree).
+__device__ __forceinline__ double row_sum8(double v) {
+  v = dpp_add<0xB1, 0xf>(v);
+  v = dpp_add<0x4E, 0xf>(v);
+  return dpp_add<0x141, 0xf>(v);
+}
+
+// One 16-lane row per word: lane (row r, column c) of word pass q handles
+// word 4q + r of member 16p + c (level 1, member pass p) or of group c
+// (level 2), so one load per (word pass, member pass) polls a whole round
+// and the sums are row-wise DPP trees.
 template <int NV>
-__device__ bool allreduce2_spread(uint64_t* s1, uint64_t* s2, uint32_t seq, int G, Ctrl* ctrl,
-                                  const double* part, double* out, int b) {
-  static_assert(NV >= 3 && NV <= 8, "three to eight words");
-  constexpr int NP = NV <= 4 ? 4 : 8;         // lanes per member: NV rounded up to a power of two
-  constexpr int MPP = 64 / NP;                // members per polling load
-  constexpr int P1 = 32 / MPP;                // loads for up to 32 members
-  static_assert(kReplicas * NP <= 64 && kGroups * NP <= 64, "one lane per (copy or group, word)");
+__device__ bool allreduce2_rows(uint64_t* s1, uint64_t* s2, uint32_t seq, int G, Ctrl* ctrl,
+                                const double* part, double* out, int b) {
+  static_assert(NV >= 1 && NV <= 8, "one to eight words");
+  static_assert(kReplicas <= 16 && kGroups <= 8, "copies and groups along a row");
+  constexpr int NQ = (NV + 3) / 4;            // word passes (four rows each)
+  constexpr int NL = 2 * NQ;                  // loads of a level-1 polling round (two member passes)
   const int lane = threadIdx.x & 63;
-  const int wd = lane & (NP - 1);             // this lane's word
+  const int row = lane >> 4, col = lane & 15;
   const uint32_t par = seq & 1u, tag = (seq >> 1) & 1u;
   const int ng = G < kGroups ? G : kGroups;
   uint64_t* L1 = s1 + (size_t)par * (kSlots1Words / 2);
@@ -273,52 +291,58 @@ __device__ bool allreduce2_spread(uint64_t* s1, uint64_t* s2, uint32_t seq, int 
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const double pv = readlane_d(part[v], 0);
-      if (wd == v) mine = pv;
+      if (lane == v) mine = pv;
     }
     if (lane < NV) store_agent(L1 + (size_t)b * kSlotWords + lane, tag_encode(mine, tag));
   }
   if (b < ng) {
-    const int nm = (G - b + ng - 1) / ng;   // members of group b: b, b + ng, ...
-    // loads in use (a power of two); lane (j, word) of load p polls member j Pa + p
-    const int Pa = nm <= MPP ? 1 : nm <= 2 * MPP ? 2 : 4;
-    const uint64_t* src[P1];
-    bool act[P1];
+    const int nm = (G - b + ng - 1) / ng;   // members of group b: b, b + ng, ... (at most 32)
+    const uint64_t* src[NL];
+    bool act[NL];
 #pragma unroll
-    for (int p = 0; p < P1; ++p) {
-      const int k = (lane / NP) * Pa + p;
-      act[p] = wd < NV && p < Pa && k < nm;
-      src[p] = L1 + (size_t)(act[p] ? b + k * ng : b) * kSlotWords + wd;
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        const int w = 4 * q + row, k = 16 * p + col;
+        act[2 * q + p] = w < NV && k < nm;
+        src[2 * q + p] = L1 + (size_t)(act[2 * q + p] ? b + k * ng : b) * kSlotWords + (w < NV ? w : 0);
+      }
+    double v[NL];
+    if (!poll_words<NL>(src, act, tag, v, ctrl)) return false;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      // members 0..15 and 16..31 of word 4q + row (a pass with no member adds +0)
+      const double sm = row_sum16(v[2 * q]) + row_sum16(v[2 * q + 1]);
+      const int w = 4 * q + row;
+      if (w < NV && col < kReplicas)   // copy col of the group total
+        store_agent(L2 + ((size_t)col * kGroups + b) * kSlotWords + w, tag_encode(sm, tag));
     }
-    double v[P1];
-    if (!poll_words<P1>(src, act, tag, v, ctrl)) return false;
-    // the balanced tree over the members in order: the Pa consecutive
-    // members of a lane first, then across the lanes of one word
-    double sm;
-    if constexpr (P1 == 2) sm = Pa == 2 ? v[0] + v[1] : v[0];
-    else sm = Pa == 4 ? (v[0] + v[1]) + (v[2] + v[3]) : Pa == 2 ? v[0] + v[1] : v[0];
-#pragma unroll
-    for (int off = NP; off < 64; off <<= 1) sm += __shfl_xor(sm, off, 64);
-    const int r = lane / NP;   // copy r of the group total, word wd
-    if (r < kReplicas && wd < NV) store_agent(L2 + ((size_t)r * kGroups + b) * kSlotWords + wd, tag_encode(sm, tag));
   }
   const int rr = b % kReplicas;
-  const int gi = lane / NP;   // group gi's total, word wd
-  const uint64_t* src2[1] = {L2 + ((size_t)rr * kGroups + (gi < ng ? gi : 0)) * kSlotWords + wd};
-  const bool act2[1] = {gi < ng && wd < NV};
-  double v2[1];
-  if (!poll_words<1>(src2, act2, tag, v2, ctrl)) return false;
-  double t = v2[0];
+  const uint64_t* src2[NQ];
+  bool act2[NQ];
 #pragma unroll
-  for (int off = NP; off < 64; off <<= 1) t += __shfl_xor(t, off, 64);
+  for (int q = 0; q < NQ; ++q) {
+    const int w = 4 * q + row;
+    act2[q] = w < NV && col < ng;
+    src2[q] = L2 + ((size_t)rr * kGroups + (act2[q] ? col : 0)) * kSlotWords + (w < NV ? w : 0);
+  }
+  double v2[NQ];
+  if (!poll_words<NQ>(src2, act2, tag, v2, ctrl)) return false;
 #pragma unroll
-  for (int i = 0; i < NV; ++i) out[i] = readlane_d(t, i);
+  for (int q = 0; q < NQ; ++q) {
+    const double t = row_sum8(v2[q]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (4 * q + r < NV) out[4 * q + r] = readlane_d(t, 16 * r + 7);
+  }
   return true;
 }
 
 template <int NV>
 __device__ __forceinline__ bool allreduce2_wave(uint64_t* s1, uint64_t* s2, uint32_t seq, int G, Ctrl* ctrl,
                                                 const double* part, double* out, int b) {
-  if constexpr (NV >= 3 && NV <= 8) return allreduce2_spread<NV>(s1, s2, seq, G, ctrl, part, out, b);
+  if constexpr (NV <= 8) return allreduce2_rows<NV>(s1, s2, seq, G, ctrl, part, out, b);
   else return allreduce2_lanes<NV>(s1, s2, seq, G, ctrl, part, out, b);
 }
 
