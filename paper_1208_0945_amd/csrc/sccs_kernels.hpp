@@ -1736,8 +1736,8 @@ __global__ void __launch_bounds__(kBlock) k_diag(KArgs a) {
 
 // Held-out log-likelihood of one fit (Eq. 2 over its weight-0 patients):
 // block partials of -sum_i hn_i log den_i over a fixed grid, then one block
-// adds them in block order and beta'Y'X(held out) (fixed order throughout).
-constexpr int kHoBlocks = 64;
+// adds them and beta'Y'X(held out) (fixed order throughout).
+constexpr int kHoBlocks = 1024;
 __global__ void __launch_bounds__(256) k_heldout_part(const double2* pat, const double* hn, int N, double* part) {
   __shared__ double red[4];
   double s = 0.0;
@@ -1753,14 +1753,11 @@ __global__ void __launch_bounds__(256) k_heldout_final(const double* part, const
   __shared__ double red[4];
   double s = 0.0;
   for (int j = threadIdx.x; j < J; j += 256) s += beta[j] * ytx_ho[j];
+  for (int b = threadIdx.x; b < kHoBlocks; b += 256) s += part[b];
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = (red[0] + red[1]) + (red[2] + red[3]);
-    for (int b = 0; b < kHoBlocks; ++b) t += part[b];
-    *out = t;
-  }
+  if (threadIdx.x == 0) *out = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // ------------------------------------------------------------ setup kernels
