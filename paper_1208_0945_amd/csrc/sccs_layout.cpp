@@ -337,25 +337,39 @@ void independent_order(const sccs_problem* p, int32_t width, std::vector<int32_t
     for (int64_t i = lo; i < hi; ++i)
       for (int64_t k = p->patient_ptr[i]; k < p->patient_ptr[i + 1]; ++k) era_pid[k] = (int32_t)i;
   });
-  // distinct patients of each column, and per patient a slot for each
-  // column it appears in (the groups it has joined so far)
+  // distinct patients of each column (its rows are strictly increasing and
+  // eras are stored patient by patient, so a column's patients come in
+  // non-decreasing order: dropping repeats leaves each once), columns in
+  // parallel; then per patient a slot for each column it appears in (the
+  // groups it has joined so far)
   std::vector<int64_t> pat_ptr((size_t)J + 1, 0);
-  std::vector<int32_t> pats;
-  std::vector<int32_t> n_of((size_t)N, 0);
-  {
-    std::vector<int32_t> seen((size_t)N, -1);
-    for (int32_t j = 0; j < J; ++j) {
+  parallel_ranges(J, [&](int64_t lo, int64_t hi) {
+    for (int64_t j = lo; j < hi; ++j) {
+      int64_t n = 0;
+      int32_t last = -1;
       for (int64_t e = p->col_ptr[j]; e < p->col_ptr[j + 1]; ++e) {
         const int32_t i = era_pid[p->row_idx[e]];
-        if (seen[i] != j) {
-          seen[i] = j;
-          pats.push_back(i);
-          ++n_of[i];
-        }
+        n += i != last;
+        last = i;
       }
-      pat_ptr[(size_t)j + 1] = (int64_t)pats.size();
+      pat_ptr[(size_t)j + 1] = n;
     }
-  }
+  }, 1 << 30, 64);
+  for (int32_t j = 0; j < J; ++j) pat_ptr[(size_t)j + 1] += pat_ptr[j];
+  std::vector<int32_t> pats((size_t)pat_ptr[J]);
+  parallel_ranges(J, [&](int64_t lo, int64_t hi) {
+    for (int64_t j = lo; j < hi; ++j) {
+      int64_t q = pat_ptr[j];
+      int32_t last = -1;
+      for (int64_t e = p->col_ptr[j]; e < p->col_ptr[j + 1]; ++e) {
+        const int32_t i = era_pid[p->row_idx[e]];
+        if (i != last) pats[(size_t)q++] = i;
+        last = i;
+      }
+    }
+  }, 1 << 30, 64);
+  std::vector<int32_t> n_of((size_t)N, 0);
+  for (const int32_t i : pats) ++n_of[i];
   std::vector<int64_t> memb_ptr((size_t)N + 1, 0);
   for (int32_t i = 0; i < N; ++i) memb_ptr[(size_t)i + 1] = memb_ptr[i] + n_of[i];
   std::vector<int32_t> memb((size_t)memb_ptr[N]);
@@ -366,31 +380,69 @@ void independent_order(const sccs_problem* p, int32_t width, std::vector<int32_t
   std::stable_sort(visit.begin(), visit.end(), [&](int32_t x, int32_t y) {
     return p->col_ptr[x + 1] - p->col_ptr[x] > p->col_ptr[y + 1] - p->col_ptr[y];
   });
+  // Columns are placed one after another (each placement depends on the
+  // groups so far), but the two per-patient loops of a placement -- marking
+  // the groups the column's patients are in, and recording the new
+  // membership -- run on T threads over slices of the column's patients,
+  // kept in step by a spinning barrier.  Thread 0 picks the group.
   std::vector<std::vector<int32_t>> groups;
-  std::vector<int32_t> open;        // groups with room, in creation order
-  std::vector<int32_t> clash_mark;  // clash_mark[g] == j: group g shares a patient with column j
-  for (int32_t j : visit) {
-    for (int64_t q = pat_ptr[j]; q < pat_ptr[(size_t)j + 1]; ++q) {
-      const int32_t i = pats[q];
-      for (int64_t m = memb_ptr[i]; m < memb_ptr[i] + filled[i]; ++m) clash_mark[memb[m]] = j;
+  std::vector<int32_t> open;   // groups with room, in creation order
+  const int T = std::max(1, std::min(host_threads(), 8));
+  std::vector<std::vector<uint64_t>> bits((size_t)T);
+  std::atomic<int> arrived{0}, phase{0};
+  int32_t chosen = 0;
+  auto barrier = [&](int& my_phase) {
+    if (arrived.fetch_add(1) == T - 1) {
+      arrived.store(0);
+      phase.fetch_add(1);
+    } else {
+      while (phase.load() == my_phase) std::this_thread::yield();
     }
-    int32_t g = -1;
-    size_t oi = 0;
-    for (; oi < open.size(); ++oi)
-      if (clash_mark[open[oi]] != j) { g = open[oi]; break; }
-    if (g < 0) {
-      g = (int32_t)groups.size();
-      groups.emplace_back();
-      clash_mark.push_back(-1);
-      open.push_back(g);
-      oi = open.size() - 1;
+    ++my_phase;
+  };
+  auto worker = [&](int t) {
+    int my_phase = 0;
+    for (const int32_t j : visit) {
+      const int64_t q0 = pat_ptr[j], q1 = pat_ptr[(size_t)j + 1];
+      const int64_t lo = q0 + (q1 - q0) * t / T, hi = q0 + (q1 - q0) * (t + 1) / T;
+      std::vector<uint64_t>& mine = bits[(size_t)t];
+      mine.assign((groups.size() + 63) / 64, 0ull);
+      for (int64_t q = lo; q < hi; ++q) {
+        const int32_t i = pats[q];
+        for (int64_t m = memb_ptr[i]; m < memb_ptr[i] + filled[i]; ++m) mine[memb[m] >> 6] |= 1ull << (memb[m] & 63);
+      }
+      barrier(my_phase);
+      if (t == 0) {
+        for (int u = 1; u < T; ++u)
+          for (size_t x = 0; x < mine.size(); ++x) mine[x] |= bits[(size_t)u][x];
+        int32_t g = -1;
+        size_t oi = 0;
+        for (; oi < open.size(); ++oi)
+          if (!((mine[(size_t)open[oi] >> 6] >> (open[oi] & 63)) & 1ull)) { g = open[oi]; break; }
+        if (g < 0) {
+          g = (int32_t)groups.size();
+          groups.emplace_back();
+          open.push_back(g);
+          oi = open.size() - 1;
+        }
+        groups[g].push_back(j);
+        if ((int32_t)groups[g].size() >= width) open.erase(open.begin() + (ptrdiff_t)oi);
+        chosen = g;
+      }
+      barrier(my_phase);
+      // each patient appears once in the column: no two threads touch one list
+      for (int64_t q = lo; q < hi; ++q) {
+        const int32_t i = pats[q];
+        memb[memb_ptr[i] + filled[i]++] = chosen;
+      }
+      barrier(my_phase);
     }
-    groups[g].push_back(j);
-    if ((int32_t)groups[g].size() >= width) open.erase(open.begin() + (ptrdiff_t)oi);
-    for (int64_t q = pat_ptr[j]; q < pat_ptr[(size_t)j + 1]; ++q) {
-      const int32_t i = pats[q];
-      memb[memb_ptr[i] + filled[i]++] = g;
-    }
+  };
+  {
+    std::vector<std::thread> th;
+    for (int t = 1; t < T; ++t) th.emplace_back(worker, t);
+    worker(0);
+    for (auto& x : th) x.join();
   }
   order.clear();
   order.reserve((size_t)J);

@@ -94,3 +94,19 @@ def test_bootstrap_argument_errors(sccs):
     bad[1, 3] = -1
     with pytest.raises(sccs.SccsError):
         sccs.bootstrap(prob, 2, 1.0, bad)
+
+
+def test_bootstrap_relabelled(sccs):
+    """The bootstrap under the independence relabelling (partitioned engine):
+    the oracle bootstraps the renumbered problem with the same multiplicities
+    and its results are mapped back to the problem's numbering."""
+    prob = synth.tiny(n_patients=1500, n_cols=20, seed=5)
+    W = synth.bootstrap_weights(prob.n_patients, 70, seed=1)
+    order = oracle.independent_order(prob, 4)
+    r = oracle.bootstrap(synth.permute_columns(prob, order), 2, 0.05, W, 15)
+    ref = {k: np.empty_like(r[k]) for k in ("beta", "lo", "hi", "p_hat")}
+    ref["beta"][:, order] = r["beta"]
+    for k in ("lo", "hi", "p_hat"):
+        ref[k][order] = r[k]
+    got = sccs.bootstrap(prob, 2, 0.05, W, criterion=sccs.CRIT_FIXED, max_sweeps=15, column_order=1)
+    _check(sccs, got, ref, 1e-9)

@@ -59,3 +59,18 @@ def test_cv_search_budget_and_errors(sccs):
     bad[0] = 7
     with pytest.raises(sccs.SccsError):
         sccs.cv_search(prob, bad, 3, 2)
+
+
+def test_cv_search_relabelled(sccs):
+    """The variance search under the independence relabelling: the oracle
+    searches the renumbered problem (the same folds), every evaluation's
+    predictive log-likelihood agrees to 1e-9."""
+    prob = synth.zipf_problem("zipf_small", 4000, 40, 0.1, seed_path=(8, 3))
+    folds = synth.cv_folds(prob.n_patients, 5, seed=1)
+    kw = dict(var_start=1e-2, bracket_step=10.0, log10_tol=0.1, max_evals=20, warm_start=True)
+    perm = synth.permute_columns(prob, oracle.independent_order(prob, 4))
+    ref = oracle.cv_search(perm, folds, 5, 2, max_sweeps=300, tol=1e-11, **kw)
+    got = sccs.cv_search(prob, folds, 5, 2, max_sweeps=300, tol=1e-11, column_order=1, **kw)
+    assert np.allclose(got["variance"], ref["variance"], rtol=1e-12, atol=0)
+    assert np.max(np.abs(got["pred_loglik"] - ref["pred_loglik"]) / np.abs(ref["pred_loglik"])) <= 1e-9
+    assert got["best"] == ref["best"] and got["bracketed"] == ref["bracketed"]
