@@ -1556,6 +1556,10 @@ __device__ __forceinline__ void ccd_body(const KArgs& a) {
           uint64_t* s2 = a.slots2 + cls * kSlots2PerClass;
 #pragma unroll
           for (int i = 0; i < 2 * kMaxGroup; ++i) tot[i] = 0.0;
+          // beta_j and Delta_j of the lane's column, read before the wait:
+          // only this lane writes them, after the reduction
+          const double bj_pre = lane < m ? sbeta[j0 + lane] : 0.0;
+          const double tr_pre = lane < m ? strust[j0 + lane] : 1.0;
           bool okr;
           switch (m) {   // one width per slot class, fixed at compile time
             case 1: okr = allreduce2_wave<2>(s1, s2, sq, a.G, a.ctrl, part, tot, b); break;
@@ -1584,7 +1588,7 @@ __device__ __forceinline__ void ccd_body(const KArgs& a) {
             bad = !(isfinite(gg) && isfinite(hh));
             if (okr && !bad) {
               const int j = j0 + lane;
-              const double bj = sbeta[j], tr = strust[j];
+              const double bj = bj_pre, tr = tr_pre;
               const double dv = prior_step(a.prior_kind, a.inv_var, a.lambda, bj, gg, hh);
               d = fmin(fmax(dv, -tr), tr);
               strust[j] = fmax(2.0 * fabs(d), 0.5 * tr);
