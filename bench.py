@@ -403,6 +403,7 @@ def coord_curve(sccs, synth, workload, n_workgroups, sweeps_at=(1, 2, 10), c_sta
            "c_star": c_star, "sweeps": {}}
     with sccs.Handle(prob, n_workgroups=n_workgroups, merge_passes=0, column_order=column_order) as h:
         h.set_prior(kind, var)
+        h.group_timing(True)
         order = h.column_order()   # sweep position -> column
         c, p = c[order], p[order]
         beta_prev = np.zeros(prob.n_cols)

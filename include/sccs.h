@@ -265,9 +265,17 @@ sccs_status sccs_last_kernel_ms(sccs_handle* h, double* ms);
  * sweep. */
 sccs_status sccs_pass_stats(sccs_handle* h, int32_t* passes, int32_t* rejects, int32_t* zero_steps);
 
+/* Per-coordinate timing on or off (on = 1, off = 0; off when a handle is
+ * created) for the handle's later sccs_sweep / sccs_fit launches: with it
+ * on, workgroup 0 stores the device wall clock once per column group, a
+ * store its next barrier waits for, so the sweep runs slightly slower.
+ * SCCS_ERR_INVALID_ARG for another value. */
+sccs_status sccs_group_timing(sccs_handle* h, int32_t on);
+
 /* Per-coordinate timing (for achieved bandwidth against column size): after
  * an sccs_sweep / sccs_fit launch in the one-pass-per-group form (a launch
- * that did not use merged passes; binary covariates), t_us[g] is the time
+ * that did not use merged passes; binary covariates) made with
+ * sccs_group_timing on, t_us[g] is the time
  * from the start of that launch's last sweep to the moment column group g's
  * steps were taken, in microseconds of the device wall clock, for the
  * n_groups groups; group g holds the columns visited at positions

@@ -52,6 +52,8 @@ struct sccs_handle {
   bool use_merge = false;          // the next sweep launch takes the merged-pass form
   bool valued = false;             // covariate values: k_ccd_val / k_diag_val
   bool last_merged = false;        // the last sweep launch used the merged-pass form
+  bool group_timing = false;       // sweep launches stamp each column group (sccs_group_timing)
+  bool last_stamped = false;       // the last sweep launch stamped its column groups
   int32_t n_classes = 0;           // grouped prior: classes (their sums take n_classes doubles of LDS)
   double class_var = 0.0;
   std::vector<int32_t> perm;       // perm[k]: the column visited k-th (empty: the given order)
@@ -274,6 +276,7 @@ sccs_status launch(sccs_handle* h, int mode, int n_sweeps, int criterion, double
   a.want_objective = want_obj;
   a.mode = mode;
   a.diag_j = diag_j;
+  a.stamp = mode == kModeSweep && h->group_timing ? 1 : 0;
   void* params[] = {&a};
   HIPCHK(h, hipMemsetAsync(&h->args.ctrl->status, 0, sizeof(int32_t), h->stream));
   HIPCHK(h, hipEventRecord(h->ev0, h->stream));
@@ -281,6 +284,7 @@ sccs_status launch(sccs_handle* h, int mode, int n_sweeps, int criterion, double
   if (mode == kModeSweep) {   // the mirror holds the state after the previous launch
     for (int c = 0; c < kSlotClasses; ++c) h->gseq0[c] = h->h_ctrl->gseq[c];
     h->last_merged = merge;
+    h->last_stamped = a.stamp && !merge;
   }
   h->last_mode = mode;
   HIPCHK(h, hipLaunchCooperativeKernel(ccd_kernel(h->prec, mode, merge, h->valued), dim3(h->G), dim3(kBlock), params,
@@ -766,6 +770,7 @@ sccs_status sccs_sweep_static(sccs_handle* h, int32_t n_sweeps, double* logpost)
   a.want_objective = logpost != nullptr;
   a.mode = kModeSweep;
   a.diag_j = 0;
+  a.stamp = 0;
   hipLaunchKernelGGL(k_scratch_prep, dim3(64), dim3(256), 0, h->stream, base, kScrTagWords, a.ctrl,
                      (const Ctrl*)h->args.ctrl);
   HIPCHK(h, hipGetLastError());
@@ -863,10 +868,17 @@ sccs_status sccs_pass_stats(sccs_handle* h, int32_t* passes, int32_t* rejects, i
   return SCCS_OK;
 }
 
+sccs_status sccs_group_timing(sccs_handle* h, int32_t on) {
+  if (!h || (on != 0 && on != 1)) return SCCS_ERR_INVALID_ARG;
+  h->group_timing = on != 0;
+  return SCCS_OK;
+}
+
 sccs_status sccs_group_times(sccs_handle* h, int32_t max_groups, double* t_us, int32_t* first_col, int32_t* n_groups) {
   if (!h || !t_us || !first_col || !n_groups) return SCCS_ERR_INVALID_ARG;
-  if (!h->swept || h->last_mode != kModeSweep || h->last_merged || h->valued) {
-    h->err = "group times need a preceding sccs_sweep / sccs_fit launch in the one-pass-per-group form";
+  if (!h->swept || h->last_mode != kModeSweep || h->last_merged || h->valued || !h->last_stamped) {
+    h->err = "group times need a preceding sccs_sweep / sccs_fit launch in the one-pass-per-group form, "
+             "with sccs_group_timing on";
     return SCCS_ERR_STATE;
   }
   const int32_t NG = (int32_t)h->gcol.size() - 1;

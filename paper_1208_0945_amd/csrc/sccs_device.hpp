@@ -105,8 +105,9 @@ struct KArgs {
   int32_t ssum_off;
   // one-pass form: wall-clock ticks at the moment each group's steps were
   // taken in the current sweep ([n_groups]) and at the sweep's start
-  // ([n_groups]); written by workgroup 0
+  // ([n_groups]); written by workgroup 0 when stamp is set
   uint64_t* group_ticks;      // [n_groups + 1]
+  int32_t stamp;
   // first workgroup of this fit in the launch: several single fits can share
   // one launch, fit f on workgroups [b0, b0 + G) (0 for a launch of one fit)
   int32_t b0;

@@ -706,17 +706,118 @@ __device__ __forceinline__ void tile_b(const KArgs& a, int t, Coef cf) {
   }
 }
 
+// Mark patient q (relative to the range start) in an LDS bitmap.
+__device__ __forceinline__ void mark_patient(unsigned* bits, unsigned q) { atomicOr(&bits[q >> 5], 1u << (q & 31)); }
+
 // ---- tiles t, t + stride, ... < t1 of one range, in order
+//
+// Software-pipelined: while a tile's gathers are in flight, the wave loads
+// the (row, key) pairs of its next tile and the bounds of the tile after
+// that, and the per-patient words are gathered together with w (the lead
+// lanes follow from the keys alone).  A tile then waits on one round trip to
+// memory instead of a chain of four (bounds, pairs, w, then the patient
+// words).  The arithmetic, and its order, are those of tile_a and tile_b.
+
+// Bounds of tile t (e0, len), or an empty tile past the range.
+__device__ __forceinline__ void tile_bounds(const KArgs& a, int t, int t1, int& e0, int& len) {
+  e0 = 0;
+  len = 0;
+  if (t < t1) {
+    e0 = ld_idx(a.tile_start + t);
+    len = ld_idx(a.tile_start + t + 1) - e0;
+  }
+}
+// This lane's pair of a short tile (inactive lanes: no patient).
+__device__ __forceinline__ uint2 tile_pair(const KArgs& a, int e0, int len) {
+  const int lane = threadIdx.x & 63;
+  return len <= 64 && lane < len ? a.rp[e0 + lane] : make_uint2(0u, 0xffffffffu);
+}
 
 template <typename WT, int NC, bool kMark>
 __device__ __forceinline__ void tiles_a(const KArgs& a, int t, int t1, int stride, Acc<NC>& acc,
                                         unsigned* bits = nullptr, int p0 = 0, uint32_t coff = 0) {
-  for (; t < t1; t += stride) tile_a<WT, NC, kMark>(a, t, acc, bits, p0, coff);
+  if (t >= t1) return;
+  const int lane = threadIdx.x & 63;
+  const WT* __restrict__ w = (const WT*)a.w;
+  int e0, len, en, lenn;
+  tile_bounds(a, t, t1, e0, len);
+  tile_bounds(a, t + stride, t1, en, lenn);
+  uint2 rp = tile_pair(a, e0, len);
+  while (true) {
+    uint2 rpn;
+    int enn, lennn;
+    if (len <= 64) {
+      bool lead;
+      int seg_start;
+      seg_layout(rp.y, lane, len, lead, seg_start);
+      const double wv = lane < len ? (double)w[rp.x] : 0.0;
+      const double2 pv = lead ? a.pat[pid_of(rp.y)] : make_double2(1.0, 0.0);
+      rpn = tile_pair(a, en, lenn);
+      tile_bounds(a, t + 2 * stride, t1, enn, lennn);
+      const double num = seg_sum_v(wv, lane, seg_start);
+      if (lead) {
+        acc.add(col_of(rp.y) + coff, num, pv);
+        if (kMark) mark_patient(bits, pid_of(rp.y) - (unsigned)p0);
+      }
+    } else {
+      rpn = tile_pair(a, en, lenn);
+      tile_bounds(a, t + 2 * stride, t1, enn, lennn);
+      tile_a<WT, NC, kMark>(a, t, acc, bits, p0, coff);
+    }
+    t += stride;
+    if (t >= t1) break;
+    rp = rpn;
+    len = lenn;
+    en = enn;
+    lenn = lennn;
+  }
 }
 
 template <typename WT>
 __device__ __forceinline__ void tiles_b(const KArgs& a, int t, int t1, int stride, Coef cf) {
-  for (; t < t1; t += stride) tile_b<WT>(a, t, cf);
+  if (t >= t1) return;
+  const int lane = threadIdx.x & 63;
+  WT* __restrict__ w = (WT*)a.w;
+  int e0, len, en, lenn;
+  tile_bounds(a, t, t1, e0, len);
+  tile_bounds(a, t + stride, t1, en, lenn);
+  uint2 rp = tile_pair(a, e0, len);
+  while (true) {
+    uint2 rpn;
+    int enn, lennn;
+    if (len <= 64) {
+      const bool act = lane < len;
+      const uint32_t c = act ? col_of(rp.y) : 0u;
+      const double ed = cf.ed[c], em1 = cf.em1[c];
+      const bool upd = act && em1 != 0.0;
+      bool lead;
+      int seg_start;
+      seg_layout(rp.y, lane, len, lead, seg_start);
+      const WT wo = upd ? w[rp.x] : (WT)0;
+      const double den = lead && upd ? a.pat[pid_of(rp.y)].x : 0.0;
+      rpn = tile_pair(a, en, lenn);
+      tile_bounds(a, t + 2 * stride, t1, enn, lennn);
+      const WT wn = wo * (WT)ed;
+      if (upd) w[rp.x] = wn;
+      if (sizeof(WT) == 8) {
+        const double s = seg_sum_v((double)wo, lane, seg_start);
+        if (lead && upd) a.pat[pid_of(rp.y)].x = den + s * em1;
+      } else {
+        const double s = seg_sum_v(upd ? (double)wn - (double)wo : 0.0, lane, seg_start);
+        if (lead && upd) a.pat[pid_of(rp.y)].x = den + s;
+      }
+    } else {
+      rpn = tile_pair(a, en, lenn);
+      tile_bounds(a, t + 2 * stride, t1, enn, lennn);
+      tile_b<WT>(a, t, cf);
+    }
+    t += stride;
+    if (t >= t1) break;
+    rp = rpn;
+    len = lenn;
+    en = enn;
+    lenn = lennn;
+  }
 }
 
 // ---- the sweep's path
@@ -837,7 +938,6 @@ __device__ __forceinline__ void gather_first(const KArgs& a, const Pf& p, Cache&
   gather_sum(p, c);
 }
 
-__device__ __forceinline__ void mark_patient(unsigned* bits, unsigned q) { atomicOr(&bits[q >> 5], 1u << (q & 31)); }
 
 // Does the wave's cached first tile hold a patient marked in bits?
 __device__ __forceinline__ bool first_tile_stale(const Pf& p, const unsigned* bits, int p0) {
@@ -1525,7 +1625,9 @@ __device__ __forceinline__ void ccd_body(const KArgs& a) {
         int m = gc1 - j0;
         double ytx_cur = lane < m ? a.ytx[j0 + lane] : 0.0;
         __syncthreads();
-        const bool stamp = b == 0 && lane == 0;
+        // (the stamp is a store that the next barrier waits for: taken
+        // only on request)
+        const bool stamp = a.stamp && b == 0 && lane == 0;
         if (stamp) a.group_ticks[NG] = wall_clock64();
         for (int g = 0; g < NG; ++g) {
           const bool has_next = g + 1 < NG;

@@ -31,7 +31,7 @@ EXPORTS = ("sccs_default_options", "sccs_query_workspace", "sccs_create", "sccs_
            "sccs_batch_query_workspace", "sccs_batch_create", "sccs_batch_run", "sccs_batch_get",
            "sccs_batch_heldout", "sccs_batch_last_kernel_ms", "sccs_batch_destroy", "sccs_batch_last_error", "sccs_tune",
            "sccs_sweep_static", "sccs_bootstrap_query_workspace", "sccs_bootstrap",
-           "sccs_cv_query_workspace", "sccs_cv_search", "sccs_set_prior_grouped", "sccs_group_times",
+           "sccs_cv_query_workspace", "sccs_cv_search", "sccs_set_prior_grouped", "sccs_group_timing", "sccs_group_times",
            "sccs_batch_tune", "sccs_column_order", "sccs_get_column_order")
 
 
@@ -159,6 +159,7 @@ def lib() -> ctypes.CDLL:
         L.sccs_last_kernel_ms.argtypes = [H, dp]
         ip = ctypes.POINTER(ctypes.c_int32)
         L.sccs_pass_stats.argtypes = [H, ip, ip, ip]
+        L.sccs_group_timing.argtypes = [H, ctypes.c_int32]
         L.sccs_group_times.argtypes = [H, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ip]
         L.sccs_last_error.argtypes = [H]
         L.sccs_last_error.restype = ctypes.c_char_p
@@ -381,9 +382,14 @@ class Handle:
         self._check(lib().sccs_get_column_order(self.h, out.ctypes.data))
         return out
 
+    def group_timing(self, on: bool = True) -> None:
+        """Stamp each column group in later sweep launches (read with group_times)."""
+        self._check(lib().sccs_group_timing(self.h, 1 if on else 0))
+
     def group_times(self):
         """(microseconds from the last sweep's start to each column group's
-        step, first sweep position of each group) of the last one-pass launch."""
+        step, first sweep position of each group) of the last one-pass launch
+        made with group_timing on."""
         n = ctypes.c_int32()
         cap = self.J
         t = np.zeros(cap)

@@ -110,6 +110,7 @@ def test_null_arguments_rejected():
     assert L.sccs_destroy(None) == sccs.OK
     assert L.sccs_set_prior(None, 1, 1.0) == sccs.ERR_INVALID_ARG
     assert L.sccs_sweep(None, 1, None) == sccs.ERR_INVALID_ARG
+    assert L.sccs_group_timing(None, 1) == sccs.ERR_INVALID_ARG
 
 
 def _batch_query(probs, specs, **opt):

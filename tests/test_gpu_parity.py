@@ -481,20 +481,35 @@ def test_autotuner_picks_a_candidate_and_its_schedule_is_exact(sccs):
 
 
 def test_group_times_cover_the_sweep(sccs):
-    """sccs_group_times after a one-pass launch: one stamp per column group,
-    non-decreasing, inside the kernel's own time; refused after a merged-pass
-    launch and for valued problems."""
+    """sccs_group_times after a one-pass launch with timing on: one stamp per
+    column group, non-decreasing, inside the kernel's own time; refused
+    without timing, after a merged-pass launch and for valued problems; the
+    stamps leave the trajectory unchanged."""
     prob = zipf_small()
     with sccs.Handle(prob, n_workgroups=64, merge_passes=0) as h:
         h.set_prior(sccs.PRIOR_LAPLACE, 2.0)
+        h.sweep(1)
+        with pytest.raises(sccs.SccsError):
+            h.group_times()     # timing is off by default
+        h.group_timing(True)
         h.sweep(2)
         t, fc = h.group_times()
         ms = h.last_kernel_ms()
+        b_stamped = h.get_beta()[0]
+        h.group_timing(False)
+        h.sweep(1)
+        with pytest.raises(sccs.SccsError):
+            h.group_times()
+    with sccs.Handle(prob, n_workgroups=64, merge_passes=0) as h:
+        h.set_prior(sccs.PRIOR_LAPLACE, 2.0)
+        h.sweep(3)
+        assert np.array_equal(h.get_beta()[0], b_stamped)
     assert fc[0] == 0 and fc[-1] == prob.n_cols and np.all(np.diff(fc) >= 1)
     assert len(t) == len(fc) - 1 and np.all(t > 0) and np.all(np.diff(t) >= 0)
     assert t[-1] * 1e-3 <= ms
     with sccs.Handle(prob) as h:
         h.set_prior(sccs.PRIOR_LAPLACE, 2.0)
+        h.group_timing(True)
         h.sweep(1)          # first launch: one pass per group
         h.group_times()
         h.sweep(30)
