@@ -7,7 +7,6 @@ GPU, recomputed den in the oracle), so trajectories must agree far inside
 the 1e-6 relative tolerance on beta; the tests use 1e-9 on small problems.
 The mixed-precision form is held to the 1e-6 relative bar on beta.
 """
-import math
 
 import numpy as np
 import pytest
