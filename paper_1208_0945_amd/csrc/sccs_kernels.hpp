@@ -1441,17 +1441,17 @@ __device__ __forceinline__ void ccd_body(const KArgs& a) {
           for (int i = 0; i < 2 * kPassCols; ++i) tot[i] = 0.0;
           bool okr;
           switch (cls) {   // one width per slot class, fixed at compile time
-            case 0: okr = allreduce2_lanes<2>(s1, s2, sq, a.G, a.ctrl, part, tot, b); break;
+            case 0: okr = allreduce2_wave<2>(s1, s2, sq, a.G, a.ctrl, part, tot, b); break;
 #if SCCS_MAX_GROUP >= 2
-            case 1: okr = allreduce2_lanes<4>(s1, s2, sq, a.G, a.ctrl, part, tot, b); break;
+            case 1: okr = allreduce2_wave<4>(s1, s2, sq, a.G, a.ctrl, part, tot, b); break;
 #endif
 #if SCCS_MAX_GROUP >= 3
-            case 2: okr = allreduce2_lanes<6>(s1, s2, sq, a.G, a.ctrl, part, tot, b); break;
+            case 2: okr = allreduce2_wave<6>(s1, s2, sq, a.G, a.ctrl, part, tot, b); break;
 #endif
 #if SCCS_MAX_GROUP >= 4
-            case 3: okr = allreduce2_lanes<8>(s1, s2, sq, a.G, a.ctrl, part, tot, b); break;
+            case 3: okr = allreduce2_wave<8>(s1, s2, sq, a.G, a.ctrl, part, tot, b); break;
 #endif
-            default: okr = allreduce2_lanes<2 * kPassCols>(s1, s2, sq, a.G, a.ctrl, part, tot, b); break;
+            default: okr = allreduce2_wave<2 * kPassCols>(s1, s2, sq, a.G, a.ctrl, part, tot, b); break;
           }
 
           double Gc = 0.0, Hc = 0.0;

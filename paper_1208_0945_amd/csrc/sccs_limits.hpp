@@ -21,7 +21,7 @@ static_assert(kMaxGroup >= 1 && kMaxGroup <= 4, "column-in-group index is 2 bits
 #define SCCS_PASS_GROUPS 3
 #endif
 #ifndef SCCS_PASS_COLS
-#define SCCS_PASS_COLS 5
+#define SCCS_PASS_COLS 4
 #endif
 constexpr int kPassGroups = SCCS_PASS_GROUPS;
 constexpr int kPassCols = SCCS_PASS_COLS;
