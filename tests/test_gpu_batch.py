@@ -45,6 +45,28 @@ def outcomes(n_fits, n_cols=60, lo=2000, hi=30000, seed=0):
     return synth.batched_outcomes(n_fits, n_cols=n_cols, seed=seed, sizes=sizes)
 
 
+@pytest.mark.parametrize("n_workgroups", [0, 24])
+def test_outcomes_uneven_sizes_relabelled(sccs, n_workgroups):
+    """Partitioned engine, drugs renumbered for independence, 24 outcomes
+    whose patient counts span two orders of magnitude (so the launch shapes
+    give the large fits more workgroups; on 24 workgroups at most three fits
+    share a launch): every fit against the oracle on its renumbered
+    problem."""
+    probs = outcomes(24, n_cols=48, lo=600, hi=60000, seed=3)
+    with sccs.Batch(probs, [sccs.FitSpec(f, [(sccs.PRIOR_LAPLACE, 2.0)]) for f in range(len(probs))],
+                    n_workgroups=n_workgroups, engine=0, column_order=1) as b:
+        b.run(sccs.CRIT_FIXED, max_sweeps=5)
+        for f, p in enumerate(probs):
+            beta, res = b.get(f, 0)
+            order = oracle.independent_order(p, 4)
+            ref = oracle.ccd(synth.permute_columns(p, order), oracle.PRIOR_LAPLACE, 2.0, 5)
+            want = np.empty_like(ref["beta"])
+            want[order] = ref["beta"]
+            assert res["sweeps"] == 5
+            assert rel_inf(beta, want) <= FP64_TOL, f
+            assert abs(res["logpost"] - ref["logpost"]) <= 1e-10 * abs(ref["logpost"])
+
+
 @pytest.mark.parametrize("n_fits,n_workgroups", [(1, 0), (5, 0), (20, 0), (5, 7)])
 def test_outcomes_fixed_sweeps_match_oracle(sccs, engine, n_fits, n_workgroups):
     probs = outcomes(n_fits)
