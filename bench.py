@@ -380,6 +380,89 @@ def paper_fit_bench(sccs, synth, max_sweeps=1000, column_order=1):
     return out
 
 
+def valued_bench(sccs, synth, steps):
+    """Non-binary and dense covariates (values x_kj on the stored entries):
+    2M patients, 1 + Poisson(6) eras, 200 binary Zipf drugs, 20 sparse dose
+    columns (lognormal doses), 2 dense columns on every era (age-like and
+    seasonal); Normal prior variance 1 (every coordinate moves); FP64 and
+    mixed, `steps` sweeps from beta = 0 after one warm-up sweep.  Algorithmic
+    bytes per coordinate: phase A 20 c_j + 16 p_j (row index, value and w
+    per nonzero), phase B 36 c_j + 8 p_j (the binary form's bytes plus the
+    value)."""
+    t0 = time.perf_counter()
+    prob = synth.valued(n_patients=2_000_000, n_drugs=200, n_dose=20, n_dense=2)
+    print(f"[bench] generated {prob.summary()} in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    c, p = column_stats(prob)
+    out = {"metric": "non-binary and dense covariates: sweeps/s, FP64 and mixed", "unit": "sweeps/s",
+           "config": {"workload": "2M patients, 200 drugs + 20 dose + 2 dense columns, Normal var 1",
+                      "n_patients": prob.n_patients, "n_eras": prob.n_rows, "nnz": prob.nnz}}
+    betas = {}
+    for prec, name in ((0, "fp64"), (1, "mixed")):
+        with sccs.Handle(prob, precision=prec) as h:
+            h.set_prior(sccs.PRIOR_NORMAL, 1.0)
+            h.sweep(1)
+            h.set_beta(np.zeros(prob.n_cols))
+            t0 = time.perf_counter()
+            h.sweep(steps)
+            wall = time.perf_counter() - t0
+            ms = h.last_kernel_ms() / steps
+            wb = 8 if prec == 0 else 4
+            algo = float((12 + wb) * c.sum() + 16 * p.sum() + (28 + wb) * c.sum() + 8 * p.sum())
+            out[name] = {"sweeps_per_s": steps / wall, "kernel_ms_per_sweep": ms, "algo_bytes_per_sweep": algo,
+                         "achieved_GBs": algo / (ms * 1e-3) / 1e9,
+                         "frac_of_8TBs": algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            betas[name] = h.get_beta()[0]
+        print(f"[bench] {name}: {out[name]}", file=sys.stderr, flush=True)
+    out["mixed_vs_fp64_gpu_rel_err"] = float(np.max(np.abs(betas["mixed"] - betas["fp64"])) /
+                                            np.max(np.abs(betas["fp64"])))
+    out["value"] = out["fp64"]["sweeps_per_s"]
+    out["dtype"] = "f64"
+    return out
+
+
+def bootstrap_bench(sccs, synth, n_reps=200, n_patients=200_000):
+    """The bootstrap procedure of Section 2.5 at the paper's replicate count:
+    200 replicates of a mid-like problem of 200k patients (J = 2000), each
+    resampling the patients with replacement, Laplace prior lambda = 1, each
+    replicate fitted to a relative change of the log posterior below 1e-8
+    (at most 50 sweeps); percentile intervals and the share of nonzero
+    estimates."""
+    prob = synth.mid(n_patients=n_patients)
+    W = synth.bootstrap_weights(prob.n_patients, n_reps, seed=0)
+    t0 = time.perf_counter()
+    r = sccs.bootstrap(prob, sccs.PRIOR_LAPLACE, 2.0, W, criterion=sccs.CRIT_REL_LOGPOST, max_sweeps=50,
+                       tol=1e-8, column_order=1)
+    wall = time.perf_counter() - t0
+    fit_sweeps = int(np.sum(r["sweeps"]))
+    return {"metric": "bootstrap, 200 replicates: wall seconds (lower is better)", "unit": "s",
+            "higher_is_better": False, "value": wall,
+            "config": {"workload": f"mid-like, {prob.n_patients} patients, J={prob.n_cols}, {n_reps} replicates, "
+                                   "Laplace lambda 1, rel. logpost 1e-8, <= 50 sweeps",
+                       "nnz": prob.nnz},
+            "fit_sweeps": fit_sweeps, "fit_sweeps_per_s": fit_sweeps / wall,
+            "converged": int(np.sum(r["converged"])),
+            "nonzero_share_median": float(np.median(r["p_nonzero"])), "dtype": "f64"}
+
+
+def search_bench(sccs, synth, n_patients=2_000_000, n_folds=10):
+    """The prior-variance search of Section 2.5 on the mid problem: 10
+    patient folds, bracketing upward from variance 0.01 by factors of 10,
+    then golden-section steps on log10(variance) to a width of 0.05, each
+    evaluation a warm-started fit of every fold to a relative change of the
+    log posterior below 1e-10 and the held-out log-likelihood."""
+    prob = synth.mid(n_patients=n_patients)
+    folds = synth.cv_folds(prob.n_patients, n_folds)
+    t0 = time.perf_counter()
+    r = sccs.cv_search(prob, folds, n_folds, sccs.PRIOR_LAPLACE, column_order=1)
+    wall = time.perf_counter() - t0
+    return {"metric": "cross-validated prior-variance search: wall seconds (lower is better)", "unit": "s",
+            "higher_is_better": False, "value": wall,
+            "config": {"workload": f"mid, {prob.n_patients} patients, {n_folds} folds, Laplace, bracket x10 "
+                                   "from 0.01, golden section to 0.05 in log10"},
+            "evaluations": len(r["variance"]), "best_variance": float(r["variance"][r["best"]]),
+            "bracketed": bool(r["bracketed"]), "dtype": "f64"}
+
+
 def coord_curve(sccs, synth, workload, n_workgroups, sweeps_at=(1, 2, 10), c_star=240_000, column_order=1):
     """Achieved bandwidth per coordinate against its column size (one-pass
     form, FP64, from beta = 0 under the workload's prior).  For each listed
@@ -461,7 +544,8 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=12)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=["mid", "outcomes", "cv", "full", "paper"], default="mid")
+    ap.add_argument("--workload", choices=["mid", "outcomes", "cv", "full", "paper", "valued", "bootstrap", "search"],
+                    default="mid")
     ap.add_argument("--tune", action="store_true", help="run the autotuner on the mid workload and print its table")
     ap.add_argument("--mixed-only", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -514,6 +598,15 @@ def main():
     if args.coord_curve:
         print(json.dumps(coord_curve(sccs, synth, args.workload, args.workgroups if args.workload == "mid" else 0,
                                      column_order=args.column_order)), flush=True)
+        return
+    if args.workload == "valued":
+        print(json.dumps(valued_bench(sccs, synth, args.steps)), flush=True)
+        return
+    if args.workload == "bootstrap":
+        print(json.dumps(bootstrap_bench(sccs, synth)), flush=True)
+        return
+    if args.workload == "search":
+        print(json.dumps(search_bench(sccs, synth)), flush=True)
         return
     if args.workload == "paper":
         print(json.dumps(paper_fit_bench(sccs, synth, column_order=args.column_order)), flush=True)
