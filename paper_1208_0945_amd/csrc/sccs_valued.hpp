@@ -149,6 +149,108 @@ __device__ __forceinline__ void tile_b_val(const KArgs& a, int t, const double* 
   }
 }
 
+// Tiles t, t + stride, ... < t1 in order, software-pipelined as the binary
+// sweep's tile loops: the next tile's pairs and values and the bounds of
+// the tile after it are loaded while this tile's gathers are in flight, and
+// the patient words are gathered together with w.  The arithmetic and its
+// order are those of tile_a_val and tile_b_val.
+__device__ __forceinline__ double tile_value(const KArgs& a, int e0, int len) {
+  const int lane = threadIdx.x & 63;
+  return len <= 64 && lane < len ? a.val[e0 + lane] : 0.0;
+}
+
+template <typename WT, int NC>
+__device__ __forceinline__ void tiles_a_val(const KArgs& a, int t, int t1, int stride, AccV<NC>& acc) {
+  if (t >= t1) return;
+  const int lane = threadIdx.x & 63;
+  const WT* __restrict__ w = (const WT*)a.w;
+  int e0, len, en, lenn;
+  tile_bounds(a, t, t1, e0, len);
+  tile_bounds(a, t + stride, t1, en, lenn);
+  uint2 rp = tile_pair(a, e0, len);
+  double x = tile_value(a, e0, len);
+  while (true) {
+    uint2 rpn;
+    double xn;
+    int enn, lennn;
+    if (len <= 64) {
+      bool lead;
+      int seg_start;
+      seg_layout(rp.y, lane, len, lead, seg_start);
+      const bool act = lane < len;
+      const double wv = act ? (double)w[rp.x] : 0.0;
+      const double2 pv = lead ? a.pat[pid_of(rp.y)] : make_double2(1.0, 0.0);
+      rpn = tile_pair(a, en, lenn);
+      xn = tile_value(a, en, lenn);
+      tile_bounds(a, t + 2 * stride, t1, enn, lennn);
+      const double wx = act ? wv * x : 0.0;
+      const double s1 = seg_sum_v(wx, lane, seg_start);
+      const double s2 = seg_sum_v(wx * x, lane, seg_start);
+      if (lead) acc.add(col_of(rp.y), s1, s2, pv);
+    } else {
+      rpn = tile_pair(a, en, lenn);
+      xn = tile_value(a, en, lenn);
+      tile_bounds(a, t + 2 * stride, t1, enn, lennn);
+      tile_a_val<WT, NC>(a, t, acc);
+    }
+    t += stride;
+    if (t >= t1) break;
+    rp = rpn;
+    x = xn;
+    e0 = en;
+    len = lenn;
+    en = enn;
+    lenn = lennn;
+  }
+}
+
+template <typename WT>
+__device__ __forceinline__ void tiles_b_val(const KArgs& a, int t, int t1, int stride, const double* s_d) {
+  if (t >= t1) return;
+  const int lane = threadIdx.x & 63;
+  WT* __restrict__ w = (WT*)a.w;
+  int e0, len, en, lenn;
+  tile_bounds(a, t, t1, e0, len);
+  tile_bounds(a, t + stride, t1, en, lenn);
+  uint2 rp = tile_pair(a, e0, len);
+  double x = tile_value(a, e0, len);
+  while (true) {
+    uint2 rpn;
+    double xn;
+    int enn, lennn;
+    if (len <= 64) {
+      const bool act = lane < len;
+      const double d = act ? s_d[col_of(rp.y)] : 0.0;
+      const bool upd = act && d != 0.0;
+      bool lead;
+      int seg_start;
+      seg_layout(rp.y, lane, len, lead, seg_start);
+      const WT wo = upd ? w[rp.x] : (WT)0;
+      const double den = lead && upd ? a.pat[pid_of(rp.y)].x : 0.0;
+      rpn = tile_pair(a, en, lenn);
+      xn = tile_value(a, en, lenn);
+      tile_bounds(a, t + 2 * stride, t1, enn, lennn);
+      double delta = 0.0;
+      if (upd) w[rp.x] = val_update<WT>(wo, d, x, delta);
+      const double sd = seg_sum_v(delta, lane, seg_start);
+      if (lead && upd) a.pat[pid_of(rp.y)].x = den + sd;
+    } else {
+      rpn = tile_pair(a, en, lenn);
+      xn = tile_value(a, en, lenn);
+      tile_bounds(a, t + 2 * stride, t1, enn, lennn);
+      tile_b_val<WT>(a, t, s_d);
+    }
+    t += stride;
+    if (t >= t1) break;
+    rp = rpn;
+    x = xn;
+    e0 = en;
+    len = lenn;
+    en = enn;
+    lenn = lennn;
+  }
+}
+
 // Workgroup sum of a group's 3m words to the poller wave, the device-wide
 // reduction on the group's slot class (m - 1), and the Newton /
 // trust-region step of each column (Eq. 4 with the prior; lane c for column
@@ -268,7 +370,7 @@ __global__ void __launch_bounds__(kBlock) k_ccd_val(KArgs a) {
       const int t0 = ld_idx(a.own + (size_t)g * (a.G + 1) + b), t1 = ld_idx(a.own + (size_t)g * (a.G + 1) + b + 1);
       AccV<kMaxGroup> acc;
       acc.zero();
-      for (int t = t0 + wave; t < t1; t += kWaves) tile_a_val<WT, kMaxGroup>(a, t, acc);
+      tiles_a_val<WT, kMaxGroup>(a, t0 + wave, t1, kWaves, acc);
       const int cls = m - 1;
       uint32_t sq = gseq[0];
 #pragma unroll
@@ -290,7 +392,7 @@ __global__ void __launch_bounds__(kBlock) k_ccd_val(KArgs a) {
       if (!bci[0]) { ok = false; break; }
       if (bci[1]) { status = SCCS_ERR_NUMERIC; ok = false; break; }
       if (bci[2])
-        for (int t = t0 + wave; t < t1; t += kWaves) tile_b_val<WT>(a, t, s_d);
+        tiles_b_val<WT>(a, t0 + wave, t1, kWaves, s_d);
       // the next group may share patients with this one
       __syncthreads();
     }
@@ -355,7 +457,7 @@ __global__ void __launch_bounds__(kBlock) k_diag_val(KArgs a) {
   AccV<kMaxGroup> acc;
   acc.zero();
   const int t0 = a.own[(size_t)a.diag_g * (a.G + 1) + b], t1 = a.own[(size_t)a.diag_g * (a.G + 1) + b + 1];
-  for (int t = t0 + (tid >> 6); t < t1; t += kWaves) tile_a_val<WT, kMaxGroup>(a, t, acc);
+  tiles_a_val<WT, kMaxGroup>(a, t0 + (tid >> 6), t1, kWaves, acc);
   double loc[kValWords] = {0.0, 0.0, 0.0}, part[kValWords];
 #pragma unroll
   for (int i = 0; i < kMaxGroup; ++i)
